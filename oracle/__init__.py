@@ -1,0 +1,226 @@
+"""FP64 CPU oracle of the cased-well time step (arXiv 2302.13907).
+
+TEST INFRASTRUCTURE ONLY.  The tests, the smoke check and the benchmark's CPU
+baseline leg may import this package; the product package never does.  The
+arithmetic lives in ``cwell_oracle.c`` (plain C loops, FP64, no fused
+multiply-add contraction); this module compiles it with gcc and wraps it with
+ctypes.  It shares no code with the HIP path.
+
+Parity status of every function is listed in ``ORACLE_PINS`` below, together
+with the test that pins it.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "cwell_oracle.c")
+_LIB = os.path.join(_HERE, "libcwell_oracle.so")
+
+FIELDS = ("vr", "vt", "vz", "srr", "stt", "szz", "srt", "srz", "stz")
+SRC_KINDS = {"volume": 0, "force_r": 1, "force_z": 2, "torsion": 3}
+REC_KINDS = {"pressure": 0, "field": 1}
+
+# Which check pins which part of the oracle (test file :: test name).
+ORACLE_PINS = {
+    "velocity/strain operators vs the matrices A, B, C, D of Eq. (1)":
+        "tests/test_oracle_pins.py::test_operators_match_paper_matrices",
+    "discrete skew-adjointness (stencil indices, weights, axis and edge closure)":
+        "tests/test_oracle_pins.py::test_operators_skew_adjoint",
+    "leapfrog ordering + material averaging: energy conservation":
+        "tests/test_oracle_pins.py::test_energy_conserved",
+    "theta stencils and periodic wrap: axisymmetric invariance":
+        "tests/test_oracle_pins.py::test_theta_invariance_bitwise",
+    "P-SV / SH decoupling of axisymmetric sources":
+        "tests/test_oracle_pins.py::test_decoupling",
+    "source/receiver normalisation and timing: reciprocity":
+        "tests/test_oracle_pins.py::test_reciprocity",
+    "point source in a homogeneous fluid: closed form, 2nd order":
+        "tests/test_oracle_pins.py::test_point_source_closed_form",
+    "fluid-solid coupling: low-frequency tube-wave speed":
+        "tests/test_oracle_physics.py::test_tube_wave_speed",
+    "shear stencils, zero shear at fluid contacts: torsional casing wave":
+        "tests/test_oracle_physics.py::test_torsion_wave_in_casing",
+    "absorbing layer: reflection bound":
+        "tests/test_oracle_physics.py::test_pml_reflection_bound",
+    "Courant limit: stability margin by power iteration":
+        "tests/test_oracle_pins.py::test_cfl_margin",
+    "Ricker pulse of Sec. 2: zeros, extrema, zero mean, spectral peak":
+        "tests/test_oracle_pins.py::test_ricker_properties",
+}
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle shared library with gcc (FP64, no contraction)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        cmd = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-fopenmp",
+               "-ffp-contract=off", "-fno-fast-math", _SRC, "-o", tmp, "-lm"]
+        subprocess.check_call(cmd)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        build()
+        lib = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        D = ctypes.POINTER(ctypes.c_double)
+        I = ctypes.c_int
+        L = ctypes.c_long
+        lib.orc_create.restype = P
+        lib.orc_create.argtypes = [I, I, I, ctypes.c_double, ctypes.c_double]
+        lib.orc_free.argtypes = [P]
+        lib.orc_set_material.argtypes = [P, D, D, D]
+        lib.orc_cfl_dt.restype = ctypes.c_double
+        lib.orc_cfl_dt.argtypes = [P]
+        lib.orc_vpmax.restype = ctypes.c_double
+        lib.orc_vpmax.argtypes = [P]
+        lib.orc_ricker.restype = ctypes.c_double
+        lib.orc_ricker.argtypes = [ctypes.c_double, ctypes.c_double]
+        lib.orc_set_pml.argtypes = [P, I, I, ctypes.c_double, ctypes.c_double]
+        lib.orc_set_dt.argtypes = [P, ctypes.c_double]
+        lib.orc_add_source.argtypes = [P, I, I, I, I, D, L]
+        lib.orc_add_receiver.argtypes = [P, I, I, I, I, I]
+        lib.orc_run.argtypes = [P, L, D, D]
+        lib.orc_get_field.argtypes = [P, I, D]
+        lib.orc_set_field.argtypes = [P, I, D]
+        lib.orc_get_coef.argtypes = [P, I, D]
+        lib.orc_steps_done.restype = L
+        lib.orc_steps_done.argtypes = [P]
+        lib.orc_get_dt.restype = ctypes.c_double
+        lib.orc_get_dt.argtypes = [P]
+        lib.orc_apply_div.argtypes = [P, ctypes.POINTER(D), ctypes.POINTER(D)]
+        lib.orc_apply_strain.argtypes = [P, ctypes.POINTER(D), ctypes.POINTER(D)]
+        _lib = lib
+    return _lib
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def ricker(f0: float, t) -> np.ndarray:
+    """Ricker pulse of Sec. 2 (delay 2/f0) sampled at times t, via the C oracle."""
+    lib = _load()
+    t = np.atleast_1d(np.asarray(t, dtype=np.float64))
+    return np.array([lib.orc_ricker(float(f0), float(x)) for x in t])
+
+
+class OracleSim:
+    """One FP64 simulation.  Arrays are C-order [nr][ntheta][nz] float64."""
+
+    def __init__(self, nr: int, ntheta: int, nz: int, dr: float, dz: float):
+        self.lib = _load()
+        self.shape = (nr, ntheta, nz)
+        self.dr, self.dz = float(dr), float(dz)
+        self.h = self.lib.orc_create(nr, ntheta, nz, self.dr, self.dz)
+        if not self.h:
+            raise ValueError("bad grid")
+        self.nrec = 0
+        self._keep = []
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h:
+            self.lib.orc_free(h)
+            self.h = None
+
+    def _arr(self, a) -> np.ndarray:
+        a = np.ascontiguousarray(a, dtype=np.float64)
+        if a.shape != self.shape:
+            a = np.ascontiguousarray(np.broadcast_to(a, self.shape), dtype=np.float64)
+        return a
+
+    def set_material(self, rho, lam, mu):
+        r, l, m = self._arr(rho), self._arr(lam), self._arr(mu)
+        rc = self.lib.orc_set_material(self.h, _dp(r), _dp(l), _dp(m))
+        if rc:
+            raise ValueError("material rejected (%d)" % rc)
+
+    def cfl_dt(self) -> float:
+        return self.lib.orc_cfl_dt(self.h)
+
+    def vp_max(self) -> float:
+        return self.lib.orc_vpmax(self.h)
+
+    def set_pml(self, npml_r: int, npml_z: int, rc: float = 1e-3, alpha: float = 0.0):
+        if self.lib.orc_set_pml(self.h, npml_r, npml_z, rc, alpha):
+            raise ValueError("bad layer")
+
+    def set_dt(self, dt: float):
+        if self.lib.orc_set_dt(self.h, dt):
+            raise ValueError("set_dt failed")
+
+    @property
+    def dt(self) -> float:
+        return self.lib.orc_get_dt(self.h)
+
+    def add_source(self, kind: str, i: int, j: int, k: int, w: Sequence[float]):
+        w = np.ascontiguousarray(w, dtype=np.float64)
+        rc = self.lib.orc_add_source(self.h, SRC_KINDS[kind], i, j, k, _dp(w), len(w))
+        if rc:
+            raise ValueError("bad source (%d)" % rc)
+
+    def add_receiver(self, kind: str, i: int, j: int, k: int, field: Optional[str] = None) -> int:
+        fid = FIELDS.index(field) if field else 0
+        rc = self.lib.orc_add_receiver(self.h, REC_KINDS[kind], fid, i, j, k)
+        if rc < 0:
+            raise ValueError("bad receiver (%d)" % rc)
+        self.nrec += 1
+        return rc
+
+    def run(self, nsteps: int, energy: bool = False):
+        """Advance nsteps; returns traces [nrec][nsteps] (and energy [nsteps])."""
+        tr = np.zeros((max(self.nrec, 1), nsteps))
+        en = np.zeros(nsteps) if energy else None
+        self.lib.orc_run(self.h, nsteps, _dp(tr), _dp(en) if en is not None else None)
+        tr = tr[: self.nrec]
+        return (tr, en) if energy else tr
+
+    def field(self, name: str) -> np.ndarray:
+        out = np.empty(self.shape)
+        self.lib.orc_get_field(self.h, FIELDS.index(name), _dp(out))
+        return out
+
+    def set_field(self, name: str, a):
+        a = self._arr(a)
+        self.lib.orc_set_field(self.h, FIELDS.index(name), _dp(a))
+
+    def coef(self, name: str) -> np.ndarray:
+        names = ("b_r", "b_t", "b_z", "mu_rt", "mu_rz", "mu_tz")
+        out = np.empty(self.shape)
+        self.lib.orc_get_coef(self.h, names.index(name), _dp(out))
+        return out
+
+    @property
+    def steps_done(self) -> int:
+        return self.lib.orc_steps_done(self.h)
+
+    def apply_div(self, sig):
+        """Velocity right-hand sides (no density) of stresses sig = (srr, stt, szz, srt, srz, stz)."""
+        sig = [self._arr(a) for a in sig]
+        out = [np.zeros(self.shape) for _ in range(3)]
+        S = (ctypes.POINTER(ctypes.c_double) * 6)(*[_dp(a) for a in sig])
+        O = (ctypes.POINTER(ctypes.c_double) * 3)(*[_dp(a) for a in out])
+        self.lib.orc_apply_div(self.h, S, O)
+        return out
+
+    def apply_strain(self, vel):
+        """Strain rates (e_rr, e_tt, e_zz, g_rt, g_rz, g_tz) of vel = (vr, vt, vz)."""
+        vel = [self._arr(a) for a in vel]
+        out = [np.zeros(self.shape) for _ in range(6)]
+        V = (ctypes.POINTER(ctypes.c_double) * 3)(*[_dp(a) for a in vel])
+        O = (ctypes.POINTER(ctypes.c_double) * 6)(*[_dp(a) for a in out])
+        self.lib.orc_apply_strain(self.h, V, O)
+        return out

@@ -1,0 +1,172 @@
+"""Seeded synthetic inputs for the cased-well workloads.
+
+This module only describes workloads: grid sizes, the layered medium sampled
+at the cell centres, source and receiver positions, seeds.  It holds none of
+the solver's arithmetic (no stencil, no Courant limit, no wavelet); both the
+HIP path and the test oracle take what it produces as plain arrays.
+
+The medium is the cased well of Sec. 5: a fluid-filled hole, a steel casing,
+a cement annulus whose upper edge may be graded (the "degree of hardening of
+the upper edge" the paper studies), and host rock.  The paper's own material
+values are not given in the text; the values below are typical ones.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import List, Optional, Tuple
+
+import numpy as np
+
+# (Vp, Vs, rho) in SI units
+FLUID = (1500.0, 0.0, 1000.0)
+STEEL = (5900.0, 3200.0, 7850.0)
+CEMENT = (3000.0, 1700.0, 1900.0)
+ROCK = (4000.0, 2300.0, 2400.0)
+
+R_HOLE, R_CASING, R_CEMENT = 0.10, 0.11, 0.15
+
+ROCK_SEED = 20230227
+
+
+def moduli(vp: float, vs: float, rho: float) -> Tuple[float, float, float]:
+    """(rho, lambda, mu) from wave speeds: mu = rho Vs^2, lambda = rho Vp^2 - 2 mu."""
+    mu = rho * vs * vs
+    return rho, rho * vp * vp - 2.0 * mu, mu
+
+
+def cased_well(nr: int, nt: int, nz: int, dr: float, dz: float,
+               z_top: float, ramp: float = 0.0,
+               rock_jitter: float = 0.0, seed: int = ROCK_SEED,
+               radii: Tuple[float, float, float] = (R_HOLE, R_CASING, R_CEMENT)):
+    """rho, lambda, mu (float64, [nr][nt][nz]) of the cased well.
+
+    Sampled at the cell centres r_i = (i + 1/2) dr, z_k = k dz (z grows with
+    depth).  Annulus cells with z_k >= z_top hold cement; above it the annulus
+    holds fluid.  With ramp > 0 the cement keeps its density and bulk modulus
+    but its shear modulus grows linearly from 0 at z_top to full at
+    z_top + ramp.  rock_jitter > 0 multiplies lambda and mu of every rock cell
+    by independent factors (1 + eps), eps ~ U[-jitter, jitter], drawn for
+    lambda first, then mu, over the whole grid in C order.
+    """
+    r = (np.arange(nr) + 0.5) * dr
+    z = np.arange(nz) * dz
+    shape = (nr, nt, nz)
+    rho = np.empty(shape)
+    lam = np.empty(shape)
+    mu = np.empty(shape)
+    R = r[:, None, None] + np.zeros(shape)
+    Z = z[None, None, :] + np.zeros(shape)
+    fluid = R < radii[0]
+    steel = (R >= radii[0]) & (R < radii[1])
+    annulus = (R >= radii[1]) & (R < radii[2])
+    rock = R >= radii[2]
+    for mask, mat in ((fluid, FLUID), (steel, STEEL), (rock, ROCK)):
+        ro, la, m = moduli(*mat)
+        rho[mask], lam[mask], mu[mask] = ro, la, m
+    cem = annulus & (Z >= z_top)
+    mud = annulus & (Z < z_top)
+    ro, la, m = moduli(*FLUID)
+    rho[mud], lam[mud], mu[mud] = ro, la, m
+    ro, la, m = moduli(*CEMENT)
+    K = la + 2.0 * m / 3.0
+    if ramp > 0:
+        frac = np.clip((Z - z_top) / ramp, 0.0, 1.0)
+    else:
+        frac = np.ones(shape)
+    mu_c = m * frac
+    rho[cem] = ro
+    mu[cem] = mu_c[cem]
+    lam[cem] = (K - 2.0 * mu_c / 3.0)[cem]
+    if rock_jitter > 0:
+        rng = np.random.default_rng(seed)
+        e_l = rng.uniform(-rock_jitter, rock_jitter, size=shape)
+        e_m = rng.uniform(-rock_jitter, rock_jitter, size=shape)
+        lam[rock] *= 1.0 + e_l[rock]
+        mu[rock] *= 1.0 + e_m[rock]
+    return rho, lam, mu
+
+
+def homogeneous(nr: int, nt: int, nz: int, mat=FLUID):
+    ro, la, m = moduli(*mat)
+    shape = (nr, nt, nz)
+    return np.full(shape, ro), np.full(shape, la), np.full(shape, m)
+
+
+def random_medium(nr: int, nt: int, nz: int, seed: int, fluid_rings: int = 2):
+    """Heterogeneous random medium with a fluid core of `fluid_rings` rings."""
+    rng = np.random.default_rng(seed)
+    shape = (nr, nt, nz)
+    rho = rng.uniform(1000.0, 8000.0, shape)
+    mu = rng.uniform(5e9, 8e10, shape)
+    lam = rng.uniform(1e9, 1e11, shape)
+    mu[:fluid_rings] = 0.0
+    lam[:fluid_rings] = 2.25e9
+    rho[:fluid_rings] = 1000.0
+    return rho, lam, mu
+
+
+def random_fields(shape, seed: int, n: int = 9, scale: float = 1.0) -> List[np.ndarray]:
+    rng = np.random.default_rng(seed)
+    return [scale * rng.standard_normal(shape) for _ in range(n)]
+
+
+@dataclass
+class Workload:
+    """One synthetic workload of the paper's kind (a cased well, an axis source)."""
+    name: str
+    nr: int
+    nt: int
+    nz: int
+    dr: float
+    dz: float
+    steps: int
+    npml: int
+    f0: float
+    src_k: int
+    rec_k: List[int]
+    z_top: float
+    ramp: float = 0.0
+    rock_jitter: float = 0.0
+    cfl_fraction: float = 0.5
+    pml_rc: float = 1e-3
+    extra: dict = field(default_factory=dict)
+
+    @property
+    def cells(self) -> int:
+        return self.nr * self.nt * self.nz
+
+    def medium(self):
+        return cased_well(self.nr, self.nt, self.nz, self.dr, self.dz,
+                          self.z_top, self.ramp, self.rock_jitter)
+
+
+def parity_case() -> Workload:
+    """48 x 32 x 192 cells of 5 mm, 300 steps, 10-cell layer, 20 kHz axis
+    source at z = 0.2 m, 16 axis receivers every 20 mm from z = 0.22 m,
+    sharp cement top at z = 0.5 m, rock moduli jittered by +-2 %."""
+    return Workload("cased-well 48x32x192 (5 mm), 300 steps", 48, 32, 192, 5e-3, 5e-3,
+                    steps=300, npml=10, f0=20e3, src_k=40,
+                    rec_k=[44 + 4 * m for m in range(16)], z_top=0.5,
+                    rock_jitter=0.02)
+
+
+def production_case() -> Workload:
+    """256 x 128 x 8192 cells of 2 mm (268 M cells), 2000 steps, 20-cell
+    layer, 15 kHz axis source at k = 2048, 64 axis receivers every 10 cells
+    below it, cement top at k = 4096 with a 0.3 m shear ramp."""
+    nz = 8192
+    return Workload("cased-well 256x128x8192 (2 mm), 2000 steps", 256, 128, nz, 2e-3, 2e-3,
+                    steps=2000, npml=20, f0=15e3, src_k=2048,
+                    rec_k=[2048 + 10 * (m + 1) for m in range(64)],
+                    z_top=(nz // 2) * 2e-3, ramp=0.3)
+
+
+def scaled_case(nr: int, nt: int, nz: int, steps: int = 50) -> Workload:
+    """The production medium on a smaller grid (same 2 mm cells and layout
+    fractions); used for parity at sizes the oracle finishes quickly."""
+    npml = min(20, max(2, nr // 6), max(2, (nz - 2) // 4))
+    src_k = nz // 4
+    rec = [min(nz - 1, src_k + 10 * (m + 1)) for m in range(8)]
+    return Workload("cased-well %dx%dx%d (2 mm), %d steps" % (nr, nt, nz, steps), nr, nt, nz,
+                    2e-3, 2e-3, steps=steps, npml=npml, f0=15e3, src_k=src_k, rec_k=rec,
+                    z_top=(nz // 2) * 2e-3, ramp=0.3)
