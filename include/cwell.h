@@ -1,0 +1,197 @@
+/*
+ * cwell.h -- C ABI of the MI355X cased-well wave solver.
+ *
+ * The library advances the first-order velocity-stress system of dynamic
+ * elasticity in cylindrical coordinates (r, theta, z) -- Eq. (1) of
+ * Cheverda et al., "Parallel Modeling of the Acoustic Signal Propagation in
+ * a Cased Well" (arXiv 2302.13907), Sec. 2 -- with the explicit staggered-grid
+ * finite-difference scheme of Sec. 3 (material attached to the cell centre),
+ * a perfectly matched absorbing layer in r and z that does not split the
+ * azimuthal terms (Sec. 1, Sec. 6), the four point-source kinds of Sec. 2
+ * and receivers that record seismograms (Sec. 5).  The fluid is the same
+ * medium with zero shear modulus (Sec. 2).
+ *
+ * Grid.  Every field lives on the same nr x ntheta x nz index space, stored
+ * C order [i][j][k] with k (depth z) fastest, float32.  Staggering:
+ *     s_rr, s_tt, s_zz at (r_i, th_j, z_k);      v_r  at (R_i, th_j, z_k)
+ *     v_t  at (r_i, th_j+1/2, z_k);               v_z  at (r_i, th_j, z_k+1/2)
+ *     s_rt at (R_i, th_j+1/2, z_k);               s_rz at (R_i, th_j, z_k+1/2)
+ *     s_tz at (r_i, th_j+1/2, z_k+1/2)
+ * with r_i = (i+1/2) dr, R_i = (i+1) dr, th_j = j * 2 pi / ntheta, z_k = k dz.
+ * theta is periodic.  Values with i or k outside the grid read as zero: no
+ * unknown sits on the axis r = 0, and this closure is exact when the
+ * innermost ring is fluid.
+ *
+ * Time.  Leapfrog: velocities at t_{n+1/2}, stresses at t_n, zero initial
+ * data (Eq. (2)).  Step n: velocity update from sigma^n, force sources with
+ * w[n]; stress update from v^{n+1/2}, stress sources with w[n]; receivers
+ * record sigma^{n+1} (and v^{n+1/2}) into column n of the trace buffer.
+ *
+ * Calling sequence.
+ *   cw_create -> cw_set_material (or cw_set_material_rz) -> [cw_set_pml]
+ *   -> cw_set_dt -> [cw_add_source]* -> [cw_add_receiver]*
+ *   -> [cw_set_trace_capacity] -> cw_workspace_bytes -> cw_bind
+ *   -> { cw_step | cw_get_* | cw_set_field | cw_energy | cw_reset }*
+ *   -> cw_destroy.
+ * Configuration calls after cw_bind return CW_ERR_STATE.
+ *
+ * Ownership.  Host inputs are copied; the caller keeps them.  Outputs go to
+ * caller-owned host buffers.  Device memory is one caller-owned workspace
+ * (for example a torch uint8 tensor) handed over by cw_bind; the library
+ * never allocates or frees device memory and never frees the workspace.
+ * All device work is enqueued on the HIP stream given to cw_bind.
+ *
+ * Errors.  Every call returns a cw_status; no exception crosses the ABI.
+ * cw_last_error() returns a message for the last failing call of the
+ * calling thread.  One cw_sim must not be used by two threads at once.
+ */
+#ifndef CWELL_H
+#define CWELL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t cw_status;
+#define CW_OK 0
+#define CW_ERR_ARG (-1)        /* null pointer, bad enum, bad size */
+#define CW_ERR_RANGE (-2)      /* index or step count out of range */
+#define CW_ERR_MATERIAL (-3)   /* rho <= 0, mu < 0, lambda + 2 mu <= 0, or not finite */
+#define CW_ERR_UNSTABLE (-4)   /* dt above the Courant limit */
+#define CW_ERR_STATE (-5)      /* call out of order */
+#define CW_ERR_NONFINITE (-6)  /* a NaN or Inf was found */
+#define CW_ERR_HIP (-7)        /* a HIP runtime call failed */
+#define CW_ERR_NOMEM (-8)      /* host allocation failed or workspace too small */
+
+typedef struct cw_sim cw_sim;
+
+typedef struct {
+  int32_t nr, ntheta, nz; /* cells in r, theta, z; each >= 1 */
+  double dr, dz;          /* cell sizes in metres, > 0; dtheta = 2 pi / ntheta */
+} cw_grid;
+
+/* field identifiers (cw_get_field, cw_set_field, CW_REC_FIELD) */
+enum { CW_VR = 0, CW_VT, CW_VZ, CW_SRR, CW_STT, CW_SZZ, CW_SRT, CW_SRZ, CW_STZ, CW_NFIELD };
+
+/* source kinds of Sec. 2: volumetric point source (s_rr, s_tt, s_zz),
+   transverse (radial) point force (v_r), longitudinal point force (v_z),
+   torsion source (s_rt, s_tz) */
+enum { CW_SRC_VOLUME = 0, CW_SRC_FORCE_R, CW_SRC_FORCE_Z, CW_SRC_TORSION };
+
+/* receiver kinds: pressure -(s_rr + s_tt + s_zz)/3, or one field */
+enum { CW_REC_PRESSURE = 0, CW_REC_FIELD };
+
+/* Create a simulation for grid *g.  *out receives the handle. */
+cw_status cw_create(const cw_grid *g, cw_sim **out);
+
+/* Medium at the cell centres (Sec. 3), host float64 arrays in C order
+   [nr][ntheta][nz], SI units (kg/m^3, Pa).  mu = 0 marks fluid (Sec. 2).
+   Staggered nodes use the arithmetic mean of the two adjacent densities
+   and the harmonic mean of the four adjacent shear moduli (zero if any of
+   them is zero); neighbour indices beyond the last cell in r or z are
+   clamped, theta wraps.  Copied.  Errors: CW_ERR_MATERIAL. */
+cw_status cw_set_material(cw_sim *s, const double *rho, const double *lam, const double *mu);
+
+/* Same for an axisymmetric medium: arrays [nr][nz], repeated over theta. */
+cw_status cw_set_material_rz(cw_sim *s, const double *rho, const double *lam, const double *mu);
+
+/* Absorbing layer (Sec. 1, Sec. 6): npml_r cells at the outer radius,
+   npml_z cells at each z end (0 and 0 switch it off: then the zero-value
+   closure is lossless).  Convolutional form with a quadratic damping
+   profile d(x) = d0 x^2, d0 = -3 Vp_max ln(rc) / (2 L), a constant
+   frequency shift alpha (1/s), and the 1/r metric stretched by the
+   integrated radial profile; theta is never stretched.  Requires
+   npml_r < nr, 2 npml_z + 2 <= nz, 0 < rc < 1, alpha >= 0.  Call before
+   cw_set_dt. */
+cw_status cw_set_pml(cw_sim *s, int32_t npml_r, int32_t npml_z, double rc, double alpha);
+
+/* Courant limit: min over cells of 1 / (Vp sqrt(1/dr^2 + 1/(r_i dth)^2 + 1/dz^2)). */
+cw_status cw_cfl_dt(const cw_sim *s, double *dt_cfl);
+
+/* Time step in seconds; CW_ERR_UNSTABLE if above the Courant limit. */
+cw_status cw_set_dt(cw_sim *s, double dt);
+
+/* Add a source of `kind` at cell (i, j, k); j = -1 spreads it over the whole
+   ring i.  w[0..n) are wavelet samples (copied): w[n] enters at step n,
+   with unit strength per unit volume -- the amount added to each target
+   node is dt * w[n] / V (force sources: dt * b * w[n] / V, b the node's
+   buoyancy), V the node volume r dr dth dz (ring: 2 pi r dr dz), r the
+   node's own radius.  Stress sources are best sampled at t_{n+1/2}, force
+   sources at t_n. */
+cw_status cw_add_source(cw_sim *s, int32_t kind, int32_t i, int32_t j, int32_t k,
+                        const double *w, int64_t n);
+
+/* Add a receiver at (i, j, k), j = -1 averaging over ring i.  `field` is
+   used by CW_REC_FIELD only.  *id receives its row in the trace buffer. */
+cw_status cw_add_receiver(cw_sim *s, int32_t kind, int32_t field, int32_t i, int32_t j,
+                          int32_t k, int32_t *id);
+
+/* Steps the trace buffer can hold (float64 [nreceivers][capacity]).
+   Default 0; cw_step fails with CW_ERR_RANGE if receivers exist and the
+   total step count would exceed it. */
+cw_status cw_set_trace_capacity(cw_sim *s, int64_t nsteps);
+
+/* Device bytes the workspace must provide for the current configuration. */
+cw_status cw_workspace_bytes(const cw_sim *s, uint64_t *bytes);
+
+/* Bind a device workspace of at least cw_workspace_bytes bytes (256-byte
+   aligned) and the HIP stream (hipStream_t, 0 = null stream) all work is
+   enqueued on; upload the medium, tables and wavelets; zero the state.
+   Asynchronous with respect to the host. */
+cw_status cw_bind(cw_sim *s, void *workspace, uint64_t bytes, void *stream);
+
+/* Enqueue nsteps time steps.  Asynchronous. */
+cw_status cw_step(cw_sim *s, int64_t nsteps);
+
+/* Wait for all work enqueued by this simulation. */
+cw_status cw_sync(cw_sim *s);
+
+/* Copy the traces recorded so far into out (float64, [nreceivers][cap]
+   row-major, cap >= steps done).  *nsteps_done receives the step count.
+   Synchronous. */
+cw_status cw_get_traces(cw_sim *s, double *out, int64_t cap, int64_t *nsteps_done);
+
+/* Copy one field of the current state to host float32 [nr][ntheta][nz].
+   Synchronous. */
+cw_status cw_get_field(cw_sim *s, int32_t field, float *host_out);
+
+/* Overwrite one field of the current state (initial conditions, restart). */
+cw_status cw_set_field(cw_sim *s, int32_t field, const float *host_in);
+
+/* Energy E^{n+1/2} in float64 after the last step: kinetic energy of
+   v^{n+1/2} plus the strain energy as the product of sigma^{n+1} and
+   sigma^n (zero-shear terms dropped), each node weighted by its radius
+   times dr dth dz.  Constant to rounding when the layer is off and no
+   source fires.  Requires at least one step.  Synchronous. */
+cw_status cw_energy(cw_sim *s, double *E);
+
+/* Zero the state, the layer's memory and the traces; step count to 0. */
+cw_status cw_reset(cw_sim *s);
+
+/* Number of time steps done. */
+cw_status cw_steps_done(const cw_sim *s, int64_t *n);
+
+/* Kernel timing.  With enable = 1, cw_step brackets every launch of the
+   step kernels with HIP events on the simulation's stream (a few
+   microseconds of overhead per launch); enable = 0 stops recording and
+   clears the records.  cw_profile_read waits for the recorded work and
+   returns, for kernel `kernel` (CW_K_*), the summed device time in
+   milliseconds and the number of launches recorded. */
+enum { CW_K_VELOCITY = 0, CW_K_STRESS, CW_K_FUSED, CW_K_INJECT, CW_K_RECORD, CW_K_COUNT };
+cw_status cw_profile(cw_sim *s, int32_t enable);
+cw_status cw_profile_read(cw_sim *s, int32_t kernel, double *total_ms, int64_t *launches);
+
+/* Host helper: Ricker pulse of Sec. 2 with the printed delay 2/f0,
+   out[m] = f(t[m]). */
+cw_status cw_ricker(double f0, const double *t, int64_t n, double *out);
+
+void cw_destroy(cw_sim *s);
+const char *cw_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CWELL_H */

@@ -96,6 +96,8 @@ def _load():
         lib.orc_get_field.argtypes = [P, I, D]
         lib.orc_set_field.argtypes = [P, I, D]
         lib.orc_get_coef.argtypes = [P, I, D]
+        lib.orc_threads.restype = I
+        lib.orc_threads.argtypes = []
         lib.orc_steps_done.restype = L
         lib.orc_steps_done.argtypes = [P]
         lib.orc_get_dt.restype = ctypes.c_double
@@ -104,6 +106,11 @@ def _load():
         lib.orc_apply_strain.argtypes = [P, ctypes.POINTER(D), ctypes.POINTER(D)]
         _lib = lib
     return _lib
+
+
+def threads() -> int:
+    """OpenMP threads the oracle's loops use."""
+    return int(_load().orc_threads())
 
 
 def _dp(a: np.ndarray):

@@ -700,4 +700,11 @@ int orc_get_coef(const orc *s, int q, double *out)
 }
 
 long orc_steps_done(const orc *s) { return s->nstep; }
+
+#ifdef _OPENMP
+#include <omp.h>
+int orc_threads(void) { return omp_get_max_threads(); }
+#else
+int orc_threads(void) { return 1; }
+#endif
 double orc_get_dt(const orc *s) { return s->dt; }

@@ -1,0 +1,687 @@
+// Host side of libcwell: configuration, coefficient tables (float64 on the
+// host, stored float32), workspace layout, and the time loop.
+#include "cwell_internal.hpp"
+#include "../../include/cwell.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+using namespace cw;
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr int kEnergyBlocks = 1024;
+
+thread_local std::string g_err;
+
+cw_status fail(cw_status st, const char *fmt, ...)
+{
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+#define HIPCHK(call)                                                                   \
+  do {                                                                                 \
+    hipError_t e_ = (call);                                                            \
+    if (e_ != hipSuccess) return fail(CW_ERR_HIP, "%s: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+struct SourceSpec {
+  int kind, i, j, k;
+  std::vector<double> w;
+};
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+}  // namespace
+
+struct cw_sim {
+  // grid
+  int nr = 0, nt = 0, nz = 0;
+  double dr = 0, dz = 0, dth = 0;
+  size_t n = 0;
+  // medium (float32 copies, uploaded at bind) and what the setup derives from it
+  std::vector<float> rho, lam, mu;
+  bool have_material = false;
+  double vp_max = 0, dt_cfl = 0;
+  // layer
+  int npr = 0, npz = 0;
+  double rc = 1e-3, alpha = 0;
+  // time step and derived tables
+  double dt = 0;
+  std::vector<float> tab_r, tab_z, inv_rc, inv_rf;
+  // sources / receivers
+  std::vector<SourceSpec> sources;
+  std::vector<Receiver> receivers;
+  int64_t trace_cap = 0;
+  // device state
+  bool bound = false;
+  int device = 0;
+  hipStream_t stream = nullptr;
+  char *ws = nullptr;
+  uint64_t ws_bytes = 0;
+  float *fields[2][NF] = {};
+  float *d_rho = nullptr, *d_lam = nullptr, *d_mu = nullptr;
+  float *d_inv_rc = nullptr, *d_inv_rf = nullptr, *d_tab_r = nullptr, *d_tab_z = nullptr;
+  float *psi_r[NPSI_R] = {};
+  float *psi_z[NPSI_Z] = {};
+  Inject *d_inject = nullptr;
+  int ninject = 0;
+  std::vector<Inject> inject_host;
+  Receiver *d_rec = nullptr;
+  double *d_traces = nullptr;
+  double *d_energy = nullptr;   // kEnergyBlocks partials + 1 result
+  int cur = 0;                  // fields[cur] holds the current state
+  int64_t nstep = 0;
+  // kernel timing: (kernel id, start, stop) per recorded launch
+  bool profiling = false;
+  struct Rec { int kernel; hipEvent_t start, stop; };
+  std::vector<Rec> prof;
+  std::vector<hipEvent_t> event_pool;
+  ~cw_sim()
+  {
+    for (auto &r : prof) { event_pool.push_back(r.start); event_pool.push_back(r.stop); }
+    for (hipEvent_t e : event_pool) (void)hipEventDestroy(e);
+  }
+};
+
+namespace {
+
+int nzs_of(const cw_sim *s) { return s->npz > 0 ? 2 * s->npz + 1 : 0; }
+
+// Number of float32 amplitude samples over all injections.
+size_t amp_floats(const cw_sim *s)
+{
+  size_t t = 0;
+  for (const auto &src : s->sources) {
+    int targets = (src.kind == CW_SRC_VOLUME) ? 3 : (src.kind == CW_SRC_TORSION ? 2 : 1);
+    t += (size_t)targets * src.w.size();
+  }
+  return t;
+}
+
+int inject_count(const cw_sim *s)
+{
+  int t = 0;
+  for (const auto &src : s->sources)
+    t += (src.kind == CW_SRC_VOLUME) ? 3 : (src.kind == CW_SRC_TORSION ? 2 : 1);
+  return t;
+}
+
+struct Layout {
+  size_t fields, material, metric, tabr, tabz, psir, psiz, inject, amp, rec, traces, energy, total;
+};
+
+Layout layout(const cw_sim *s)
+{
+  Layout L{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) { size_t o = off; off += align256(bytes); return o; };
+  L.fields = take(2 * NF * s->n * sizeof(float));
+  L.material = take(3 * s->n * sizeof(float));
+  L.metric = take(2 * (size_t)s->nr * sizeof(float));
+  L.tabr = take(NTAB_R * (size_t)s->nr * sizeof(float));
+  L.tabz = take(NTAB_Z * (size_t)s->nz * sizeof(float));
+  L.psir = take((size_t)NPSI_R * s->npr * s->nt * s->nz * sizeof(float));
+  L.psiz = take((size_t)NPSI_Z * s->nr * s->nt * nzs_of(s) * sizeof(float));
+  L.inject = take((size_t)inject_count(s) * sizeof(Inject));
+  L.amp = take(amp_floats(s) * sizeof(float));
+  L.rec = take(s->receivers.size() * sizeof(Receiver));
+  L.traces = take(s->receivers.size() * (size_t)s->trace_cap * sizeof(double));
+  L.energy = take((kEnergyBlocks + 1) * sizeof(double));
+  L.total = off;
+  return L;
+}
+
+// Courant limit over the cell centres with the azimuthal width r_i dth.
+double courant(const cw_sim *s, const double *rho, const double *lam, const double *mu,
+               bool rz_only)
+{
+  double best = INFINITY;
+  const size_t per_ring = rz_only ? (size_t)s->nz : (size_t)s->nt * s->nz;
+  for (int i = 0; i < s->nr; i++) {
+    const double ra = (i + 0.5) * s->dr * s->dth;
+    const double g = std::sqrt(1.0 / (s->dr * s->dr) + 1.0 / (ra * ra) + 1.0 / (s->dz * s->dz));
+    double vmax = 0;
+    for (size_t c = 0; c < per_ring; c++) {
+      const size_t p = (size_t)i * per_ring + c;
+      vmax = std::max(vmax, std::sqrt((lam[p] + 2.0 * mu[p]) / rho[p]));
+    }
+    best = std::min(best, 1.0 / (vmax * g));
+  }
+  return best;
+}
+
+cw_status check_medium(size_t n, const double *rho, const double *lam, const double *mu)
+{
+  for (size_t p = 0; p < n; p++) {
+    const double r = rho[p], l = lam[p], m = mu[p];
+    if (!std::isfinite(r) || !std::isfinite(l) || !std::isfinite(m) || !(r > 0) || !(m >= 0) ||
+        !(l + 2 * m > 0))
+      return fail(CW_ERR_MATERIAL, "invalid medium at flat index %zu: rho=%g lambda=%g mu=%g", p, r, l, m);
+  }
+  return CW_OK;
+}
+
+// Damping coefficients of the recursive convolution for profile value d.
+void conv_coef(double d, double alpha, double dt, float *a, float *b)
+{
+  const double bb = std::exp(-(d + alpha) * dt);
+  *b = (float)bb;
+  *a = d > 0 ? (float)(d * (bb - 1.0) / (d + alpha)) : 0.0f;
+}
+
+void build_tables(cw_sim *s)
+{
+  s->inv_rc.resize(s->nr);
+  s->inv_rf.resize(s->nr);
+  for (int i = 0; i < s->nr; i++) {
+    s->inv_rc[i] = (float)(1.0 / ((i + 0.5) * s->dr));
+    s->inv_rf[i] = (float)(1.0 / ((i + 1.0) * s->dr));
+  }
+  s->tab_r.assign(NTAB_R * (size_t)s->nr, 0.0f);
+  s->tab_z.assign(NTAB_Z * (size_t)s->nz, 0.0f);
+  const double Lr = s->npr * s->dr, Lz = s->npz * s->dz;
+  const double d0r = s->npr > 0 ? -3.0 * s->vp_max * std::log(s->rc) / (2.0 * Lr) : 0.0;
+  const double d0z = s->npz > 0 ? -3.0 * s->vp_max * std::log(s->rc) / (2.0 * Lz) : 0.0;
+  const double r0 = (s->nr - s->npr) * s->dr;   // inner edge of the radial layer
+  for (int i = 0; i < s->nr; i++) {
+    for (int face = 0; face < 2; face++) {
+      const double r = (i + (face ? 1.0 : 0.5)) * s->dr;
+      const double x = (s->npr > 0 && r > r0) ? (r - r0) / Lr : 0.0;
+      const double d = d0r * x * x;                       // radial profile
+      const double dint = s->npr > 0 ? d0r * Lr * x * x * x / (3.0 * r) : 0.0;  // (1/r) * integral of d
+      float *T = s->tab_r.data();
+      conv_coef(d, s->alpha, s->dt, &T[(face ? AR_F : AR_C) * s->nr + i], &T[(face ? BR_F : BR_C) * s->nr + i]);
+      conv_coef(dint, s->alpha, s->dt, &T[(face ? AT_F : AT_C) * s->nr + i], &T[(face ? BT_F : BT_C) * s->nr + i]);
+    }
+  }
+  for (int k = 0; k < s->nz; k++) {
+    for (int half = 0; half < 2; half++) {
+      const double z = (k + (half ? 0.5 : 0.0)) * s->dz;
+      double x = 0.0;
+      if (s->npz > 0) {
+        x = std::max((s->npz * s->dz - z) / Lz, (z - (s->nz - 1 - s->npz) * s->dz) / Lz);
+        x = std::max(x, 0.0);
+      }
+      float *T = s->tab_z.data();
+      conv_coef(d0z * x * x, s->alpha, s->dt, &T[(half ? AZ_H : AZ_C) * s->nz + k], &T[(half ? BZ_H : BZ_C) * s->nz + k]);
+    }
+  }
+}
+
+bool configurable(cw_sim *s, cw_status *st)
+{
+  if (!s) { *st = fail(CW_ERR_ARG, "null simulation"); return false; }
+  if (s->bound) { *st = fail(CW_ERR_STATE, "configuration after cw_bind"); return false; }
+  return true;
+}
+
+StepArgs step_args(const cw_sim *s, int in, int out)
+{
+  StepArgs a{};
+  a.nr = s->nr; a.nt = s->nt; a.nz = s->nz;
+  a.npr = s->npr; a.npz = s->npz; a.nzs = nzs_of(s);
+  a.dt = (float)s->dt;
+  a.inv_dr = (float)(1.0 / s->dr);
+  a.inv_dz = (float)(1.0 / s->dz);
+  a.inv_dth = (float)(1.0 / s->dth);
+  a.inv_rc = s->d_inv_rc; a.inv_rf = s->d_inv_rf;
+  a.rho = s->d_rho; a.lam = s->d_lam; a.mu = s->d_mu;
+  for (int q = 0; q < NF; q++) { a.in[q] = s->fields[in][q]; a.out[q] = s->fields[out][q]; }
+  for (int q = 0; q < NPSI_R; q++) a.psi_r[q] = s->psi_r[q];
+  for (int q = 0; q < NPSI_Z; q++) a.psi_z[q] = s->psi_z[q];
+  a.tab_r = s->d_tab_r; a.tab_z = s->d_tab_z;
+  return a;
+}
+
+hipError_t take_event(cw_sim *s, hipEvent_t *e)
+{
+  if (!s->event_pool.empty()) {
+    *e = s->event_pool.back();
+    s->event_pool.pop_back();
+    return hipSuccess;
+  }
+  return hipEventCreate(e);
+}
+
+// Launch `fn` on the stream, bracketed by events when profiling.
+template <class F>
+cw_status timed(cw_sim *s, int kernel, F &&fn)
+{
+  if (!s->profiling) {
+    HIPCHK(fn());
+    return CW_OK;
+  }
+  cw_sim::Rec r{kernel, nullptr, nullptr};
+  HIPCHK(take_event(s, &r.start));
+  HIPCHK(take_event(s, &r.stop));
+  HIPCHK(hipEventRecord(r.start, s->stream));
+  HIPCHK(fn());
+  HIPCHK(hipEventRecord(r.stop, s->stream));
+  s->prof.push_back(r);
+  return CW_OK;
+}
+
+cw_status zero_state(cw_sim *s)
+{
+  const Layout L = layout(s);
+  HIPCHK(hipMemsetAsync(s->ws + L.fields, 0, 2 * NF * s->n * sizeof(float), s->stream));
+  const size_t psir = (size_t)NPSI_R * s->npr * s->nt * s->nz * sizeof(float);
+  const size_t psiz = (size_t)NPSI_Z * s->nr * s->nt * nzs_of(s) * sizeof(float);
+  if (psir) HIPCHK(hipMemsetAsync(s->ws + L.psir, 0, psir, s->stream));
+  if (psiz) HIPCHK(hipMemsetAsync(s->ws + L.psiz, 0, psiz, s->stream));
+  const size_t tb = s->receivers.size() * (size_t)s->trace_cap * sizeof(double);
+  if (tb) HIPCHK(hipMemsetAsync(s->ws + L.traces, 0, tb, s->stream));
+  s->cur = 0;
+  s->nstep = 0;
+  return CW_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *cw_last_error(void) { return g_err.c_str(); }
+
+cw_status cw_create(const cw_grid *g, cw_sim **out)
+{
+  if (!g || !out) return fail(CW_ERR_ARG, "null argument");
+  if (g->nr < 1 || g->ntheta < 1 || g->nz < 1)
+    return fail(CW_ERR_ARG, "grid sizes must be >= 1 (got %d %d %d)", g->nr, g->ntheta, g->nz);
+  if (!(g->dr > 0) || !(g->dz > 0) || !std::isfinite(g->dr) || !std::isfinite(g->dz))
+    return fail(CW_ERR_ARG, "cell sizes must be finite and > 0");
+  cw_sim *s = new (std::nothrow) cw_sim();
+  if (!s) return fail(CW_ERR_NOMEM, "out of host memory");
+  s->nr = g->nr; s->nt = g->ntheta; s->nz = g->nz;
+  s->dr = g->dr; s->dz = g->dz; s->dth = 2.0 * kPi / g->ntheta;
+  s->n = (size_t)s->nr * s->nt * s->nz;
+  *out = s;
+  return CW_OK;
+}
+
+void cw_destroy(cw_sim *s) { delete s; }
+
+static cw_status set_medium(cw_sim *s, const double *rho, const double *lam, const double *mu, bool rz)
+{
+  cw_status st;
+  if (!configurable(s, &st)) return st;
+  if (!rho || !lam || !mu) return fail(CW_ERR_ARG, "null medium array");
+  const size_t nin = rz ? (size_t)s->nr * s->nz : s->n;
+  if ((st = check_medium(nin, rho, lam, mu)) != CW_OK) return st;
+  try {
+    s->rho.resize(s->n); s->lam.resize(s->n); s->mu.resize(s->n);
+  } catch (...) {
+    return fail(CW_ERR_NOMEM, "out of host memory for the medium");
+  }
+  double vmax = 0;
+  for (size_t p = 0; p < nin; p++) vmax = std::max(vmax, std::sqrt((lam[p] + 2 * mu[p]) / rho[p]));
+  for (int i = 0; i < s->nr; i++)
+    for (int j = 0; j < s->nt; j++) {
+      const size_t dst = ((size_t)i * s->nt + j) * s->nz;
+      const size_t src = rz ? (size_t)i * s->nz : dst;
+      for (int k = 0; k < s->nz; k++) {
+        s->rho[dst + k] = (float)rho[src + k];
+        s->lam[dst + k] = (float)lam[src + k];
+        s->mu[dst + k] = (float)mu[src + k];
+      }
+    }
+  s->vp_max = vmax;
+  s->dt_cfl = courant(s, rho, lam, mu, rz);
+  s->have_material = true;
+  s->dt = 0;   // the tables depend on the medium: set_dt again
+  return CW_OK;
+}
+
+cw_status cw_set_material(cw_sim *s, const double *rho, const double *lam, const double *mu)
+{
+  return set_medium(s, rho, lam, mu, false);
+}
+
+cw_status cw_set_material_rz(cw_sim *s, const double *rho, const double *lam, const double *mu)
+{
+  return set_medium(s, rho, lam, mu, true);
+}
+
+cw_status cw_set_pml(cw_sim *s, int32_t npml_r, int32_t npml_z, double rc, double alpha)
+{
+  cw_status st;
+  if (!configurable(s, &st)) return st;
+  if (npml_r < 0 || npml_z < 0) return fail(CW_ERR_RANGE, "negative layer width");
+  if (npml_r >= s->nr) return fail(CW_ERR_RANGE, "npml_r=%d must be < nr=%d", npml_r, s->nr);
+  if (npml_z > 0 && 2 * npml_z + 2 > s->nz)
+    return fail(CW_ERR_RANGE, "2*npml_z+2=%d must be <= nz=%d", 2 * npml_z + 2, s->nz);
+  if ((npml_r > 0 || npml_z > 0) && !(rc > 0 && rc < 1 && alpha >= 0 && std::isfinite(alpha)))
+    return fail(CW_ERR_ARG, "need 0 < rc < 1 and alpha >= 0");
+  s->npr = npml_r; s->npz = npml_z; s->rc = rc; s->alpha = alpha;
+  s->dt = 0;
+  return CW_OK;
+}
+
+cw_status cw_cfl_dt(const cw_sim *s, double *dt_cfl)
+{
+  if (!s || !dt_cfl) return fail(CW_ERR_ARG, "null argument");
+  if (!s->have_material) return fail(CW_ERR_STATE, "medium not set");
+  *dt_cfl = s->dt_cfl;
+  return CW_OK;
+}
+
+cw_status cw_set_dt(cw_sim *s, double dt)
+{
+  cw_status st;
+  if (!configurable(s, &st)) return st;
+  if (!s->have_material) return fail(CW_ERR_STATE, "medium not set");
+  if (!(dt > 0) || !std::isfinite(dt)) return fail(CW_ERR_ARG, "dt must be finite and > 0");
+  if (dt > s->dt_cfl * (1.0 + 1e-12))
+    return fail(CW_ERR_UNSTABLE, "dt=%.6g above the Courant limit %.6g", dt, s->dt_cfl);
+  s->dt = dt;
+  build_tables(s);
+  return CW_OK;
+}
+
+cw_status cw_add_source(cw_sim *s, int32_t kind, int32_t i, int32_t j, int32_t k,
+                        const double *w, int64_t n)
+{
+  cw_status st;
+  if (!configurable(s, &st)) return st;
+  if (kind < CW_SRC_VOLUME || kind > CW_SRC_TORSION) return fail(CW_ERR_ARG, "bad source kind %d", kind);
+  if (i < 0 || i >= s->nr || j < -1 || j >= s->nt || k < 0 || k >= s->nz)
+    return fail(CW_ERR_RANGE, "source cell (%d,%d,%d) outside the grid", i, j, k);
+  if (n < 0 || (n > 0 && !w)) return fail(CW_ERR_ARG, "bad wavelet");
+  if (n > INT32_MAX) return fail(CW_ERR_RANGE, "wavelet too long");
+  for (int64_t m = 0; m < n; m++)
+    if (!std::isfinite(w[m])) return fail(CW_ERR_NONFINITE, "wavelet sample %lld not finite", (long long)m);
+  if (!s->have_material) return fail(CW_ERR_STATE, "medium not set");
+  if (!(s->dt > 0)) return fail(CW_ERR_STATE, "dt not set");
+  SourceSpec src;
+  src.kind = kind; src.i = i; src.j = j; src.k = k;
+  src.w.assign(w, w + n);
+  s->sources.push_back(std::move(src));
+  return CW_OK;
+}
+
+cw_status cw_add_receiver(cw_sim *s, int32_t kind, int32_t field, int32_t i, int32_t j, int32_t k,
+                          int32_t *id)
+{
+  cw_status st;
+  if (!configurable(s, &st)) return st;
+  if (kind != CW_REC_PRESSURE && kind != CW_REC_FIELD) return fail(CW_ERR_ARG, "bad receiver kind %d", kind);
+  if (kind == CW_REC_FIELD && (field < 0 || field >= CW_NFIELD)) return fail(CW_ERR_ARG, "bad field %d", field);
+  if (i < 0 || i >= s->nr || j < -1 || j >= s->nt || k < 0 || k >= s->nz)
+    return fail(CW_ERR_RANGE, "receiver cell (%d,%d,%d) outside the grid", i, j, k);
+  Receiver r{kind, kind == CW_REC_FIELD ? field : 0, i, j, k};
+  s->receivers.push_back(r);
+  if (id) *id = (int32_t)s->receivers.size() - 1;
+  return CW_OK;
+}
+
+cw_status cw_set_trace_capacity(cw_sim *s, int64_t nsteps)
+{
+  cw_status st;
+  if (!configurable(s, &st)) return st;
+  if (nsteps < 0) return fail(CW_ERR_RANGE, "negative capacity");
+  s->trace_cap = nsteps;
+  return CW_OK;
+}
+
+cw_status cw_workspace_bytes(const cw_sim *s, uint64_t *bytes)
+{
+  if (!s || !bytes) return fail(CW_ERR_ARG, "null argument");
+  *bytes = layout(s).total;
+  return CW_OK;
+}
+
+cw_status cw_bind(cw_sim *s, void *workspace, uint64_t bytes, void *stream)
+{
+  cw_status st;
+  if (!configurable(s, &st)) return st;
+  if (!s->have_material) return fail(CW_ERR_STATE, "medium not set");
+  if (!(s->dt > 0)) return fail(CW_ERR_STATE, "dt not set");
+  if (!workspace) return fail(CW_ERR_ARG, "null workspace");
+  if (((uintptr_t)workspace & 255) != 0) return fail(CW_ERR_ARG, "workspace not 256-byte aligned");
+  const Layout L = layout(s);
+  if (bytes < L.total)
+    return fail(CW_ERR_NOMEM, "workspace of %llu bytes, need %llu", (unsigned long long)bytes,
+                (unsigned long long)L.total);
+  HIPCHK(hipGetDevice(&s->device));
+  s->stream = (hipStream_t)stream;
+  s->ws = (char *)workspace;
+  s->ws_bytes = bytes;
+  char *w = s->ws;
+  for (int b = 0; b < 2; b++)
+    for (int q = 0; q < NF; q++)
+      s->fields[b][q] = (float *)(w + L.fields) + ((size_t)b * NF + q) * s->n;
+  s->d_rho = (float *)(w + L.material);
+  s->d_lam = s->d_rho + s->n;
+  s->d_mu = s->d_lam + s->n;
+  s->d_inv_rc = (float *)(w + L.metric);
+  s->d_inv_rf = s->d_inv_rc + s->nr;
+  s->d_tab_r = (float *)(w + L.tabr);
+  s->d_tab_z = (float *)(w + L.tabz);
+  const size_t slab_r = (size_t)s->npr * s->nt * s->nz, slab_z = (size_t)s->nr * s->nt * nzs_of(s);
+  for (int q = 0; q < NPSI_R; q++) s->psi_r[q] = slab_r ? (float *)(w + L.psir) + q * slab_r : nullptr;
+  for (int q = 0; q < NPSI_Z; q++) s->psi_z[q] = slab_z ? (float *)(w + L.psiz) + q * slab_z : nullptr;
+  s->d_inject = (Inject *)(w + L.inject);
+  s->d_rec = (Receiver *)(w + L.rec);
+  s->d_traces = (double *)(w + L.traces);
+  s->d_energy = (double *)(w + L.energy);
+
+  // injections: dt * w[n] / V per target node, V the node (or ring) volume
+  std::vector<float> amps(amp_floats(s));
+  s->inject_host.clear();
+  size_t ao = 0;
+  float *d_amp = (float *)(w + L.amp);
+  for (const auto &src : s->sources) {
+    struct T { int field; bool face; };   // face: the node sits at R_i, else at r_i
+    std::vector<T> targets;
+    int phase = 1;
+    switch (src.kind) {
+    case CW_SRC_VOLUME: targets = {{SRR, false}, {STT, false}, {SZZ, false}}; break;
+    case CW_SRC_TORSION: targets = {{SRT, true}, {STZ, false}}; break;
+    case CW_SRC_FORCE_R: targets = {{VR, true}}; phase = 0; break;
+    case CW_SRC_FORCE_Z: targets = {{VZ, false}}; phase = 0; break;
+    }
+    for (const T &t : targets) {
+      const double rad = (src.i + (t.face ? 1.0 : 0.5)) * s->dr;
+      const double vol = src.j < 0 ? 2.0 * kPi * rad * s->dr * s->dz : rad * s->dr * s->dth * s->dz;
+      double scale = 1.0;
+      if (t.field == VR || t.field == VZ) {
+        // buoyancy at the node: 2 / (rho + rho of the next cell in r or z, clamped);
+        // a ring source takes the ring's first cell, the medium being that of the caller
+        const int jj = src.j < 0 ? 0 : src.j;
+        const size_t p = ((size_t)src.i * s->nt + jj) * s->nz + src.k;
+        const int i1 = std::min(src.i + 1, s->nr - 1), k1 = std::min(src.k + 1, s->nz - 1);
+        const size_t p1 = t.field == VR ? ((size_t)i1 * s->nt + jj) * s->nz + src.k
+                                        : ((size_t)src.i * s->nt + jj) * s->nz + k1;
+        scale = 2.0 / ((double)s->rho[p] + (double)s->rho[p1]);
+      }
+      Inject e{};
+      e.field = t.field; e.i = src.i; e.j = src.j; e.k = src.k; e.phase = phase;
+      e.nsamp = (int)src.w.size();
+      e.scale = (float)scale;
+      e.amp = d_amp + ao;
+      for (size_t m = 0; m < src.w.size(); m++) amps[ao + m] = (float)(s->dt * src.w[m] / vol);
+      ao += src.w.size();
+      s->inject_host.push_back(e);
+    }
+  }
+  s->ninject = (int)s->inject_host.size();
+
+  HIPCHK(hipMemcpyAsync(s->d_rho, s->rho.data(), s->n * sizeof(float), hipMemcpyHostToDevice, s->stream));
+  HIPCHK(hipMemcpyAsync(s->d_lam, s->lam.data(), s->n * sizeof(float), hipMemcpyHostToDevice, s->stream));
+  HIPCHK(hipMemcpyAsync(s->d_mu, s->mu.data(), s->n * sizeof(float), hipMemcpyHostToDevice, s->stream));
+  HIPCHK(hipMemcpyAsync(s->d_inv_rc, s->inv_rc.data(), s->nr * sizeof(float), hipMemcpyHostToDevice, s->stream));
+  HIPCHK(hipMemcpyAsync(s->d_inv_rf, s->inv_rf.data(), s->nr * sizeof(float), hipMemcpyHostToDevice, s->stream));
+  HIPCHK(hipMemcpyAsync(s->d_tab_r, s->tab_r.data(), s->tab_r.size() * sizeof(float), hipMemcpyHostToDevice, s->stream));
+  HIPCHK(hipMemcpyAsync(s->d_tab_z, s->tab_z.data(), s->tab_z.size() * sizeof(float), hipMemcpyHostToDevice, s->stream));
+  if (s->ninject) {
+    HIPCHK(hipMemcpyAsync(s->d_inject, s->inject_host.data(), s->ninject * sizeof(Inject), hipMemcpyHostToDevice, s->stream));
+    HIPCHK(hipMemcpyAsync(d_amp, amps.data(), amps.size() * sizeof(float), hipMemcpyHostToDevice, s->stream));
+  }
+  if (!s->receivers.empty())
+    HIPCHK(hipMemcpyAsync(s->d_rec, s->receivers.data(), s->receivers.size() * sizeof(Receiver), hipMemcpyHostToDevice, s->stream));
+  s->bound = true;
+  if ((st = zero_state(s)) != CW_OK) { s->bound = false; return st; }
+  // the host arrays above are pageable: finish the copies before they can go away
+  HIPCHK(hipStreamSynchronize(s->stream));
+  return CW_OK;
+}
+
+cw_status cw_step(cw_sim *s, int64_t nsteps)
+{
+  if (!s) return fail(CW_ERR_ARG, "null simulation");
+  if (!s->bound) return fail(CW_ERR_STATE, "cw_bind first");
+  if (nsteps < 0) return fail(CW_ERR_RANGE, "negative step count");
+  if (!s->receivers.empty() && s->nstep + nsteps > s->trace_cap)
+    return fail(CW_ERR_RANGE, "trace capacity %lld exceeded (%lld + %lld steps)", (long long)s->trace_cap,
+                (long long)s->nstep, (long long)nsteps);
+  HIPCHK(hipSetDevice(s->device));
+  cw_status st;
+  const int nrec = (int)s->receivers.size();
+  for (int64_t t = 0; t < nsteps; t++) {
+    const StepArgs a = step_args(s, s->cur, 1 - s->cur);
+    const int64_t n = s->nstep;
+    if ((st = timed(s, CW_K_VELOCITY, [&] { return launch_velocity_basic(a, s->stream); })) != CW_OK) return st;
+    if (s->ninject && (st = timed(s, CW_K_INJECT, [&] {
+          return launch_inject(s->d_inject, s->ninject, 0, n, a, s->stream); })) != CW_OK) return st;
+    if ((st = timed(s, CW_K_STRESS, [&] { return launch_stress_basic(a, s->stream); })) != CW_OK) return st;
+    if (s->ninject && (st = timed(s, CW_K_INJECT, [&] {
+          return launch_inject(s->d_inject, s->ninject, 1, n, a, s->stream); })) != CW_OK) return st;
+    if (nrec && (st = timed(s, CW_K_RECORD, [&] {
+          return launch_record(s->d_rec, nrec, n, s->trace_cap, a, s->d_traces, s->stream); })) != CW_OK)
+      return st;
+    s->cur = 1 - s->cur;
+    s->nstep++;
+  }
+  return CW_OK;
+}
+
+cw_status cw_sync(cw_sim *s)
+{
+  if (!s) return fail(CW_ERR_ARG, "null simulation");
+  if (!s->bound) return fail(CW_ERR_STATE, "cw_bind first");
+  HIPCHK(hipStreamSynchronize(s->stream));
+  return CW_OK;
+}
+
+cw_status cw_get_traces(cw_sim *s, double *out, int64_t cap, int64_t *nsteps_done)
+{
+  if (!s || (!out && !s->receivers.empty())) return fail(CW_ERR_ARG, "null argument");
+  if (!s->bound) return fail(CW_ERR_STATE, "cw_bind first");
+  if (cap < s->nstep) return fail(CW_ERR_RANGE, "cap %lld < steps done %lld", (long long)cap, (long long)s->nstep);
+  if (nsteps_done) *nsteps_done = s->nstep;
+  if (s->receivers.empty() || s->nstep == 0) return CW_OK;
+  HIPCHK(hipSetDevice(s->device));
+  HIPCHK(hipMemcpy2DAsync(out, cap * sizeof(double), s->d_traces, s->trace_cap * sizeof(double),
+                          s->nstep * sizeof(double), s->receivers.size(), hipMemcpyDeviceToHost, s->stream));
+  HIPCHK(hipStreamSynchronize(s->stream));
+  return CW_OK;
+}
+
+cw_status cw_get_field(cw_sim *s, int32_t field, float *host_out)
+{
+  if (!s || !host_out) return fail(CW_ERR_ARG, "null argument");
+  if (field < 0 || field >= CW_NFIELD) return fail(CW_ERR_ARG, "bad field %d", field);
+  if (!s->bound) return fail(CW_ERR_STATE, "cw_bind first");
+  HIPCHK(hipSetDevice(s->device));
+  HIPCHK(hipMemcpyAsync(host_out, s->fields[s->cur][field], s->n * sizeof(float), hipMemcpyDeviceToHost, s->stream));
+  HIPCHK(hipStreamSynchronize(s->stream));
+  return CW_OK;
+}
+
+cw_status cw_set_field(cw_sim *s, int32_t field, const float *host_in)
+{
+  if (!s || !host_in) return fail(CW_ERR_ARG, "null argument");
+  if (field < 0 || field >= CW_NFIELD) return fail(CW_ERR_ARG, "bad field %d", field);
+  if (!s->bound) return fail(CW_ERR_STATE, "cw_bind first");
+  HIPCHK(hipSetDevice(s->device));
+  HIPCHK(hipMemcpyAsync(s->fields[s->cur][field], host_in, s->n * sizeof(float), hipMemcpyHostToDevice, s->stream));
+  HIPCHK(hipStreamSynchronize(s->stream));
+  return CW_OK;
+}
+
+cw_status cw_energy(cw_sim *s, double *E)
+{
+  if (!s || !E) return fail(CW_ERR_ARG, "null argument");
+  if (!s->bound) return fail(CW_ERR_STATE, "cw_bind first");
+  if (s->nstep < 1) return fail(CW_ERR_STATE, "energy needs at least one step");
+  HIPCHK(hipSetDevice(s->device));
+  const StepArgs a = step_args(s, 1 - s->cur, s->cur);   // in: level n, out: level n+1
+  const double scale = s->dr * s->dr * s->dth * s->dz;  // radii are in units of dr
+  HIPCHK(launch_energy(a, s->d_energy, kEnergyBlocks, scale, s->d_energy + kEnergyBlocks, s->stream));
+  HIPCHK(hipMemcpyAsync(E, s->d_energy + kEnergyBlocks, sizeof(double), hipMemcpyDeviceToHost, s->stream));
+  HIPCHK(hipStreamSynchronize(s->stream));
+  if (!std::isfinite(*E)) return fail(CW_ERR_NONFINITE, "energy is not finite");
+  return CW_OK;
+}
+
+cw_status cw_reset(cw_sim *s)
+{
+  if (!s) return fail(CW_ERR_ARG, "null simulation");
+  if (!s->bound) return fail(CW_ERR_STATE, "cw_bind first");
+  HIPCHK(hipSetDevice(s->device));
+  return zero_state(s);
+}
+
+cw_status cw_profile(cw_sim *s, int32_t enable)
+{
+  if (!s) return fail(CW_ERR_ARG, "null simulation");
+  if (!enable) {
+    if (!s->prof.empty() && s->bound) HIPCHK(hipStreamSynchronize(s->stream));
+    for (auto &r : s->prof) { s->event_pool.push_back(r.start); s->event_pool.push_back(r.stop); }
+    s->prof.clear();
+  }
+  s->profiling = enable != 0;
+  return CW_OK;
+}
+
+cw_status cw_profile_read(cw_sim *s, int32_t kernel, double *total_ms, int64_t *launches)
+{
+  if (!s || !total_ms || !launches) return fail(CW_ERR_ARG, "null argument");
+  if (kernel < 0 || kernel >= CW_K_COUNT) return fail(CW_ERR_ARG, "bad kernel id %d", kernel);
+  double tot = 0;
+  int64_t cnt = 0;
+  for (auto &r : s->prof) {
+    if (r.kernel != kernel) continue;
+    HIPCHK(hipEventSynchronize(r.stop));
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, r.start, r.stop));
+    tot += ms;
+    cnt++;
+  }
+  *total_ms = tot;
+  *launches = cnt;
+  return CW_OK;
+}
+
+cw_status cw_steps_done(const cw_sim *s, int64_t *n)
+{
+  if (!s || !n) return fail(CW_ERR_ARG, "null argument");
+  *n = s->nstep;
+  return CW_OK;
+}
+
+cw_status cw_ricker(double f0, const double *t, int64_t n, double *out)
+{
+  if (!(f0 > 0) || (n > 0 && (!t || !out)) || n < 0) return fail(CW_ERR_ARG, "bad Ricker arguments");
+  for (int64_t m = 0; m < n; m++) {
+    const double x = kPi * f0 * (t[m] - 2.0 / f0);
+    const double x2 = x * x;
+    out[m] = (1.0 - 2.0 * x2) * std::exp(-x2);
+  }
+  return CW_OK;
+}
+
+}  // extern "C"

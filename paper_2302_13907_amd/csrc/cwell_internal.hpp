@@ -1,0 +1,67 @@
+// Internal declarations shared by the host API and the kernels of libcwell.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+namespace cw {
+
+enum Field { VR = 0, VT, VZ, SRR, STT, SZZ, SRT, SRZ, STZ, NF };
+
+// Layer memory variables living in the radial slab i >= nr - npml_r.
+enum PsiR {
+  R_VR_DR = 0, R_VR_B, R_VT_DR, R_VT_B, R_VZ_DR, R_VZ_B,
+  R_N_DR, R_N_B, R_RT_DR, R_RT_B, R_RZ_DR, R_TZ_B, NPSI_R
+};
+// ... and in the z slabs k < npml_z, k >= nz - 1 - npml_z.
+enum PsiZ { Z_VR_DZ = 0, Z_VT_DZ, Z_VZ_DZ, Z_N_DZ, Z_RZ_DZ, Z_TZ_DZ, NPSI_Z };
+
+// Rows of the packed radial layer table (each row nr floats): damping
+// coefficients a, b of the radial profile at centres r_i and faces R_i, and
+// of the integrated profile (stretching 1/r) at centres and faces.
+enum TabR { AR_C = 0, BR_C, AR_F, BR_F, AT_C, BT_C, AT_F, BT_F, NTAB_R };
+// Rows of the packed z table (each row nz floats): at z_k and z_{k+1/2}.
+enum TabZ { AZ_C = 0, BZ_C, AZ_H, BZ_H, NTAB_Z };
+
+// Everything one time step reads and writes, by value as a kernel argument.
+struct StepArgs {
+  int nr, nt, nz;
+  int npr, npz, nzs;        // layer cells in r, in z (each end), z-slab rows (2 npz + 1)
+  float dt, inv_dr, inv_dz, inv_dth;
+  const float *inv_rc;      // 1 / r_i  [nr]
+  const float *inv_rf;      // 1 / R_i  [nr]
+  const float *rho, *lam, *mu;
+  const float *in[NF];      // state at level n (v^{n-1/2}, sigma^n)
+  float *out[NF];           // state at level n+1
+  float *psi_r[NPSI_R];     // [npr][nt][nz]
+  float *psi_z[NPSI_Z];     // [nr][nt][nzs]
+  const float *tab_r;       // [NTAB_R][nr]
+  const float *tab_z;       // [NTAB_Z][nz]
+};
+
+// One point (or ring) injection: field[(i, j or all j, k)] += scale * amp[n].
+struct Inject {
+  int field, i, j, k;       // j = -1: the whole ring
+  int phase;                // 0: after the velocity update, 1: after the stress update
+  int nsamp;                // amp has nsamp entries
+  float scale;              // 1, or the node buoyancy for force sources
+  const float *amp;         // dt * w[n] / V, float32
+};
+
+// One receiver: trace[id][n] = ring mean or point value.
+struct Receiver {
+  int kind, field, i, j, k;
+};
+
+// Launchers (step kernels), enqueued on `stream`.
+hipError_t launch_velocity_basic(const StepArgs &a, hipStream_t stream);
+hipError_t launch_stress_basic(const StepArgs &a, hipStream_t stream);
+hipError_t launch_inject(const Inject *dev_list, int ninj, int phase, int64_t step,
+                         const StepArgs &a, hipStream_t stream);
+hipError_t launch_record(const Receiver *dev_rec, int nrec, int64_t step, int64_t cap,
+                         const StepArgs &a, double *traces, hipStream_t stream);
+hipError_t launch_energy(const StepArgs &a, double *partials, int nblocks, double scale,
+                         double *result, hipStream_t stream);
+
+}  // namespace cw

@@ -1,0 +1,349 @@
+// Straightforward kernels of the time step: one thread per cell, k (depth)
+// across the lanes so every load of a wavefront is one contiguous 256-byte
+// run.  The velocity and stress updates are separate launches (two passes
+// over the state); they are the plain FP32 form the fused kernel is checked
+// against, and they carry the source, receiver and energy kernels.
+//
+// The discrete operators are the staggered-grid form (Sec. 3) of Eq. (1):
+//   rho dv_r/dt = ds_rr/dr + (1/r)(ds_rt/dth + s_rr - s_tt) + ds_rz/dz
+//   rho dv_t/dt = ds_rt/dr + (1/r)(ds_tt/dth + 2 s_rt)      + ds_tz/dz
+//   rho dv_z/dt = ds_rz/dr + (1/r)(ds_tz/dth + s_rz)        + ds_zz/dz
+//   ds_qq/dt = lam tr(e) + 2 mu e_qq, e_rr = dv_r/dr,
+//              e_tt = (1/r)(dv_t/dth + v_r), e_zz = dv_z/dz
+//   ds_rt/dt = mu (dv_t/dr + (1/r)(dv_r/dth - v_t))
+//   ds_rz/dt = mu (dv_z/dr + dv_r/dz),  ds_tz/dt = mu ((1/r) dv_z/dth + dv_t/dz)
+// with the curvature terms averaged onto each node, zero values beyond the
+// axis and the outer faces, and every r- or z-derivative term and 1/r
+// bracket passed through the absorbing layer's recursive convolution.
+#include "cwell_internal.hpp"
+
+namespace cw {
+
+namespace {
+
+__device__ __forceinline__ float ld(const float *f, const StepArgs &a, int i, int j, int k)
+{
+  if (i < 0 || i >= a.nr || k < 0 || k >= a.nz) return 0.0f;
+  return f[((size_t)i * a.nt + j) * a.nz + k];
+}
+
+__device__ __forceinline__ size_t at(const StepArgs &a, int i, int j, int k)
+{
+  return ((size_t)i * a.nt + j) * a.nz + k;
+}
+
+// Harmonic mean of four moduli: 4 / (1/a + 1/b + 1/c + 1/d).  A zero
+// argument makes its reciprocal +inf and the mean exactly zero.
+__device__ __forceinline__ float hm4(float p, float q, float r, float s)
+{
+  return 4.0f / (1.0f / p + 1.0f / q + 1.0f / r + 1.0f / s);
+}
+
+// z-slab row of depth index k, or -1 outside the slabs.
+__device__ __forceinline__ int zrow(const StepArgs &a, int k)
+{
+  if (a.npz == 0) return -1;
+  if (k < a.npz) return k;
+  int lo = a.nz - 1 - a.npz;
+  if (k >= lo) return k - lo + a.npz;
+  return -1;
+}
+
+// psi <- b psi + a X; returns X + psi
+__device__ __forceinline__ float cpml(float *psi, size_t p, float ca, float cb, float X)
+{
+  float v = cb * psi[p] + ca * X;
+  psi[p] = v;
+  return X + v;
+}
+
+__global__ void __launch_bounds__(256) k_velocity_basic(StepArgs a)
+{
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y, i = blockIdx.z;
+  if (k >= a.nz) return;
+  const int jm = j == 0 ? a.nt - 1 : j - 1;
+  const int jp = j == a.nt - 1 ? 0 : j + 1;
+  const float *sRR = a.in[SRR], *sTT = a.in[STT], *sZZ = a.in[SZZ];
+  const float *sRT = a.in[SRT], *sRZ = a.in[SRZ], *sTZ = a.in[STZ];
+
+  const float srr0 = ld(sRR, a, i, j, k), srr1 = ld(sRR, a, i + 1, j, k);
+  const float stt0 = ld(sTT, a, i, j, k), stt1 = ld(sTT, a, i + 1, j, k), stt_jp = ld(sTT, a, i, jp, k);
+  const float srt0 = ld(sRT, a, i, j, k), srt_jm = ld(sRT, a, i, jm, k), srt_im = ld(sRT, a, i - 1, j, k);
+  const float srz0 = ld(sRZ, a, i, j, k), srz_km = ld(sRZ, a, i, j, k - 1), srz_im = ld(sRZ, a, i - 1, j, k);
+  const float stz0 = ld(sTZ, a, i, j, k), stz_jm = ld(sTZ, a, i, jm, k), stz_km = ld(sTZ, a, i, j, k - 1);
+  const float szz0 = ld(sZZ, a, i, j, k), szz_kp = ld(sZZ, a, i, j, k + 1);
+
+  const float irc = a.inv_rc[i], irf = a.inv_rf[i];
+  // v_r at (R_i, th_j, z_k)
+  float r_dr = (srr1 - srr0) * a.inv_dr;
+  float r_b = irf * ((srt0 - srt_jm) * a.inv_dth + 0.5f * (srr1 + srr0) - 0.5f * (stt1 + stt0));
+  float r_dz = (srz0 - srz_km) * a.inv_dz;
+  // v_t at (r_i, th_j+1/2, z_k)
+  float t_dr = (srt0 - srt_im) * a.inv_dr;
+  float t_b = irc * ((stt_jp - stt0) * a.inv_dth + (srt0 + srt_im));
+  float t_dz = (stz0 - stz_km) * a.inv_dz;
+  // v_z at (r_i, th_j, z_k+1/2)
+  float z_dr = (srz0 - srz_im) * a.inv_dr;
+  float z_b = irc * ((stz0 - stz_jm) * a.inv_dth + 0.5f * (srz0 + srz_im));
+  float z_dz = (szz_kp - szz0) * a.inv_dz;
+
+  const int ir = i - (a.nr - a.npr);
+  if (ir >= 0) {
+    const size_t q = ((size_t)ir * a.nt + j) * a.nz + k;
+    const float *T = a.tab_r;
+    r_dr = cpml(a.psi_r[R_VR_DR], q, T[AR_F * a.nr + i], T[BR_F * a.nr + i], r_dr);
+    r_b = cpml(a.psi_r[R_VR_B], q, T[AT_F * a.nr + i], T[BT_F * a.nr + i], r_b);
+    t_dr = cpml(a.psi_r[R_VT_DR], q, T[AR_C * a.nr + i], T[BR_C * a.nr + i], t_dr);
+    t_b = cpml(a.psi_r[R_VT_B], q, T[AT_C * a.nr + i], T[BT_C * a.nr + i], t_b);
+    z_dr = cpml(a.psi_r[R_VZ_DR], q, T[AR_C * a.nr + i], T[BR_C * a.nr + i], z_dr);
+    z_b = cpml(a.psi_r[R_VZ_B], q, T[AT_C * a.nr + i], T[BT_C * a.nr + i], z_b);
+  }
+  const int kz = zrow(a, k);
+  if (kz >= 0) {
+    const size_t q = ((size_t)i * a.nt + j) * a.nzs + kz;
+    const float *T = a.tab_z;
+    r_dz = cpml(a.psi_z[Z_VR_DZ], q, T[AZ_C * a.nz + k], T[BZ_C * a.nz + k], r_dz);
+    t_dz = cpml(a.psi_z[Z_VT_DZ], q, T[AZ_C * a.nz + k], T[BZ_C * a.nz + k], t_dz);
+    z_dz = cpml(a.psi_z[Z_VZ_DZ], q, T[AZ_H * a.nz + k], T[BZ_H * a.nz + k], z_dz);
+  }
+
+  // buoyancies: arithmetic mean of the two adjacent densities (clamped at the edges)
+  const int i1 = i + 1 < a.nr ? i + 1 : a.nr - 1;
+  const int k1 = k + 1 < a.nz ? k + 1 : a.nz - 1;
+  const size_t p = at(a, i, j, k);
+  const float rho0 = a.rho[p];
+  const float b_r = 2.0f / (rho0 + a.rho[at(a, i1, j, k)]);
+  const float b_t = 2.0f / (rho0 + a.rho[at(a, i, jp, k)]);
+  const float b_z = 2.0f / (rho0 + a.rho[at(a, i, j, k1)]);
+
+  a.out[VR][p] = a.in[VR][p] + a.dt * b_r * (r_dr + r_b + r_dz);
+  a.out[VT][p] = a.in[VT][p] + a.dt * b_t * (t_dr + t_b + t_dz);
+  a.out[VZ][p] = a.in[VZ][p] + a.dt * b_z * (z_dr + z_b + z_dz);
+}
+
+__global__ void __launch_bounds__(256) k_stress_basic(StepArgs a)
+{
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y, i = blockIdx.z;
+  if (k >= a.nz) return;
+  const int jm = j == 0 ? a.nt - 1 : j - 1;
+  const int jp = j == a.nt - 1 ? 0 : j + 1;
+  // velocities at level n+1/2 are in the output buffer
+  const float *vR = a.out[VR], *vT = a.out[VT], *vZ = a.out[VZ];
+
+  const float vr0 = ld(vR, a, i, j, k), vr_im = ld(vR, a, i - 1, j, k);
+  const float vr_jp = ld(vR, a, i, jp, k), vr_kp = ld(vR, a, i, j, k + 1);
+  const float vt0 = ld(vT, a, i, j, k), vt_jm = ld(vT, a, i, jm, k);
+  const float vt_ip = ld(vT, a, i + 1, j, k), vt_kp = ld(vT, a, i, j, k + 1);
+  const float vz0 = ld(vZ, a, i, j, k), vz_km = ld(vZ, a, i, j, k - 1);
+  const float vz_ip = ld(vZ, a, i + 1, j, k), vz_jp = ld(vZ, a, i, jp, k);
+
+  const float irc = a.inv_rc[i], irf = a.inv_rf[i];
+  float err = (vr0 - vr_im) * a.inv_dr;
+  float ett = irc * ((vt0 - vt_jm) * a.inv_dth + 0.5f * (vr0 + vr_im));
+  float ezz = (vz0 - vz_km) * a.inv_dz;
+  float rt_dr = (vt_ip - vt0) * a.inv_dr;
+  float rt_b = irf * ((vr_jp - vr0) * a.inv_dth - 0.5f * (vt_ip + vt0));
+  float rz_dr = (vz_ip - vz0) * a.inv_dr;
+  float rz_dz = (vr_kp - vr0) * a.inv_dz;
+  float tz_b = irc * (vz_jp - vz0) * a.inv_dth;
+  float tz_dz = (vt_kp - vt0) * a.inv_dz;
+
+  const int ir = i - (a.nr - a.npr);
+  if (ir >= 0) {
+    const size_t q = ((size_t)ir * a.nt + j) * a.nz + k;
+    const float *T = a.tab_r;
+    err = cpml(a.psi_r[R_N_DR], q, T[AR_C * a.nr + i], T[BR_C * a.nr + i], err);
+    ett = cpml(a.psi_r[R_N_B], q, T[AT_C * a.nr + i], T[BT_C * a.nr + i], ett);
+    rt_dr = cpml(a.psi_r[R_RT_DR], q, T[AR_F * a.nr + i], T[BR_F * a.nr + i], rt_dr);
+    rt_b = cpml(a.psi_r[R_RT_B], q, T[AT_F * a.nr + i], T[BT_F * a.nr + i], rt_b);
+    rz_dr = cpml(a.psi_r[R_RZ_DR], q, T[AR_F * a.nr + i], T[BR_F * a.nr + i], rz_dr);
+    tz_b = cpml(a.psi_r[R_TZ_B], q, T[AT_C * a.nr + i], T[BT_C * a.nr + i], tz_b);
+  }
+  const int kz = zrow(a, k);
+  if (kz >= 0) {
+    const size_t q = ((size_t)i * a.nt + j) * a.nzs + kz;
+    const float *T = a.tab_z;
+    ezz = cpml(a.psi_z[Z_N_DZ], q, T[AZ_C * a.nz + k], T[BZ_C * a.nz + k], ezz);
+    rz_dz = cpml(a.psi_z[Z_RZ_DZ], q, T[AZ_H * a.nz + k], T[BZ_H * a.nz + k], rz_dz);
+    tz_dz = cpml(a.psi_z[Z_TZ_DZ], q, T[AZ_H * a.nz + k], T[BZ_H * a.nz + k], tz_dz);
+  }
+
+  const int i1 = i + 1 < a.nr ? i + 1 : a.nr - 1;
+  const int k1 = k + 1 < a.nz ? k + 1 : a.nz - 1;
+  const size_t p = at(a, i, j, k);
+  const float lam = a.lam[p], mu = a.mu[p];
+  const float mu_i1 = a.mu[at(a, i1, j, k)], mu_jp = a.mu[at(a, i, jp, k)];
+  const float mu_k1 = a.mu[at(a, i, j, k1)];
+  const float mu_rt = hm4(mu, mu_i1, mu_jp, a.mu[at(a, i1, jp, k)]);
+  const float mu_rz = hm4(mu, mu_i1, mu_k1, a.mu[at(a, i1, j, k1)]);
+  const float mu_tz = hm4(mu, mu_jp, mu_k1, a.mu[at(a, i, jp, k1)]);
+
+  const float tr = err + ett + ezz;
+  const float lt = lam * tr, m2 = 2.0f * mu;
+  a.out[SRR][p] = a.in[SRR][p] + a.dt * (lt + m2 * err);
+  a.out[STT][p] = a.in[STT][p] + a.dt * (lt + m2 * ett);
+  a.out[SZZ][p] = a.in[SZZ][p] + a.dt * (lt + m2 * ezz);
+  a.out[SRT][p] = a.in[SRT][p] + a.dt * mu_rt * (rt_dr + rt_b);
+  a.out[SRZ][p] = a.in[SRZ][p] + a.dt * mu_rz * (rz_dr + rz_dz);
+  a.out[STZ][p] = a.in[STZ][p] + a.dt * mu_tz * (tz_b + tz_dz);
+}
+
+// One block applies every injection of the phase in list order, so two
+// sources hitting the same node add in a fixed order.
+__global__ void __launch_bounds__(256) k_inject(const Inject *list, int ninj, int phase,
+                                                int64_t step, StepArgs a)
+{
+  for (int m = 0; m < ninj; m++) {
+    const Inject e = list[m];
+    if (e.phase == phase && step < e.nsamp) {
+      const float amp = e.scale * e.amp[step];
+      float *f = a.out[e.field];
+      if (e.j >= 0) {
+        if (threadIdx.x == 0) f[at(a, e.i, e.j, e.k)] += amp;
+      } else {
+        for (int j = threadIdx.x; j < a.nt; j += blockDim.x) f[at(a, e.i, j, e.k)] += amp;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// One wavefront per receiver; float64 sum over the ring in a fixed order.
+__global__ void __launch_bounds__(64) k_record(const Receiver *rec, int64_t step, int64_t cap,
+                                               StepArgs a, double *traces)
+{
+  const Receiver r = rec[blockIdx.x];
+  const int j0 = r.j < 0 ? 0 : r.j, j1 = r.j < 0 ? a.nt : r.j + 1;
+  double acc = 0.0;
+  for (int j = j0 + (int)threadIdx.x; j < j1; j += 64) {
+    const size_t p = at(a, r.i, j, r.k);
+    if (r.kind == 0)
+      acc += (double)a.out[SRR][p] + (double)a.out[STT][p] + (double)a.out[SZZ][p];
+    else
+      acc += (double)a.out[r.field][p];
+  }
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if (threadIdx.x == 0) {
+    const double cnt = (double)(j1 - j0);
+    traces[(size_t)blockIdx.x * cap + step] = r.kind == 0 ? -acc / (3.0 * cnt) : acc / cnt;
+  }
+}
+
+// Energy density of one cell in float64; a.in = level n, a.out = level n+1.
+__device__ double cell_energy(const StepArgs &a, int i, int j, int k)
+{
+  const int jp = j == a.nt - 1 ? 0 : j + 1;
+  const int i1 = i + 1 < a.nr ? i + 1 : a.nr - 1;
+  const int k1 = k + 1 < a.nz ? k + 1 : a.nz - 1;
+  const size_t p = at(a, i, j, k);
+  const double ri = (double)(i + 0.5), Ri = (double)(i + 1);   // radii in units of dr
+  const double rho0 = a.rho[p];
+  const double rr = 0.5 * (rho0 + a.rho[at(a, i1, j, k)]);
+  const double rt = 0.5 * (rho0 + a.rho[at(a, i, jp, k)]);
+  const double rz = 0.5 * (rho0 + a.rho[at(a, i, j, k1)]);
+  const double vr = a.out[VR][p], vt = a.out[VT][p], vz = a.out[VZ][p];
+  double E = 0.5 * (Ri * rr * vr * vr + ri * rt * vt * vt + ri * rz * vz * vz);
+  const double lam = a.lam[p], mu = a.mu[p];
+  const double K = lam + 2.0 * mu / 3.0;
+  const double n1[3] = {a.out[SRR][p], a.out[STT][p], a.out[SZZ][p]};
+  const double n0[3] = {a.in[SRR][p], a.in[STT][p], a.in[SZZ][p]};
+  const double t1 = n1[0] + n1[1] + n1[2], t0 = n0[0] + n0[1] + n0[2];
+  E += 0.5 * ri * t1 * t0 / (9.0 * K);
+  if (mu > 0.0) {
+    double d = 0.0;
+    for (int q = 0; q < 3; q++) d += (n1[q] - t1 / 3.0) * (n0[q] - t0 / 3.0);
+    E += 0.5 * ri * d / (2.0 * mu);
+  }
+  const double m_i1 = a.mu[at(a, i1, j, k)], m_jp = a.mu[at(a, i, jp, k)], m_k1 = a.mu[at(a, i, j, k1)];
+  auto hm = [](double w, double x, double y, double z) {
+    return (w == 0.0 || x == 0.0 || y == 0.0 || z == 0.0) ? 0.0 : 4.0 / (1.0 / w + 1.0 / x + 1.0 / y + 1.0 / z);
+  };
+  const double mrt = hm(mu, m_i1, m_jp, a.mu[at(a, i1, jp, k)]);
+  const double mrz = hm(mu, m_i1, m_k1, a.mu[at(a, i1, j, k1)]);
+  const double mtz = hm(mu, m_jp, m_k1, a.mu[at(a, i, jp, k1)]);
+  if (mrt > 0.0) E += 0.5 * Ri * (double)a.out[SRT][p] * (double)a.in[SRT][p] / mrt;
+  if (mrz > 0.0) E += 0.5 * Ri * (double)a.out[SRZ][p] * (double)a.in[SRZ][p] / mrz;
+  if (mtz > 0.0) E += 0.5 * ri * (double)a.out[STZ][p] * (double)a.in[STZ][p] / mtz;
+  return E;
+}
+
+__global__ void __launch_bounds__(256) k_energy_partial(StepArgs a, double *partials)
+{
+  __shared__ double red[256];
+  const size_t n = (size_t)a.nr * a.nt * a.nz;
+  double acc = 0.0;
+  for (size_t c = (size_t)blockIdx.x * 256 + threadIdx.x; c < n; c += (size_t)gridDim.x * 256) {
+    const int k = (int)(c % a.nz);
+    const size_t ij = c / a.nz;
+    const int j = (int)(ij % a.nt), i = (int)(ij / a.nt);
+    acc += cell_energy(a, i, j, k);
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partials[blockIdx.x] = red[0];
+}
+
+__global__ void __launch_bounds__(256) k_energy_final(const double *partials, int n, double scale,
+                                                      double *result)
+{
+  __shared__ double red[256];
+  double acc = 0.0;
+  for (int c = threadIdx.x; c < n; c += 256) acc += partials[c];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *result = red[0] * scale;
+}
+
+}  // namespace
+
+hipError_t launch_velocity_basic(const StepArgs &a, hipStream_t stream)
+{
+  dim3 grid((a.nz + 255) / 256, a.nt, a.nr);
+  hipLaunchKernelGGL(k_velocity_basic, grid, dim3(256), 0, stream, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_stress_basic(const StepArgs &a, hipStream_t stream)
+{
+  dim3 grid((a.nz + 255) / 256, a.nt, a.nr);
+  hipLaunchKernelGGL(k_stress_basic, grid, dim3(256), 0, stream, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_inject(const Inject *dev_list, int ninj, int phase, int64_t step,
+                         const StepArgs &a, hipStream_t stream)
+{
+  if (ninj == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_inject, dim3(1), dim3(256), 0, stream, dev_list, ninj, phase, step, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_record(const Receiver *dev_rec, int nrec, int64_t step, int64_t cap,
+                         const StepArgs &a, double *traces, hipStream_t stream)
+{
+  if (nrec == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_record, dim3(nrec), dim3(64), 0, stream, dev_rec, step, cap, a, traces);
+  return hipGetLastError();
+}
+
+hipError_t launch_energy(const StepArgs &a, double *partials, int nblocks, double scale,
+                         double *result, hipStream_t stream)
+{
+  hipLaunchKernelGGL(k_energy_partial, dim3(nblocks), dim3(256), 0, stream, a, partials);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(256), 0, stream, partials, nblocks, scale, result);
+  return hipGetLastError();
+}
+
+}  // namespace cw

@@ -1,0 +1,250 @@
+"""Thin Python binding of libcwell (the C ABI declared in include/cwell.h).
+
+Argument marshalling only: every step of the solver runs in the library's
+HIP kernels.  PyTorch supplies the device workspace and the stream.  The
+library must have been built (``python -m paper_2302_13907_amd.build`` or
+``__graft_entry__.build()``); there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcwell.so")
+
+FIELDS = ("vr", "vt", "vz", "srr", "stt", "szz", "srt", "srz", "stz")
+SRC_KINDS = {"volume": 0, "force_r": 1, "force_z": 2, "torsion": 3}
+REC_KINDS = {"pressure": 0, "field": 1}
+
+CW_OK = 0
+STATUS = {0: "CW_OK", -1: "CW_ERR_ARG", -2: "CW_ERR_RANGE", -3: "CW_ERR_MATERIAL",
+          -4: "CW_ERR_UNSTABLE", -5: "CW_ERR_STATE", -6: "CW_ERR_NONFINITE",
+          -7: "CW_ERR_HIP", -8: "CW_ERR_NOMEM"}
+
+# every symbol include/cwell.h declares
+EXPORTS = ("cw_create", "cw_set_material", "cw_set_material_rz", "cw_set_pml", "cw_cfl_dt",
+           "cw_set_dt", "cw_add_source", "cw_add_receiver", "cw_set_trace_capacity",
+           "cw_workspace_bytes", "cw_bind", "cw_step", "cw_sync", "cw_get_traces",
+           "cw_get_field", "cw_set_field", "cw_energy", "cw_reset", "cw_steps_done",
+           "cw_ricker", "cw_destroy", "cw_last_error", "cw_profile", "cw_profile_read")
+
+KERNELS = {"velocity": 0, "stress": 1, "fused": 2, "inject": 3, "record": 4}
+
+
+class CwellError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("%s: %s" % (STATUS.get(status, status), msg))
+        self.status = status
+
+
+class _Grid(ctypes.Structure):
+    _fields_ = [("nr", ctypes.c_int32), ("ntheta", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("dr", ctypes.c_double), ("dz", ctypes.c_double)]
+
+
+_lib = None
+
+
+def load():
+    """Load libcwell.so (after torch, so both share torch's HIP runtime)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    import torch  # noqa: F401  -- the HIP runtime the library binds to
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libcwell.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I32, I64, D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    DP = ctypes.POINTER(ctypes.c_double)
+    FP = ctypes.POINTER(ctypes.c_float)
+    sig = {
+        "cw_create": [ctypes.POINTER(_Grid), ctypes.POINTER(P)],
+        "cw_set_material": [P, DP, DP, DP],
+        "cw_set_material_rz": [P, DP, DP, DP],
+        "cw_set_pml": [P, I32, I32, D, D],
+        "cw_cfl_dt": [P, DP],
+        "cw_set_dt": [P, D],
+        "cw_add_source": [P, I32, I32, I32, I32, DP, I64],
+        "cw_add_receiver": [P, I32, I32, I32, I32, I32, ctypes.POINTER(I32)],
+        "cw_set_trace_capacity": [P, I64],
+        "cw_workspace_bytes": [P, ctypes.POINTER(ctypes.c_uint64)],
+        "cw_bind": [P, P, ctypes.c_uint64, P],
+        "cw_step": [P, I64],
+        "cw_sync": [P],
+        "cw_get_traces": [P, DP, I64, ctypes.POINTER(I64)],
+        "cw_get_field": [P, I32, FP],
+        "cw_set_field": [P, I32, FP],
+        "cw_energy": [P, DP],
+        "cw_reset": [P],
+        "cw_steps_done": [P, ctypes.POINTER(I64)],
+        "cw_ricker": [D, DP, I64, DP],
+        "cw_profile": [P, I32],
+        "cw_profile_read": [P, I32, DP, ctypes.POINTER(I64)],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int32
+    lib.cw_destroy.argtypes = [P]
+    lib.cw_destroy.restype = None
+    lib.cw_last_error.argtypes = []
+    lib.cw_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(st: int):
+    if st != CW_OK:
+        raise CwellError(st, load().cw_last_error().decode())
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _fp(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+
+
+def ricker(f0: float, t) -> np.ndarray:
+    """Ricker pulse of Sec. 2 (delay 2/f0) at times t, computed by libcwell."""
+    t = np.ascontiguousarray(np.atleast_1d(t), dtype=np.float64)
+    out = np.empty_like(t)
+    _check(load().cw_ricker(float(f0), _dp(t), len(t), _dp(out)))
+    return out
+
+
+class Sim:
+    """One simulation on one GPU.  Arrays are C order [nr][ntheta][nz]."""
+
+    def __init__(self, nr: int, ntheta: int, nz: int, dr: float, dz: float):
+        self.lib = load()
+        self.shape = (int(nr), int(ntheta), int(nz))
+        self.dr, self.dz = float(dr), float(dz)
+        g = _Grid(int(nr), int(ntheta), int(nz), float(dr), float(dz))
+        h = ctypes.c_void_p()
+        _check(self.lib.cw_create(ctypes.byref(g), ctypes.byref(h)))
+        self.h = h
+        self.nrec = 0
+        self.workspace = None
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.cw_destroy(self.h)
+            self.h = None
+        self.workspace = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_material(self, rho, lam, mu):
+        """3-D arrays [nr][nt][nz], or axisymmetric [nr][nz] ones."""
+        arrs = [np.ascontiguousarray(x, dtype=np.float64) for x in (rho, lam, mu)]
+        if arrs[0].shape == (self.shape[0], self.shape[2]):
+            for a in arrs:
+                if a.shape != arrs[0].shape:
+                    raise ValueError("medium arrays differ in shape")
+            _check(self.lib.cw_set_material_rz(self.h, *[_dp(a) for a in arrs]))
+            return
+        arrs = [np.ascontiguousarray(np.broadcast_to(a, self.shape), dtype=np.float64) for a in arrs]
+        _check(self.lib.cw_set_material(self.h, *[_dp(a) for a in arrs]))
+
+    def set_pml(self, npml_r: int, npml_z: int, rc: float = 1e-3, alpha: float = 0.0):
+        _check(self.lib.cw_set_pml(self.h, int(npml_r), int(npml_z), float(rc), float(alpha)))
+
+    def cfl_dt(self) -> float:
+        v = ctypes.c_double()
+        _check(self.lib.cw_cfl_dt(self.h, ctypes.byref(v)))
+        return v.value
+
+    def set_dt(self, dt: float):
+        _check(self.lib.cw_set_dt(self.h, float(dt)))
+        self.dt = float(dt)
+
+    def add_source(self, kind: str, i: int, j: int, k: int, w: Sequence[float]):
+        w = np.ascontiguousarray(w, dtype=np.float64)
+        _check(self.lib.cw_add_source(self.h, SRC_KINDS[kind], i, j, k, _dp(w), len(w)))
+
+    def add_receiver(self, kind: str, i: int, j: int, k: int, field: Optional[str] = None) -> int:
+        rid = ctypes.c_int32()
+        fid = FIELDS.index(field) if field else 0
+        _check(self.lib.cw_add_receiver(self.h, REC_KINDS[kind], fid, i, j, k, ctypes.byref(rid)))
+        self.nrec += 1
+        return rid.value
+
+    def set_trace_capacity(self, nsteps: int):
+        _check(self.lib.cw_set_trace_capacity(self.h, int(nsteps)))
+        self.trace_cap = int(nsteps)
+
+    def workspace_bytes(self) -> int:
+        b = ctypes.c_uint64()
+        _check(self.lib.cw_workspace_bytes(self.h, ctypes.byref(b)))
+        return b.value
+
+    def bind(self, device: str = "cuda", stream=None):
+        """Allocate the device workspace with torch and hand it to the library."""
+        import torch
+        nbytes = self.workspace_bytes()
+        ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        ptr = ws.data_ptr()
+        off = (-ptr) % 256
+        if stream is None:
+            stream = torch.cuda.current_stream(ws.device)
+        self.stream = stream
+        self.workspace = ws
+        _check(self.lib.cw_bind(self.h, ctypes.c_void_p(ptr + off), nbytes,
+                                ctypes.c_void_p(stream.cuda_stream)))
+
+    def step(self, nsteps: int = 1):
+        _check(self.lib.cw_step(self.h, int(nsteps)))
+
+    def sync(self):
+        _check(self.lib.cw_sync(self.h))
+
+    @property
+    def steps_done(self) -> int:
+        n = ctypes.c_int64()
+        _check(self.lib.cw_steps_done(self.h, ctypes.byref(n)))
+        return n.value
+
+    def traces(self) -> np.ndarray:
+        n = self.steps_done
+        out = np.zeros((max(self.nrec, 1), max(n, 1)))
+        done = ctypes.c_int64()
+        _check(self.lib.cw_get_traces(self.h, _dp(out), out.shape[1], ctypes.byref(done)))
+        return out[: self.nrec, : done.value]
+
+    def field(self, name: str) -> np.ndarray:
+        out = np.empty(self.shape, dtype=np.float32)
+        _check(self.lib.cw_get_field(self.h, FIELDS.index(name), _fp(out)))
+        return out
+
+    def set_field(self, name: str, a):
+        a = np.ascontiguousarray(np.broadcast_to(a, self.shape), dtype=np.float32)
+        _check(self.lib.cw_set_field(self.h, FIELDS.index(name), _fp(a)))
+
+    def energy(self) -> float:
+        e = ctypes.c_double()
+        _check(self.lib.cw_energy(self.h, ctypes.byref(e)))
+        return e.value
+
+    def reset(self):
+        _check(self.lib.cw_reset(self.h))
+
+    def profile(self, enable: bool = True):
+        """Start (or stop and clear) per-launch HIP-event timing of the step kernels."""
+        _check(self.lib.cw_profile(self.h, 1 if enable else 0))
+
+    def kernel_time(self, kernel: str):
+        """(summed device milliseconds, launches) recorded for one step kernel."""
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        _check(self.lib.cw_profile_read(self.h, KERNELS[kernel], ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value

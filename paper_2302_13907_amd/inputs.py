@@ -86,6 +86,13 @@ def cased_well(nr: int, nt: int, nz: int, dr: float, dz: float,
     return rho, lam, mu
 
 
+def cased_well_rz(nr: int, nz: int, dr: float, dz: float, z_top: float, ramp: float = 0.0,
+                  radii: Tuple[float, float, float] = (R_HOLE, R_CASING, R_CEMENT)):
+    """Axisymmetric form of cased_well (no jitter): rho, lambda, mu as [nr][nz]."""
+    rho, lam, mu = cased_well(nr, 1, nz, dr, dz, z_top, ramp, 0.0, radii=radii)
+    return rho[:, 0, :].copy(), lam[:, 0, :].copy(), mu[:, 0, :].copy()
+
+
 def homogeneous(nr: int, nt: int, nz: int, mat=FLUID):
     ro, la, m = moduli(*mat)
     shape = (nr, nt, nz)
@@ -138,6 +145,16 @@ class Workload:
     def medium(self):
         return cased_well(self.nr, self.nt, self.nz, self.dr, self.dz,
                           self.z_top, self.ramp, self.rock_jitter)
+
+    def medium_rz(self):
+        """[nr][nz] arrays; only for workloads without azimuthal jitter."""
+        assert self.rock_jitter == 0
+        return cased_well_rz(self.nr, self.nz, self.dr, self.dz, self.z_top, self.ramp)
+
+    @property
+    def layer_cells(self):
+        """(cells in the radial layer slab, cells in the two z layer slabs)."""
+        return (self.npml * self.nt * self.nz, self.nr * self.nt * (2 * self.npml + 1))
 
 
 def parity_case() -> Workload:

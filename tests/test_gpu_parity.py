@@ -1,0 +1,221 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on
+the same seeded inputs, plus the physics properties that must hold bitwise
+or to FP32 rounding on the device.
+
+Tolerances: receiver traces within 1e-5 relative L2 of the oracle (FP32
+arithmetic, FP64 trace accumulation); fields within 1e-5 of their group's RMS
+(velocities / stresses)."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2302_13907_amd import cwell, inputs
+
+from gpu_common import (FIELDS, STRESS, VEL, Scenario, announce, field_errors, parity_scenario,
+                        rel_l2, run_gpu, run_oracle)
+
+pytestmark = pytest.mark.gpu
+
+TRACE_TOL = 1e-5
+FIELD_TOL = 1e-5
+
+
+def test_parity_case_traces_and_fields():
+    """48 x 32 x 192 cased well (5 mm), 300 steps, 10-cell layer, 20 kHz axis
+    source, 16 axis receivers, jittered rock."""
+    announce("parity case 48x32x192, 300 steps")
+    sc = parity_scenario()
+    tr_g, f_g = run_gpu(sc)
+    tr_o, f_o = run_oracle(sc)
+    assert np.abs(tr_o).max() > 0
+    e = rel_l2(tr_g, tr_o)
+    fe = field_errors(f_g, f_o)
+    announce("trace relL2 = %.3e; field errors " % e + " ".join("%s=%.2e" % kv for kv in fe.items()))
+    assert e <= TRACE_TOL, e
+    assert max(fe.values()) <= FIELD_TOL, fe
+
+
+def _cased(shape, h, z_top, jitter=0.02, ramp=0.0):
+    return inputs.cased_well(*shape, h, h, z_top=z_top, ramp=ramp, rock_jitter=jitter)
+
+
+CASES = {
+    # ragged z (not a multiple of the 64-lane rows), all four source kinds, layer on
+    "ragged_all_sources": dict(shape=(34, 12, 77), npml=(6, 5), steps=120, sources=[
+        ("volume", 0, -1, 30, 1.0), ("force_r", 3, 2, 40, 1e-3), ("force_z", 5, 7, 20, 1e-3),
+        ("torsion", 21, -1, 50, 1.0)]),
+    # a single azimuthal cell (axisymmetric), odd sizes, layer on
+    "ntheta_1": dict(shape=(31, 1, 65), npml=(5, 6), steps=150, sources=[
+        ("volume", 0, -1, 25, 1.0), ("torsion", 20, -1, 30, 1.0)]),
+    # three azimuthal cells, layer off (lossless closure), point sources
+    "ntheta_3_no_layer": dict(shape=(25, 3, 40), npml=(0, 0), steps=100, sources=[
+        ("volume", 2, 1, 20, 1.0), ("force_z", 0, 0, 10, 1e-3)]),
+    # layer in r only, long z
+    "layer_r_only": dict(shape=(30, 8, 300), npml=(8, 0), steps=80, sources=[
+        ("volume", 0, -1, 150, 1.0)]),
+    # graded cement top (zero-to-full shear ramp)
+    "ramp": dict(shape=(36, 8, 128), npml=(6, 6), steps=120, ramp=0.2, sources=[
+        ("volume", 0, -1, 30, 1.0)]),
+}
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_parity_edge_cases(name):
+    c = CASES[name]
+    shape = c["shape"]
+    h = 5e-3
+    announce("edge case %s %s" % (name, shape))
+    med = _cased(shape, h, z_top=shape[2] * h / 2, ramp=c.get("ramp", 0.0))
+    recs = [("pressure", 0, -1, k, None) for k in range(3, shape[2] - 3, max(1, shape[2] // 8))]
+    # point samples of every field near the first source (and one in the casing),
+    # where the wave arrives within the run
+    ks = min(c["sources"][0][3] + 2, shape[2] - 1)
+    recs += [("field", 2, 0, ks, f) for f in FIELDS]
+    recs += [("field", min(21, shape[0] - 1), 1 % shape[1], ks, f) for f in FIELDS]
+    recs += [("field", 1, -1, ks, "vr")]
+    sc = Scenario(shape=shape, h=(h, h), medium=med, steps=c["steps"], npml=c["npml"],
+                  sources=c["sources"], receivers=recs)
+    tr_g, f_g = run_gpu(sc)
+    tr_o, f_o = run_oracle(sc)
+    fe = field_errors(f_g, f_o)
+    announce("  field errors max %.2e" % max(fe.values()))
+    assert max(fe.values()) <= FIELD_TOL, fe
+    # traces group by group (pressure, velocity samples, stress samples): a
+    # single row may be exactly zero (decoupled field) or hold only the first
+    # arrivals' float32-rounding-level tail
+    kinds = [r[0] if r[0] == "pressure" else ("vel" if r[4] in VEL else "stress") for r in recs]
+    for g in ("pressure", "vel", "stress"):
+        rows = [m for m, kd in enumerate(kinds) if kd == g]
+        a, b = tr_g[rows], tr_o[rows]
+        if np.abs(b).max() == 0:
+            assert np.abs(a).max() == 0, g
+            continue
+        e = rel_l2(a, b)
+        announce("  %s traces relL2 %.2e" % (g, e))
+        assert e <= TRACE_TOL, (g, e)
+
+
+def test_theta_invariance_bitwise_gpu():
+    """theta-invariant medium + ring sources: every field identical along theta, bitwise."""
+    shape = (34, 16, 96)
+    med = inputs.cased_well(*shape, 5e-3, 5e-3, z_top=0.25, ramp=0.1)
+    sc = Scenario(shape=shape, h=(5e-3, 5e-3), medium=med, steps=200, npml=(6, 6),
+                  sources=[("volume", 0, -1, 30, 1.0), ("torsion", 21, -1, 60, 1.0)])
+    _, f = run_gpu(sc)
+    for n in FIELDS:
+        a = f[n]
+        assert np.array_equal(a, np.broadcast_to(a[:, :1, :], a.shape)), n
+    assert np.abs(f["vr"]).max() > 0 and np.abs(f["vt"]).max() > 0
+
+
+def test_decoupling_bitwise_gpu():
+    shape = (34, 8, 96)
+    med = inputs.cased_well(*shape, 5e-3, 5e-3, z_top=0.25)
+    sc = Scenario(shape=shape, h=(5e-3, 5e-3), medium=med, steps=150, npml=(6, 6),
+                  sources=[("volume", 0, -1, 30, 1.0)])
+    _, f = run_gpu(sc)
+    for n in ("vt", "srt", "stz"):
+        assert not np.any(f[n]), n
+    sc.sources = [("torsion", 21, -1, 30, 1.0)]
+    _, f = run_gpu(sc)
+    for n in ("vr", "vz", "srr", "stt", "szz", "srz"):
+        assert not np.any(f[n]), n
+    assert not np.any(f["vt"][:20])
+
+
+def _random_state(shape, med, seed):
+    """Random state the energy is exactly conserved for: isotropic stress in
+    the fluid, shear only on nodes whose effective shear modulus is not zero
+    (taken from the oracle's staggered coefficients)."""
+    import oracle
+    rng = np.random.default_rng(seed)
+    rho, lam, mu = med
+    fluid = mu == 0
+    p = rng.standard_normal(shape)
+    init = {}
+    for n in ("srr", "stt", "szz"):
+        init[n] = np.where(fluid, p, rng.standard_normal(shape))
+    o = oracle.OracleSim(*shape, 0.01, 0.01)
+    o.set_material(*med)
+    for n, c in (("srt", "mu_rt"), ("srz", "mu_rz"), ("stz", "mu_tz")):
+        init[n] = np.where(o.coef(c) > 0, rng.standard_normal(shape), 0.0)
+    for n in VEL:
+        init[n] = 1e-6 * rng.standard_normal(shape)
+    return {k: v.astype(np.float32).astype(np.float64) for k, v in init.items()}
+
+
+def test_energy_conservation_gpu():
+    """Layer off, no source, random heterogeneous medium with a fluid core:
+    the float64 energy of the float32 state drifts only at float32 rounding
+    level and tracks the oracle's energy."""
+    shape = (16, 12, 70)
+    med = inputs.random_medium(*shape, seed=3)
+    init = _random_state(shape, med, seed=8)
+    sc = Scenario(shape=shape, h=(0.01, 0.01), medium=med, steps=1, initial=init)
+    _, _, s = run_gpu(sc, keep_sim=True)
+    E = [s.energy()]
+    for _ in range(40):
+        s.step(10)
+        E.append(s.energy())
+    E = np.array(E)
+    drift = np.abs(E / E[0] - 1).max()
+    announce("energy drift over 401 steps: %.2e" % drift)
+    assert drift < 2e-5, drift
+    import oracle
+    o = oracle.OracleSim(*shape, 0.01, 0.01)
+    o.set_material(*med)
+    o.set_dt(0.5 * o.cfl_dt())
+    for n, a in init.items():
+        o.set_field(n, a)
+    _, Eo = o.run(401, energy=True)
+    assert abs(E[-1] / Eo[-1] - 1) < 2e-5
+    assert abs(E[0] / Eo[0] - 1) < 1e-6
+
+
+def test_reciprocity_gpu():
+    shape = (30, 4, 60)
+    med = inputs.cased_well(*shape, 5e-3, 5e-3, z_top=0.15, rock_jitter=0.02)
+    out = []
+    for ka, kb in ((15, 40), (40, 15)):
+        sc = Scenario(shape=shape, h=(5e-3, 5e-3), medium=med, steps=300, f0=30e3,
+                      sources=[("volume", 0, -1, ka, 1.0)],
+                      receivers=[("pressure", 0, -1, kb, None)])
+        out.append(run_gpu(sc)[0][0])
+    assert np.abs(out[0]).max() > 0
+    assert rel_l2(out[0], out[1]) < 1e-5
+
+
+def test_deterministic_bitwise():
+    sc = parity_scenario()
+    sc.steps = 60
+    a, fa = run_gpu(sc)
+    b, fb = run_gpu(sc)
+    assert np.array_equal(a, b)
+    for n in FIELDS:
+        assert np.array_equal(fa[n], fb[n]), n
+
+
+def test_api_state_after_bind():
+    s = cwell.Sim(8, 4, 16, 5e-3, 5e-3)
+    s.set_material(*inputs.homogeneous(8, 4, 16))
+    s.set_dt(0.5 * s.cfl_dt())
+    s.add_receiver("pressure", 0, -1, 3)
+    s.set_trace_capacity(5)
+    s.bind()
+    with pytest.raises(cwell.CwellError) as e:
+        s.set_material(*inputs.homogeneous(8, 4, 16))
+    assert e.value.status == -5
+    with pytest.raises(cwell.CwellError) as e:
+        s.energy()
+    assert e.value.status == -5
+    s.step(5)
+    with pytest.raises(cwell.CwellError) as e:
+        s.step(1)                      # trace capacity
+    assert e.value.status == -2
+    assert s.traces().shape == (1, 5)
+    s.reset()
+    assert s.steps_done == 0
+    s.step(2)
+    assert s.steps_done == 2
+    s.close()
