@@ -112,6 +112,11 @@ def main():
     ap.add_argument("--workload", choices=("production", "parity"), default="production")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--path", choices=("auto", "fused", "two-pass"), default="auto",
+                    help="kernel path of the step")
+    ap.add_argument("--copy-gib", type=float, default=0.0,
+                    help="after the run, copy this many GiB device-to-device once (a known-size "
+                         "reference dispatch for hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -141,6 +146,7 @@ def main():
     for k in w.rec_k:
         s.add_receiver("pressure", 0, -1, k)
     s.set_trace_capacity(total)
+    s.set_path(args.path)
     log("binding %.2f GB workspace" % (s.workspace_bytes() / 1e9))
     s.bind("cuda:0")
     log("warm-up %d steps" % args.warmup)
@@ -193,6 +199,16 @@ def main():
     s.close()
     del s
     torch.cuda.empty_cache()
+    if args.copy_gib > 0:
+        nb = int(args.copy_gib * (1 << 30))
+        src = torch.ones(nb // 4, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_reference_bytes"] = nb
+        del src, dst
+        torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         log("CPU baseline: FP64 oracle for about %.0f s" % args.cpu_seconds)
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)

@@ -174,6 +174,18 @@ cw_status cw_reset(cw_sim *s);
 /* Number of time steps done. */
 cw_status cw_steps_done(const cw_sim *s, int64_t *n);
 
+/* Kernel path of cw_step.  CW_PATH_TWO_PASS: a velocity launch and a
+   stress launch per step (plus source launches), one thread per cell, any
+   number of sources.  CW_PATH_FUSED: one launch per step that marches each
+   theta x depth tile outward through the rings and reads the state, the
+   medium and the layer memory once (float32 storage only, at most 12
+   source injections -- 3 per volume source, 2 per torsion source, 1 per
+   force -- and nr <= 2048).  CW_PATH_AUTO (default): the path measured
+   fastest on MI355X, the two-pass one.  Both compute the same scheme;
+   results agree to float32 rounding. */
+enum { CW_PATH_AUTO = 0, CW_PATH_TWO_PASS, CW_PATH_FUSED };
+cw_status cw_set_path(cw_sim *s, int32_t path);
+
 /* Kernel timing.  With enable = 1, cw_step brackets every launch of the
    step kernels with HIP events on the simulation's stream (a few
    microseconds of overhead per launch); enable = 0 stops recording and

@@ -18,6 +18,10 @@ namespace {
 
 constexpr double kPi = 3.14159265358979323846;
 constexpr int kEnergyBlocks = 1024;
+#ifndef CW_AUTO_FUSED
+#define CW_AUTO_FUSED 0
+#endif
+constexpr bool kAutoFused = CW_AUTO_FUSED;    // what CW_PATH_AUTO picks when the fused step applies
 
 thread_local std::string g_err;
 
@@ -75,11 +79,14 @@ struct cw_sim {
   float *fields[2][NF] = {};
   float *d_rho = nullptr, *d_lam = nullptr, *d_mu = nullptr;
   float *d_inv_rc = nullptr, *d_inv_rf = nullptr, *d_tab_r = nullptr, *d_tab_z = nullptr;
-  float *psi_r[NPSI_R] = {};
-  float *psi_z[NPSI_Z] = {};
+  float *psi_r[2][NPSI_R] = {};  // two copies: the fused step reads one, writes the other
+  float *psi_z[2][NPSI_Z] = {};
+  int psi_cur = 0;
+  int path = CW_PATH_AUTO;
   Inject *d_inject = nullptr;
   int ninject = 0;
   std::vector<Inject> inject_host;
+  std::vector<std::vector<float>> inject_amp;   // host copy of each injection's amplitudes
   Receiver *d_rec = nullptr;
   double *d_traces = nullptr;
   double *d_energy = nullptr;   // kEnergyBlocks partials + 1 result
@@ -134,8 +141,8 @@ Layout layout(const cw_sim *s)
   L.metric = take(2 * (size_t)s->nr * sizeof(float));
   L.tabr = take(NTAB_R * (size_t)s->nr * sizeof(float));
   L.tabz = take(NTAB_Z * (size_t)s->nz * sizeof(float));
-  L.psir = take((size_t)NPSI_R * s->npr * s->nt * s->nz * sizeof(float));
-  L.psiz = take((size_t)NPSI_Z * s->nr * s->nt * nzs_of(s) * sizeof(float));
+  L.psir = take(2 * (size_t)NPSI_R * s->npr * s->nt * s->nz * sizeof(float));
+  L.psiz = take(2 * (size_t)NPSI_Z * s->nr * s->nt * nzs_of(s) * sizeof(float));
   L.inject = take((size_t)inject_count(s) * sizeof(Inject));
   L.amp = take(amp_floats(s) * sizeof(float));
   L.rec = take(s->receivers.size() * sizeof(Receiver));
@@ -241,8 +248,8 @@ StepArgs step_args(const cw_sim *s, int in, int out)
   a.inv_rc = s->d_inv_rc; a.inv_rf = s->d_inv_rf;
   a.rho = s->d_rho; a.lam = s->d_lam; a.mu = s->d_mu;
   for (int q = 0; q < NF; q++) { a.in[q] = s->fields[in][q]; a.out[q] = s->fields[out][q]; }
-  for (int q = 0; q < NPSI_R; q++) a.psi_r[q] = s->psi_r[q];
-  for (int q = 0; q < NPSI_Z; q++) a.psi_z[q] = s->psi_z[q];
+  for (int q = 0; q < NPSI_R; q++) a.psi_r[q] = s->psi_r[s->psi_cur][q];
+  for (int q = 0; q < NPSI_Z; q++) a.psi_z[q] = s->psi_z[s->psi_cur][q];
   a.tab_r = s->d_tab_r; a.tab_z = s->d_tab_z;
   return a;
 }
@@ -279,13 +286,14 @@ cw_status zero_state(cw_sim *s)
 {
   const Layout L = layout(s);
   HIPCHK(hipMemsetAsync(s->ws + L.fields, 0, 2 * NF * s->n * sizeof(float), s->stream));
-  const size_t psir = (size_t)NPSI_R * s->npr * s->nt * s->nz * sizeof(float);
-  const size_t psiz = (size_t)NPSI_Z * s->nr * s->nt * nzs_of(s) * sizeof(float);
+  const size_t psir = 2 * (size_t)NPSI_R * s->npr * s->nt * s->nz * sizeof(float);
+  const size_t psiz = 2 * (size_t)NPSI_Z * s->nr * s->nt * nzs_of(s) * sizeof(float);
   if (psir) HIPCHK(hipMemsetAsync(s->ws + L.psir, 0, psir, s->stream));
   if (psiz) HIPCHK(hipMemsetAsync(s->ws + L.psiz, 0, psiz, s->stream));
   const size_t tb = s->receivers.size() * (size_t)s->trace_cap * sizeof(double);
   if (tb) HIPCHK(hipMemsetAsync(s->ws + L.traces, 0, tb, s->stream));
   s->cur = 0;
+  s->psi_cur = 0;
   s->nstep = 0;
   return CW_OK;
 }
@@ -471,8 +479,12 @@ cw_status cw_bind(cw_sim *s, void *workspace, uint64_t bytes, void *stream)
   s->d_tab_r = (float *)(w + L.tabr);
   s->d_tab_z = (float *)(w + L.tabz);
   const size_t slab_r = (size_t)s->npr * s->nt * s->nz, slab_z = (size_t)s->nr * s->nt * nzs_of(s);
-  for (int q = 0; q < NPSI_R; q++) s->psi_r[q] = slab_r ? (float *)(w + L.psir) + q * slab_r : nullptr;
-  for (int q = 0; q < NPSI_Z; q++) s->psi_z[q] = slab_z ? (float *)(w + L.psiz) + q * slab_z : nullptr;
+  for (int c = 0; c < 2; c++) {
+    for (int q = 0; q < NPSI_R; q++)
+      s->psi_r[c][q] = slab_r ? (float *)(w + L.psir) + (c * NPSI_R + q) * slab_r : nullptr;
+    for (int q = 0; q < NPSI_Z; q++)
+      s->psi_z[c][q] = slab_z ? (float *)(w + L.psiz) + (c * NPSI_Z + q) * slab_z : nullptr;
+  }
   s->d_inject = (Inject *)(w + L.inject);
   s->d_rec = (Receiver *)(w + L.rec);
   s->d_traces = (double *)(w + L.traces);
@@ -481,6 +493,7 @@ cw_status cw_bind(cw_sim *s, void *workspace, uint64_t bytes, void *stream)
   // injections: dt * w[n] / V per target node, V the node (or ring) volume
   std::vector<float> amps(amp_floats(s));
   s->inject_host.clear();
+  s->inject_amp.clear();
   size_t ao = 0;
   float *d_amp = (float *)(w + L.amp);
   for (const auto &src : s->sources) {
@@ -513,6 +526,7 @@ cw_status cw_bind(cw_sim *s, void *workspace, uint64_t bytes, void *stream)
       e.scale = (float)scale;
       e.amp = d_amp + ao;
       for (size_t m = 0; m < src.w.size(); m++) amps[ao + m] = (float)(s->dt * src.w[m] / vol);
+      s->inject_amp.emplace_back(amps.begin() + ao, amps.begin() + ao + src.w.size());
       ao += src.w.size();
       s->inject_host.push_back(e);
     }
@@ -550,15 +564,49 @@ cw_status cw_step(cw_sim *s, int64_t nsteps)
   HIPCHK(hipSetDevice(s->device));
   cw_status st;
   const int nrec = (int)s->receivers.size();
+  // the fused step addresses a ring with 32-bit byte offsets
+  const bool fits = s->ninject <= kMaxFusedInject && s->nr <= kMaxFusedRings &&
+                    (uint64_t)s->nt * s->nz * 4 < (1ull << 32);
+  const bool fused = s->path == CW_PATH_FUSED || (s->path == CW_PATH_AUTO && fits && kAutoFused);
+
+  if (s->path == CW_PATH_FUSED && !fits)
+    return fail(CW_ERR_RANGE, "the fused step takes at most %d injections and %d rings (have %d, %d)",
+                kMaxFusedInject, kMaxFusedRings, s->ninject, s->nr);
+  FusedArgs f{};
+  if (fused) fused_tiles(s->nt, s->nz, &f.own_rows, &f.ntile_z);
   for (int64_t t = 0; t < nsteps; t++) {
     const StepArgs a = step_args(s, s->cur, 1 - s->cur);
     const int64_t n = s->nstep;
-    if ((st = timed(s, CW_K_VELOCITY, [&] { return launch_velocity_basic(a, s->stream); })) != CW_OK) return st;
-    if (s->ninject && (st = timed(s, CW_K_INJECT, [&] {
-          return launch_inject(s->d_inject, s->ninject, 0, n, a, s->stream); })) != CW_OK) return st;
-    if ((st = timed(s, CW_K_STRESS, [&] { return launch_stress_basic(a, s->stream); })) != CW_OK) return st;
-    if (s->ninject && (st = timed(s, CW_K_INJECT, [&] {
-          return launch_inject(s->d_inject, s->ninject, 1, n, a, s->stream); })) != CW_OK) return st;
+    if (fused) {
+      f.nr = s->nr; f.nt = s->nt; f.nz = s->nz; f.npr = s->npr; f.npz = s->npz; f.nzs = nzs_of(s);
+      f.dt = a.dt; f.inv_dr = a.inv_dr; f.inv_dz = a.inv_dz; f.inv_dth = a.inv_dth;
+      f.n = s->n;
+      f.slab_r = (size_t)s->npr * s->nt * s->nz;
+      f.slab_z = (size_t)s->nr * s->nt * nzs_of(s);
+      f.in = s->fields[s->cur][0];
+      f.out = s->fields[1 - s->cur][0];
+      f.med = s->d_rho;
+      f.psi_r_in = s->psi_r[s->psi_cur][0]; f.psi_r_out = s->psi_r[1 - s->psi_cur][0];
+      f.psi_z_in = s->psi_z[s->psi_cur][0]; f.psi_z_out = s->psi_z[1 - s->psi_cur][0];
+      f.inv_rc = s->d_inv_rc; f.inv_rf = s->d_inv_rf; f.tab_r = s->d_tab_r; f.tab_z = s->d_tab_z;
+      f.ninj = 0;
+      for (int e = 0; e < s->ninject; e++) {
+        const Inject &in = s->inject_host[e];
+        if (n >= in.nsamp) continue;
+        InjectStep &o = f.inj[f.ninj++];
+        o.field = in.field; o.i = in.i; o.j = in.j; o.k = in.k; o.phase = in.phase;
+        o.amp = in.scale * s->inject_amp[e][n];
+      }
+      if ((st = timed(s, CW_K_FUSED, [&] { return launch_fused(f, s->stream); })) != CW_OK) return st;
+      s->psi_cur = 1 - s->psi_cur;
+    } else {
+      if ((st = timed(s, CW_K_VELOCITY, [&] { return launch_velocity_basic(a, s->stream); })) != CW_OK) return st;
+      if (s->ninject && (st = timed(s, CW_K_INJECT, [&] {
+            return launch_inject(s->d_inject, s->ninject, 0, n, a, s->stream); })) != CW_OK) return st;
+      if ((st = timed(s, CW_K_STRESS, [&] { return launch_stress_basic(a, s->stream); })) != CW_OK) return st;
+      if (s->ninject && (st = timed(s, CW_K_INJECT, [&] {
+            return launch_inject(s->d_inject, s->ninject, 1, n, a, s->stream); })) != CW_OK) return st;
+    }
     if (nrec && (st = timed(s, CW_K_RECORD, [&] {
           return launch_record(s->d_rec, nrec, n, s->trace_cap, a, s->d_traces, s->stream); })) != CW_OK)
       return st;
@@ -633,6 +681,14 @@ cw_status cw_reset(cw_sim *s)
   if (!s->bound) return fail(CW_ERR_STATE, "cw_bind first");
   HIPCHK(hipSetDevice(s->device));
   return zero_state(s);
+}
+
+cw_status cw_set_path(cw_sim *s, int32_t path)
+{
+  if (!s) return fail(CW_ERR_ARG, "null simulation");
+  if (path < CW_PATH_AUTO || path > CW_PATH_FUSED) return fail(CW_ERR_ARG, "bad path %d", path);
+  s->path = path;
+  return CW_OK;
 }
 
 cw_status cw_profile(cw_sim *s, int32_t enable)

@@ -54,7 +54,60 @@ struct Receiver {
   int kind, field, i, j, k;
 };
 
+// Workgroups are dispatched to the 8 XCDs (each with its own L2) in
+// round-robin order.  This remaps the dispatch index b of a grid of G
+// workgroups so that each XCD receives one contiguous range of logical
+// tiles: neighbouring tiles, which share halo cache lines, then run on the
+// same XCD and share its L2.
+__device__ __forceinline__ int xcd_tile_remap(int b, int G)
+{
+  const int q8 = G >> 3, r8 = G & 7, xcd = b & 7, idx = b >> 3;
+  return xcd < r8 ? xcd * (q8 + 1) + idx : r8 * (q8 + 1) + (xcd - r8) * q8 + idx;
+}
+// Measured on MI355X: for these streaming kernels the plain dispatch order
+// (all XCDs sweeping one compact address range together) is faster than the
+// per-XCD contiguous ranges, although the latter fetches slightly fewer
+// bytes; the remap is therefore off unless CW_XCD_REMAP is set.
+#ifndef CW_XCD_REMAP
+#define CW_XCD_REMAP 0
+#endif
+__device__ __forceinline__ int xcd_tile(int b, int G) { return CW_XCD_REMAP ? xcd_tile_remap(b, G) : b; }
+
+// One injection of the current step, as the fused kernel applies it.
+struct InjectStep {
+  int field, i, j, k, phase;
+  float amp;                // scale * dt * w[n] / V for this step
+};
+constexpr int kMaxFusedInject = 12;
+
+// Arguments of the fused step.  Arrays of one kind are contiguous in the
+// workspace, so each kind is one base pointer and a stride: the 9 fields
+// (Field order, stride n), the medium (rho, lambda, mu, stride n), the 12
+// radial and 6 z layer memory arrays (stride slab_r / slab_z), each state
+// and layer memory at level n (in) and n+1 (out).  Few pointers keep the
+// kernel's arguments in scalar registers.
+struct FusedArgs {
+  int nr, nt, nz, npr, npz, nzs;
+  float dt, inv_dr, inv_dz, inv_dth;
+  size_t n, slab_r, slab_z;
+  const float *in;
+  float *out;
+  const float *med;
+  const float *psi_r_in;
+  float *psi_r_out;
+  const float *psi_z_in;
+  float *psi_z_out;
+  const float *inv_rc, *inv_rf, *tab_r, *tab_z;
+  int own_rows, ntile_z;
+  int ninj;
+  InjectStep inj[kMaxFusedInject];
+};
+
 // Launchers (step kernels), enqueued on `stream`.
+int fused_tiles(int nt, int nz, int *own_rows, int *ntile_z);
+size_t fused_lds_bytes(int nr);                 // dynamic LDS of the fused step
+constexpr int kMaxFusedRings = 2048;            // nr limit of the fused step (LDS tables)
+hipError_t launch_fused(const FusedArgs &f, hipStream_t stream);
 hipError_t launch_velocity_basic(const StepArgs &a, hipStream_t stream);
 hipError_t launch_stress_basic(const StepArgs &a, hipStream_t stream);
 hipError_t launch_inject(const Inject *dev_list, int ninj, int phase, int64_t step,

@@ -32,11 +32,19 @@ __device__ __forceinline__ size_t at(const StepArgs &a, int i, int j, int k)
   return ((size_t)i * a.nt + j) * a.nz + k;
 }
 
+// Reciprocal: the hardware v_rcp_f32 (1 ulp) by default, IEEE division
+// when CW_IEEE_DIV is set.
+#ifdef CW_IEEE_DIV
+__device__ __forceinline__ float rcp(float x) { return 1.0f / x; }
+#else
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+#endif
+
 // Harmonic mean of four moduli: 4 / (1/a + 1/b + 1/c + 1/d).  A zero
 // argument makes its reciprocal +inf and the mean exactly zero.
 __device__ __forceinline__ float hm4(float p, float q, float r, float s)
 {
-  return 4.0f / (1.0f / p + 1.0f / q + 1.0f / r + 1.0f / s);
+  return 4.0f * rcp(rcp(p) + rcp(q) + rcp(r) + rcp(s));
 }
 
 // z-slab row of depth index k, or -1 outside the slabs.
@@ -57,10 +65,13 @@ __device__ __forceinline__ float cpml(float *psi, size_t p, float ca, float cb, 
   return X + v;
 }
 
-__global__ void __launch_bounds__(256) k_velocity_basic(StepArgs a)
+__global__ void __launch_bounds__(256) k_velocity_basic(StepArgs a, int nbx)
 {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  const int j = blockIdx.y, i = blockIdx.z;
+  // 1-D grid remapped per XCD; logical tile = (depth chunk, row, ring)
+  const int t = xcd_tile(blockIdx.x, gridDim.x);
+  const int bx = t % nbx, ij = t / nbx;
+  const int k = bx * 256 + threadIdx.x;
+  const int j = ij % a.nt, i = ij / a.nt;
   if (k >= a.nz) return;
   const int jm = j == 0 ? a.nt - 1 : j - 1;
   const int jp = j == a.nt - 1 ? 0 : j + 1;
@@ -113,19 +124,22 @@ __global__ void __launch_bounds__(256) k_velocity_basic(StepArgs a)
   const int k1 = k + 1 < a.nz ? k + 1 : a.nz - 1;
   const size_t p = at(a, i, j, k);
   const float rho0 = a.rho[p];
-  const float b_r = 2.0f / (rho0 + a.rho[at(a, i1, j, k)]);
-  const float b_t = 2.0f / (rho0 + a.rho[at(a, i, jp, k)]);
-  const float b_z = 2.0f / (rho0 + a.rho[at(a, i, j, k1)]);
+  const float b_r = 2.0f * rcp(rho0 + a.rho[at(a, i1, j, k)]);
+  const float b_t = 2.0f * rcp(rho0 + a.rho[at(a, i, jp, k)]);
+  const float b_z = 2.0f * rcp(rho0 + a.rho[at(a, i, j, k1)]);
 
   a.out[VR][p] = a.in[VR][p] + a.dt * b_r * (r_dr + r_b + r_dz);
   a.out[VT][p] = a.in[VT][p] + a.dt * b_t * (t_dr + t_b + t_dz);
   a.out[VZ][p] = a.in[VZ][p] + a.dt * b_z * (z_dr + z_b + z_dz);
 }
 
-__global__ void __launch_bounds__(256) k_stress_basic(StepArgs a)
+__global__ void __launch_bounds__(256) k_stress_basic(StepArgs a, int nbx)
 {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  const int j = blockIdx.y, i = blockIdx.z;
+  // 1-D grid remapped per XCD; logical tile = (depth chunk, row, ring)
+  const int t = xcd_tile(blockIdx.x, gridDim.x);
+  const int bx = t % nbx, ij = t / nbx;
+  const int k = bx * 256 + threadIdx.x;
+  const int j = ij % a.nt, i = ij / a.nt;
   if (k >= a.nz) return;
   const int jm = j == 0 ? a.nt - 1 : j - 1;
   const int jp = j == a.nt - 1 ? 0 : j + 1;
@@ -308,15 +322,19 @@ __global__ void __launch_bounds__(256) k_energy_final(const double *partials, in
 
 hipError_t launch_velocity_basic(const StepArgs &a, hipStream_t stream)
 {
-  dim3 grid((a.nz + 255) / 256, a.nt, a.nr);
-  hipLaunchKernelGGL(k_velocity_basic, grid, dim3(256), 0, stream, a);
+  const int nbx = (a.nz + 255) / 256;
+  const long g = (long)nbx * a.nt * a.nr;
+  if (g > 0x7fffffff) return hipErrorInvalidConfiguration;
+  hipLaunchKernelGGL(k_velocity_basic, dim3((unsigned)g), dim3(256), 0, stream, a, nbx);
   return hipGetLastError();
 }
 
 hipError_t launch_stress_basic(const StepArgs &a, hipStream_t stream)
 {
-  dim3 grid((a.nz + 255) / 256, a.nt, a.nr);
-  hipLaunchKernelGGL(k_stress_basic, grid, dim3(256), 0, stream, a);
+  const int nbx = (a.nz + 255) / 256;
+  const long g = (long)nbx * a.nt * a.nr;
+  if (g > 0x7fffffff) return hipErrorInvalidConfiguration;
+  hipLaunchKernelGGL(k_stress_basic, dim3((unsigned)g), dim3(256), 0, stream, a, nbx);
   return hipGetLastError();
 }
 

@@ -30,7 +30,10 @@ EXPORTS = ("cw_create", "cw_set_material", "cw_set_material_rz", "cw_set_pml", "
            "cw_set_dt", "cw_add_source", "cw_add_receiver", "cw_set_trace_capacity",
            "cw_workspace_bytes", "cw_bind", "cw_step", "cw_sync", "cw_get_traces",
            "cw_get_field", "cw_set_field", "cw_energy", "cw_reset", "cw_steps_done",
-           "cw_ricker", "cw_destroy", "cw_last_error", "cw_profile", "cw_profile_read")
+           "cw_ricker", "cw_destroy", "cw_last_error", "cw_profile", "cw_profile_read",
+           "cw_set_path")
+
+PATHS = {"auto": 0, "two-pass": 1, "fused": 2}
 
 KERNELS = {"velocity": 0, "stress": 1, "fused": 2, "inject": 3, "record": 4}
 
@@ -83,6 +86,7 @@ def load():
         "cw_steps_done": [P, ctypes.POINTER(I64)],
         "cw_ricker": [D, DP, I64, DP],
         "cw_profile": [P, I32],
+        "cw_set_path": [P, I32],
         "cw_profile_read": [P, I32, DP, ctypes.POINTER(I64)],
     }
     for name, args in sig.items():
@@ -237,6 +241,10 @@ class Sim:
 
     def reset(self):
         _check(self.lib.cw_reset(self.h))
+
+    def set_path(self, path: str):
+        """Kernel path of step(): "auto", "two-pass" or "fused"."""
+        _check(self.lib.cw_set_path(self.h, PATHS[path]))
 
     def profile(self, enable: bool = True):
         """Start (or stop and clear) per-launch HIP-event timing of the step kernels."""

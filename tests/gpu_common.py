@@ -29,6 +29,7 @@ class Scenario:
     sources: List[tuple] = field(default_factory=list)     # (kind, i, j, k, amplitude)
     receivers: List[tuple] = field(default_factory=list)   # (kind, i, j, k, field)
     initial: Optional[dict] = None                          # field -> array
+    path: str = "auto"                                      # kernel path of cw_step
 
 
 def announce(msg: str):
@@ -54,6 +55,7 @@ def run_gpu(sc: Scenario, keep_sim: bool = False):
     for (kind, i, j, k, fld) in sc.receivers:
         s.add_receiver(kind, i, j, k, fld)
     s.set_trace_capacity(sc.steps)
+    s.set_path(sc.path)
     s.bind()
     if sc.initial:
         for name, a in sc.initial.items():

@@ -21,11 +21,16 @@ TRACE_TOL = 1e-5
 FIELD_TOL = 1e-5
 
 
-def test_parity_case_traces_and_fields():
+PATHS = ["fused", "two-pass"]
+
+
+@pytest.mark.parametrize("path", PATHS)
+def test_parity_case_traces_and_fields(path):
     """48 x 32 x 192 cased well (5 mm), 300 steps, 10-cell layer, 20 kHz axis
     source, 16 axis receivers, jittered rock."""
-    announce("parity case 48x32x192, 300 steps")
+    announce("parity case 48x32x192, 300 steps, %s" % path)
     sc = parity_scenario()
+    sc.path = path
     tr_g, f_g = run_gpu(sc)
     tr_o, f_o = run_oracle(sc)
     assert np.abs(tr_o).max() > 0
@@ -60,12 +65,13 @@ CASES = {
 }
 
 
+@pytest.mark.parametrize("path", PATHS)
 @pytest.mark.parametrize("name", sorted(CASES))
-def test_parity_edge_cases(name):
+def test_parity_edge_cases(name, path):
     c = CASES[name]
     shape = c["shape"]
     h = 5e-3
-    announce("edge case %s %s" % (name, shape))
+    announce("edge case %s %s %s" % (name, shape, path))
     med = _cased(shape, h, z_top=shape[2] * h / 2, ramp=c.get("ramp", 0.0))
     recs = [("pressure", 0, -1, k, None) for k in range(3, shape[2] - 3, max(1, shape[2] // 8))]
     # point samples of every field near the first source (and one in the casing),
@@ -75,7 +81,7 @@ def test_parity_edge_cases(name):
     recs += [("field", min(21, shape[0] - 1), 1 % shape[1], ks, f) for f in FIELDS]
     recs += [("field", 1, -1, ks, "vr")]
     sc = Scenario(shape=shape, h=(h, h), medium=med, steps=c["steps"], npml=c["npml"],
-                  sources=c["sources"], receivers=recs)
+                  sources=c["sources"], receivers=recs, path=path)
     tr_g, f_g = run_gpu(sc)
     tr_o, f_o = run_oracle(sc)
     fe = field_errors(f_g, f_o)
@@ -96,12 +102,13 @@ def test_parity_edge_cases(name):
         assert e <= TRACE_TOL, (g, e)
 
 
-def test_theta_invariance_bitwise_gpu():
+@pytest.mark.parametrize("path", PATHS)
+def test_theta_invariance_bitwise_gpu(path):
     """theta-invariant medium + ring sources: every field identical along theta, bitwise."""
     shape = (34, 16, 96)
     med = inputs.cased_well(*shape, 5e-3, 5e-3, z_top=0.25, ramp=0.1)
     sc = Scenario(shape=shape, h=(5e-3, 5e-3), medium=med, steps=200, npml=(6, 6),
-                  sources=[("volume", 0, -1, 30, 1.0), ("torsion", 21, -1, 60, 1.0)])
+                  sources=[("volume", 0, -1, 30, 1.0), ("torsion", 21, -1, 60, 1.0)], path=path)
     _, f = run_gpu(sc)
     for n in FIELDS:
         a = f[n]
@@ -109,11 +116,12 @@ def test_theta_invariance_bitwise_gpu():
     assert np.abs(f["vr"]).max() > 0 and np.abs(f["vt"]).max() > 0
 
 
-def test_decoupling_bitwise_gpu():
+@pytest.mark.parametrize("path", PATHS)
+def test_decoupling_bitwise_gpu(path):
     shape = (34, 8, 96)
     med = inputs.cased_well(*shape, 5e-3, 5e-3, z_top=0.25)
     sc = Scenario(shape=shape, h=(5e-3, 5e-3), medium=med, steps=150, npml=(6, 6),
-                  sources=[("volume", 0, -1, 30, 1.0)])
+                  sources=[("volume", 0, -1, 30, 1.0)], path=path)
     _, f = run_gpu(sc)
     for n in ("vt", "srt", "stz"):
         assert not np.any(f[n]), n
@@ -145,14 +153,15 @@ def _random_state(shape, med, seed):
     return {k: v.astype(np.float32).astype(np.float64) for k, v in init.items()}
 
 
-def test_energy_conservation_gpu():
+@pytest.mark.parametrize("path", PATHS)
+def test_energy_conservation_gpu(path):
     """Layer off, no source, random heterogeneous medium with a fluid core:
     the float64 energy of the float32 state drifts only at float32 rounding
     level and tracks the oracle's energy."""
     shape = (16, 12, 70)
     med = inputs.random_medium(*shape, seed=3)
     init = _random_state(shape, med, seed=8)
-    sc = Scenario(shape=shape, h=(0.01, 0.01), medium=med, steps=1, initial=init)
+    sc = Scenario(shape=shape, h=(0.01, 0.01), medium=med, steps=1, initial=init, path=path)
     _, _, s = run_gpu(sc, keep_sim=True)
     E = [s.energy()]
     for _ in range(40):
@@ -173,22 +182,25 @@ def test_energy_conservation_gpu():
     assert abs(E[0] / Eo[0] - 1) < 1e-6
 
 
-def test_reciprocity_gpu():
+@pytest.mark.parametrize("path", PATHS)
+def test_reciprocity_gpu(path):
     shape = (30, 4, 60)
     med = inputs.cased_well(*shape, 5e-3, 5e-3, z_top=0.15, rock_jitter=0.02)
     out = []
     for ka, kb in ((15, 40), (40, 15)):
         sc = Scenario(shape=shape, h=(5e-3, 5e-3), medium=med, steps=300, f0=30e3,
                       sources=[("volume", 0, -1, ka, 1.0)],
-                      receivers=[("pressure", 0, -1, kb, None)])
+                      receivers=[("pressure", 0, -1, kb, None)], path=path)
         out.append(run_gpu(sc)[0][0])
     assert np.abs(out[0]).max() > 0
     assert rel_l2(out[0], out[1]) < 1e-5
 
 
-def test_deterministic_bitwise():
+@pytest.mark.parametrize("path", PATHS)
+def test_deterministic_bitwise(path):
     sc = parity_scenario()
     sc.steps = 60
+    sc.path = path
     a, fa = run_gpu(sc)
     b, fb = run_gpu(sc)
     assert np.array_equal(a, b)
@@ -219,3 +231,35 @@ def test_api_state_after_bind():
     s.step(2)
     assert s.steps_done == 2
     s.close()
+
+
+def test_fused_matches_two_pass():
+    """The fused and two-pass paths compute the same scheme: on the parity
+    case they agree to float32 rounding."""
+    sc = parity_scenario()
+    sc.steps = 150
+    sc.path = "fused"
+    a, fa = run_gpu(sc)
+    sc.path = "two-pass"
+    b, fb = run_gpu(sc)
+    assert rel_l2(a, b) < 1e-6
+    fe = field_errors({k: v.astype(np.float64) for k, v in fa.items()},
+                      {k: v.astype(np.float64) for k, v in fb.items()})
+    assert max(fe.values()) < 1e-6, fe
+
+
+def test_many_sources_fall_back_to_two_pass():
+    """More injections than the fused step takes: auto uses the two-pass
+    kernels, an explicit fused request is refused."""
+    shape = (20, 4, 40)
+    med = inputs.cased_well(*shape, 5e-3, 5e-3, z_top=0.1)
+    srcs = [("volume", 0, -1, 5 + 2 * q, 1.0) for q in range(5)]        # 15 injections
+    sc = Scenario(shape=shape, h=(5e-3, 5e-3), medium=med, steps=40, sources=srcs,
+                  receivers=[("pressure", 0, -1, 30, None)])
+    tr_g, _ = run_gpu(sc)
+    tr_o, _ = run_oracle(sc)
+    assert rel_l2(tr_g, tr_o) < TRACE_TOL
+    sc.path = "fused"
+    with pytest.raises(cwell.CwellError) as e:
+        run_gpu(sc)
+    assert e.value.status == -2
