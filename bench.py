@@ -32,7 +32,7 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes(kernel: str, w, n_r: int, n_z: int) -> float:
+def algorithmic_bytes(kernel: str, w, n_r: int, n_z: int, fb: int = 4) -> float:
     """Algorithmic HBM bytes of one launch of `kernel` over workload w.
 
     One cell-update reads the 9 fields and the 3 moduli (rho, lambda, mu) and
@@ -41,14 +41,16 @@ def algorithmic_bytes(kernel: str, w, n_r: int, n_z: int) -> float:
     cell (48 B).  The separate velocity pass moves 6 stresses + 3 velocities
     in, 3 velocities out and rho (52 B, 6 radial / 3 z variables); the
     separate stress pass 3 velocities + 6 stresses in, 6 out, lambda and mu
-    (68 B, the other 6 radial / 3 z variables)."""
+    (68 B, the other 6 radial / 3 z variables).  With fb-byte field storage
+    the field terms scale by fb/4 (the moduli and layer memory stay
+    float32)."""
     n = w.cells
     if kernel == "fused":
-        return 84.0 * n + 96.0 * n_r + 48.0 * n_z
+        return (18 * fb + 12.0) * n + 96.0 * n_r + 48.0 * n_z
     if kernel == "velocity":
-        return 52.0 * n + 48.0 * n_r + 24.0 * n_z
+        return (12 * fb + 4.0) * n + 48.0 * n_r + 24.0 * n_z
     if kernel == "stress":
-        return 68.0 * n + 48.0 * n_r + 24.0 * n_z
+        return (15 * fb + 8.0) * n + 48.0 * n_r + 24.0 * n_z
     raise ValueError(kernel)
 
 
@@ -114,6 +116,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--path", choices=("auto", "fused", "two-pass"), default="auto",
                     help="kernel path of the step")
+    ap.add_argument("--storage", choices=("f32", "f16", "bf16"), default="f32",
+                    help="field storage (arithmetic is float32 in every case)")
     ap.add_argument("--copy-gib", type=float, default=0.0,
                     help="after the run, copy this many GiB device-to-device once (a known-size "
                          "reference dispatch for hardware byte counters)")
@@ -147,6 +151,7 @@ def main():
         s.add_receiver("pressure", 0, -1, k)
     s.set_trace_capacity(total)
     s.set_path(args.path)
+    s.set_storage(args.storage)
     log("binding %.2f GB workspace" % (s.workspace_bytes() / 1e9))
     s.bind("cuda:0")
     log("warm-up %d steps" % args.warmup)
@@ -171,7 +176,8 @@ def main():
     ms, launches = times[dom]
     avg_s = ms / 1e3 / max(launches, 1)
     n_r, n_z = w.layer_cells
-    alg = algorithmic_bytes(dom, w, n_r, n_z)
+    fb = 4 if args.storage == "f32" else 2
+    alg = algorithmic_bytes(dom, w, n_r, n_z, fb)
     achieved = alg / avg_s / 1e9
     traffic = measured_traffic(dom, w.name)
     out = {
@@ -186,6 +192,7 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
+        "storage": args.storage,
         "data": "synthetic",
         "config": {"workload": w.name, "cells": w.cells, "grid": [w.nr, w.nt, w.nz],
                    "cell_m": w.dr, "layer_cells": w.npml, "receivers": len(w.rec_k),

@@ -154,11 +154,13 @@ cw_status cw_sync(cw_sim *s);
    Synchronous. */
 cw_status cw_get_traces(cw_sim *s, double *out, int64_t cap, int64_t *nsteps_done);
 
-/* Copy one field of the current state to host float32 [nr][ntheta][nz].
-   Synchronous. */
+/* Copy one field of the current state to host float32 [nr][ntheta][nz]
+   (16-bit storage is converted, scale applied).  Synchronous. */
 cw_status cw_get_field(cw_sim *s, int32_t field, float *host_out);
 
-/* Overwrite one field of the current state (initial conditions, restart). */
+/* Overwrite one field of the current state (initial conditions, restart);
+   with float16 storage the field's scale is set from the input's largest
+   magnitude.  CW_ERR_NONFINITE for NaN or Inf input. */
 cw_status cw_set_field(cw_sim *s, int32_t field, const float *host_in);
 
 /* Energy E^{n+1/2} in float64 after the last step: kinetic energy of
@@ -173,6 +175,17 @@ cw_status cw_reset(cw_sim *s);
 
 /* Number of time steps done. */
 cw_status cw_steps_done(const cw_sim *s, int64_t *n);
+
+/* Storage of the 9 fields: float32 (default), float16 or bfloat16.  All
+   arithmetic is float32 whatever the storage; the medium, the layer memory
+   and the traces keep their own precision (float32, float32, float64).
+   float16 values carry a power-of-two scale per field: after every step
+   the device sets the next scale from the largest magnitude just written,
+   so that the stored maxima sit in [2^10, 2^11) (no host round trip).
+   bfloat16 has float32's exponent range and needs no scale.  Rounding is
+   to nearest even.  Call before cw_bind. */
+enum { CW_STORE_F32 = 0, CW_STORE_F16, CW_STORE_BF16 };
+cw_status cw_set_storage(cw_sim *s, int32_t storage);
 
 /* Kernel path of cw_step.  CW_PATH_TWO_PASS: a velocity launch and a
    stress launch per step (plus source launches), one thread per cell, any

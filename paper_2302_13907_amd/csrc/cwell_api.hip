@@ -22,6 +22,10 @@ constexpr int kEnergyBlocks = 1024;
 #define CW_AUTO_FUSED 0
 #endif
 constexpr bool kAutoFused = CW_AUTO_FUSED;    // what CW_PATH_AUTO picks when the fused step applies
+#ifndef CW_USE_VEC
+#define CW_USE_VEC 1
+#endif
+constexpr bool kUseVec = CW_USE_VEC;          // two-pass kernels: 4 depth cells per thread when nz % 4 == 0
 
 thread_local std::string g_err;
 
@@ -83,6 +87,9 @@ struct cw_sim {
   float *psi_z[2][NPSI_Z] = {};
   int psi_cur = 0;
   int path = CW_PATH_AUTO;
+  int storage = ST_F32;
+  float *d_scl = nullptr;       // [3][NF]: scale of buffer 0, buffer 1, next write
+  unsigned *d_maxabs = nullptr; // [NF][kMaxSlots]
   Inject *d_inject = nullptr;
   int ninject = 0;
   std::vector<Inject> inject_host;
@@ -108,6 +115,8 @@ namespace {
 
 int nzs_of(const cw_sim *s) { return s->npz > 0 ? 2 * s->npz + 1 : 0; }
 
+size_t field_bytes(const cw_sim *s) { return s->storage == ST_F32 ? 4 : 2; }
+
 // Number of float32 amplitude samples over all injections.
 size_t amp_floats(const cw_sim *s)
 {
@@ -128,7 +137,7 @@ int inject_count(const cw_sim *s)
 }
 
 struct Layout {
-  size_t fields, material, metric, tabr, tabz, psir, psiz, inject, amp, rec, traces, energy, total;
+  size_t fields, material, metric, tabr, tabz, psir, psiz, inject, amp, rec, traces, energy, scales, total;
 };
 
 Layout layout(const cw_sim *s)
@@ -136,7 +145,7 @@ Layout layout(const cw_sim *s)
   Layout L{};
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off += align256(bytes); return o; };
-  L.fields = take(2 * NF * s->n * sizeof(float));
+  L.fields = take(2 * NF * s->n * field_bytes(s));
   L.material = take(3 * s->n * sizeof(float));
   L.metric = take(2 * (size_t)s->nr * sizeof(float));
   L.tabr = take(NTAB_R * (size_t)s->nr * sizeof(float));
@@ -148,6 +157,7 @@ Layout layout(const cw_sim *s)
   L.rec = take(s->receivers.size() * sizeof(Receiver));
   L.traces = take(s->receivers.size() * (size_t)s->trace_cap * sizeof(double));
   L.energy = take((kEnergyBlocks + 1) * sizeof(double));
+  L.scales = take(3 * NF * sizeof(float) + NF * kMaxSlots * sizeof(unsigned));
   L.total = off;
   return L;
 }
@@ -251,6 +261,9 @@ StepArgs step_args(const cw_sim *s, int in, int out)
   for (int q = 0; q < NPSI_R; q++) a.psi_r[q] = s->psi_r[s->psi_cur][q];
   for (int q = 0; q < NPSI_Z; q++) a.psi_z[q] = s->psi_z[s->psi_cur][q];
   a.tab_r = s->d_tab_r; a.tab_z = s->d_tab_z;
+  a.scl_in = s->d_scl + in * NF;
+  a.scl_out = s->d_scl + 2 * NF;
+  a.maxabs = s->d_maxabs;
   return a;
 }
 
@@ -285,7 +298,12 @@ cw_status timed(cw_sim *s, int kernel, F &&fn)
 cw_status zero_state(cw_sim *s)
 {
   const Layout L = layout(s);
-  HIPCHK(hipMemsetAsync(s->ws + L.fields, 0, 2 * NF * s->n * sizeof(float), s->stream));
+  HIPCHK(hipMemsetAsync(s->ws + L.fields, 0, 2 * NF * s->n * field_bytes(s), s->stream));
+  // every scale 1, no maxima yet (pageable source: the caller synchronizes)
+  static const float ones[3 * NF] = {1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1,
+                                     1, 1, 1, 1, 1, 1, 1, 1, 1};
+  HIPCHK(hipMemcpyAsync(s->d_scl, ones, sizeof ones, hipMemcpyHostToDevice, s->stream));
+  HIPCHK(hipMemsetAsync(s->d_maxabs, 0, NF * kMaxSlots * sizeof(unsigned), s->stream));
   const size_t psir = 2 * (size_t)NPSI_R * s->npr * s->nt * s->nz * sizeof(float);
   const size_t psiz = 2 * (size_t)NPSI_Z * s->nr * s->nt * nzs_of(s) * sizeof(float);
   if (psir) HIPCHK(hipMemsetAsync(s->ws + L.psir, 0, psir, s->stream));
@@ -470,7 +488,9 @@ cw_status cw_bind(cw_sim *s, void *workspace, uint64_t bytes, void *stream)
   char *w = s->ws;
   for (int b = 0; b < 2; b++)
     for (int q = 0; q < NF; q++)
-      s->fields[b][q] = (float *)(w + L.fields) + ((size_t)b * NF + q) * s->n;
+      s->fields[b][q] = (float *)(w + L.fields + ((size_t)b * NF + q) * s->n * field_bytes(s));
+  s->d_scl = (float *)(w + L.scales);
+  s->d_maxabs = (unsigned *)(s->d_scl + 3 * NF);
   s->d_rho = (float *)(w + L.material);
   s->d_lam = s->d_rho + s->n;
   s->d_mu = s->d_lam + s->n;
@@ -566,14 +586,16 @@ cw_status cw_step(cw_sim *s, int64_t nsteps)
   const int nrec = (int)s->receivers.size();
   // the fused step addresses a ring with 32-bit byte offsets
   const bool fits = s->ninject <= kMaxFusedInject && s->nr <= kMaxFusedRings &&
-                    (uint64_t)s->nt * s->nz * 4 < (1ull << 32);
+                    (uint64_t)s->nt * s->nz * 4 < (1ull << 32) && s->storage == ST_F32;
   const bool fused = s->path == CW_PATH_FUSED || (s->path == CW_PATH_AUTO && fits && kAutoFused);
 
   if (s->path == CW_PATH_FUSED && !fits)
-    return fail(CW_ERR_RANGE, "the fused step takes at most %d injections and %d rings (have %d, %d)",
-                kMaxFusedInject, kMaxFusedRings, s->ninject, s->nr);
+    return fail(CW_ERR_RANGE, "the fused step takes float32 storage, at most %d injections and %d rings "
+                "(have storage %d, %d injections, %d rings)", kMaxFusedInject, kMaxFusedRings, s->storage,
+                s->ninject, s->nr);
   FusedArgs f{};
   if (fused) fused_tiles(s->nt, s->nz, &f.own_rows, &f.ntile_z);
+  const bool vec = kUseVec && vec_applies(s->nz);
   for (int64_t t = 0; t < nsteps; t++) {
     const StepArgs a = step_args(s, s->cur, 1 - s->cur);
     const int64_t n = s->nstep;
@@ -600,16 +622,24 @@ cw_status cw_step(cw_sim *s, int64_t nsteps)
       if ((st = timed(s, CW_K_FUSED, [&] { return launch_fused(f, s->stream); })) != CW_OK) return st;
       s->psi_cur = 1 - s->psi_cur;
     } else {
-      if ((st = timed(s, CW_K_VELOCITY, [&] { return launch_velocity_basic(a, s->stream); })) != CW_OK) return st;
+      if ((st = timed(s, CW_K_VELOCITY, [&] {
+            return vec ? launch_velocity_vec(a, s->storage, s->stream) : launch_velocity_basic(a, s->storage, s->stream);
+          })) != CW_OK)
+        return st;
       if (s->ninject && (st = timed(s, CW_K_INJECT, [&] {
-            return launch_inject(s->d_inject, s->ninject, 0, n, a, s->stream); })) != CW_OK) return st;
-      if ((st = timed(s, CW_K_STRESS, [&] { return launch_stress_basic(a, s->stream); })) != CW_OK) return st;
+            return launch_inject(s->d_inject, s->ninject, 0, n, a, s->storage, s->stream); })) != CW_OK) return st;
+      if ((st = timed(s, CW_K_STRESS, [&] {
+            return vec ? launch_stress_vec(a, s->storage, s->stream) : launch_stress_basic(a, s->storage, s->stream);
+          })) != CW_OK)
+        return st;
       if (s->ninject && (st = timed(s, CW_K_INJECT, [&] {
-            return launch_inject(s->d_inject, s->ninject, 1, n, a, s->stream); })) != CW_OK) return st;
+            return launch_inject(s->d_inject, s->ninject, 1, n, a, s->storage, s->stream); })) != CW_OK) return st;
     }
     if (nrec && (st = timed(s, CW_K_RECORD, [&] {
-          return launch_record(s->d_rec, nrec, n, s->trace_cap, a, s->d_traces, s->stream); })) != CW_OK)
+          return launch_record(s->d_rec, nrec, n, s->trace_cap, a, s->storage, s->d_traces, s->stream); })) != CW_OK)
       return st;
+    if (s->storage == ST_F16)
+      HIPCHK(launch_rescale(s->d_scl + (1 - s->cur) * NF, s->d_scl + 2 * NF, s->d_maxabs, s->stream));
     s->cur = 1 - s->cur;
     s->nstep++;
   }
@@ -638,14 +668,54 @@ cw_status cw_get_traces(cw_sim *s, double *out, int64_t cap, int64_t *nsteps_don
   return CW_OK;
 }
 
+// float16 scale for values up to maxabs: 2^(e - target), max = f 2^e
+static float f16_scale(double maxabs)
+{
+  if (!(maxabs > 0) || !std::isfinite(maxabs)) return 1.0f;
+  int e;
+  std::frexp(maxabs, &e);
+  return std::ldexp(1.0f, e - kF16TargetExp);
+}
+
+static float bf16_to_float(uint16_t h)
+{
+  const uint32_t u = (uint32_t)h << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return f;
+}
+
+static uint16_t float_to_bf16(float f)
+{
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
 cw_status cw_get_field(cw_sim *s, int32_t field, float *host_out)
 {
   if (!s || !host_out) return fail(CW_ERR_ARG, "null argument");
   if (field < 0 || field >= CW_NFIELD) return fail(CW_ERR_ARG, "bad field %d", field);
   if (!s->bound) return fail(CW_ERR_STATE, "cw_bind first");
   HIPCHK(hipSetDevice(s->device));
-  HIPCHK(hipMemcpyAsync(host_out, s->fields[s->cur][field], s->n * sizeof(float), hipMemcpyDeviceToHost, s->stream));
+  if (s->storage == ST_F32) {
+    HIPCHK(hipMemcpyAsync(host_out, s->fields[s->cur][field], s->n * sizeof(float), hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    return CW_OK;
+  }
+  std::vector<uint16_t> raw;
+  try { raw.resize(s->n); } catch (...) { return fail(CW_ERR_NOMEM, "out of host memory"); }
+  float scl = 1.0f;
+  HIPCHK(hipMemcpyAsync(raw.data(), s->fields[s->cur][field], s->n * 2, hipMemcpyDeviceToHost, s->stream));
+  HIPCHK(hipMemcpyAsync(&scl, s->d_scl + s->cur * NF + field, sizeof(float), hipMemcpyDeviceToHost, s->stream));
   HIPCHK(hipStreamSynchronize(s->stream));
+  if (s->storage == ST_F16) {
+    const _Float16 *h = reinterpret_cast<const _Float16 *>(raw.data());
+    for (size_t p = 0; p < s->n; p++) host_out[p] = (float)h[p] * scl;
+  } else {
+    for (size_t p = 0; p < s->n; p++) host_out[p] = bf16_to_float(raw[p]);
+  }
   return CW_OK;
 }
 
@@ -655,7 +725,29 @@ cw_status cw_set_field(cw_sim *s, int32_t field, const float *host_in)
   if (field < 0 || field >= CW_NFIELD) return fail(CW_ERR_ARG, "bad field %d", field);
   if (!s->bound) return fail(CW_ERR_STATE, "cw_bind first");
   HIPCHK(hipSetDevice(s->device));
-  HIPCHK(hipMemcpyAsync(s->fields[s->cur][field], host_in, s->n * sizeof(float), hipMemcpyHostToDevice, s->stream));
+  for (size_t p = 0; p < s->n; p++)
+    if (!std::isfinite(host_in[p])) return fail(CW_ERR_NONFINITE, "value %zu is not finite", p);
+  if (s->storage == ST_F32) {
+    HIPCHK(hipMemcpyAsync(s->fields[s->cur][field], host_in, s->n * sizeof(float), hipMemcpyHostToDevice, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    return CW_OK;
+  }
+  std::vector<uint16_t> raw;
+  try { raw.resize(s->n); } catch (...) { return fail(CW_ERR_NOMEM, "out of host memory"); }
+  float scl = 1.0f;
+  if (s->storage == ST_F16) {
+    double m = 0;
+    for (size_t p = 0; p < s->n; p++) m = std::max(m, (double)std::fabs(host_in[p]));
+    scl = f16_scale(m);
+    _Float16 *h = reinterpret_cast<_Float16 *>(raw.data());
+    for (size_t p = 0; p < s->n; p++) h[p] = (_Float16)(host_in[p] / scl);
+  } else {
+    for (size_t p = 0; p < s->n; p++) raw[p] = float_to_bf16(host_in[p]);
+  }
+  HIPCHK(hipMemcpyAsync(s->fields[s->cur][field], raw.data(), s->n * 2, hipMemcpyHostToDevice, s->stream));
+  // the buffer's scale, and the scale of the next write of this field
+  HIPCHK(hipMemcpyAsync(s->d_scl + s->cur * NF + field, &scl, sizeof(float), hipMemcpyHostToDevice, s->stream));
+  HIPCHK(hipMemcpyAsync(s->d_scl + 2 * NF + field, &scl, sizeof(float), hipMemcpyHostToDevice, s->stream));
   HIPCHK(hipStreamSynchronize(s->stream));
   return CW_OK;
 }
@@ -668,7 +760,9 @@ cw_status cw_energy(cw_sim *s, double *E)
   HIPCHK(hipSetDevice(s->device));
   const StepArgs a = step_args(s, 1 - s->cur, s->cur);   // in: level n, out: level n+1
   const double scale = s->dr * s->dr * s->dth * s->dz;  // radii are in units of dr
-  HIPCHK(launch_energy(a, s->d_energy, kEnergyBlocks, scale, s->d_energy + kEnergyBlocks, s->stream));
+  StepArgs ae = a;
+  ae.scl_out = s->d_scl + s->cur * NF;                  // the current buffer's own scales
+  HIPCHK(launch_energy(ae, s->storage, s->d_energy, kEnergyBlocks, scale, s->d_energy + kEnergyBlocks, s->stream));
   HIPCHK(hipMemcpyAsync(E, s->d_energy + kEnergyBlocks, sizeof(double), hipMemcpyDeviceToHost, s->stream));
   HIPCHK(hipStreamSynchronize(s->stream));
   if (!std::isfinite(*E)) return fail(CW_ERR_NONFINITE, "energy is not finite");
@@ -681,6 +775,15 @@ cw_status cw_reset(cw_sim *s)
   if (!s->bound) return fail(CW_ERR_STATE, "cw_bind first");
   HIPCHK(hipSetDevice(s->device));
   return zero_state(s);
+}
+
+cw_status cw_set_storage(cw_sim *s, int32_t storage)
+{
+  cw_status st;
+  if (!configurable(s, &st)) return st;
+  if (storage < CW_STORE_F32 || storage > CW_STORE_BF16) return fail(CW_ERR_ARG, "bad storage %d", storage);
+  s->storage = storage;
+  return CW_OK;
 }
 
 cw_status cw_set_path(cw_sim *s, int32_t path)

@@ -9,6 +9,10 @@ namespace cw {
 
 enum Field { VR = 0, VT, VZ, SRR, STT, SZZ, SRT, SRZ, STZ, NF };
 
+// Storage of the 9 fields (arithmetic is float32 in every case).
+enum Storage { ST_F32 = 0, ST_F16, ST_BF16 };
+constexpr int kMaxSlots = 64;       // max-abs slots per field (float16 scale tracking)
+
 // Layer memory variables living in the radial slab i >= nr - npml_r.
 enum PsiR {
   R_VR_DR = 0, R_VR_B, R_VT_DR, R_VT_B, R_VZ_DR, R_VZ_B,
@@ -38,6 +42,13 @@ struct StepArgs {
   float *psi_z[NPSI_Z];     // [nr][nt][nzs]
   const float *tab_r;       // [NTAB_R][nr]
   const float *tab_z;       // [NTAB_Z][nz]
+  // 16-bit storage: a stored value times its field's scale is the physical
+  // value.  scl_in scales the level-n buffer, scl_out the level-n+1 buffer;
+  // maxabs collects the largest |value| written (float bits, kMaxSlots
+  // slots per field, for the next step's scale).  Unused (scales 1) for
+  // float32 storage.
+  const float *scl_in, *scl_out;
+  unsigned *maxabs;
 };
 
 // One point (or ring) injection: field[(i, j or all j, k)] += scale * amp[n].
@@ -108,13 +119,21 @@ int fused_tiles(int nt, int nz, int *own_rows, int *ntile_z);
 size_t fused_lds_bytes(int nr);                 // dynamic LDS of the fused step
 constexpr int kMaxFusedRings = 2048;            // nr limit of the fused step (LDS tables)
 hipError_t launch_fused(const FusedArgs &f, hipStream_t stream);
-hipError_t launch_velocity_basic(const StepArgs &a, hipStream_t stream);
-hipError_t launch_stress_basic(const StepArgs &a, hipStream_t stream);
+hipError_t launch_velocity_basic(const StepArgs &a, int storage, hipStream_t stream);
+hipError_t launch_stress_basic(const StepArgs &a, int storage, hipStream_t stream);
 hipError_t launch_inject(const Inject *dev_list, int ninj, int phase, int64_t step,
-                         const StepArgs &a, hipStream_t stream);
+                         const StepArgs &a, int storage, hipStream_t stream);
 hipError_t launch_record(const Receiver *dev_rec, int nrec, int64_t step, int64_t cap,
-                         const StepArgs &a, double *traces, hipStream_t stream);
-hipError_t launch_energy(const StepArgs &a, double *partials, int nblocks, double scale,
+                         const StepArgs &a, int storage, double *traces, hipStream_t stream);
+hipError_t launch_energy(const StepArgs &a, int storage, double *partials, int nblocks, double scale,
                          double *result, hipStream_t stream);
+// After a float16 step: record the scale the level-n+1 buffer was written
+// with (scl_written = scl_next), derive the next scale from maxabs, clear it.
+hipError_t launch_rescale(float *scl_written, float *scl_next, unsigned *maxabs, hipStream_t stream);
+constexpr int kF16TargetExp = 11;   // scaled float16 maxima land in [2^10, 2^11)
+// depth-vectorized two-pass kernels (4 cells per thread), when nz % 4 == 0
+bool vec_applies(int nz);
+hipError_t launch_velocity_vec(const StepArgs &a, int storage, hipStream_t stream);
+hipError_t launch_stress_vec(const StepArgs &a, int storage, hipStream_t stream);
 
 }  // namespace cw

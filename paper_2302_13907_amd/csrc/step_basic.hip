@@ -1,8 +1,10 @@
-// Straightforward kernels of the time step: one thread per cell, k (depth)
-// across the lanes so every load of a wavefront is one contiguous 256-byte
-// run.  The velocity and stress updates are separate launches (two passes
-// over the state); they are the plain FP32 form the fused kernel is checked
-// against, and they carry the source, receiver and energy kernels.
+// Two-pass time step: one thread per cell, k (depth) across the lanes so
+// every load of a wavefront is one contiguous run.  The velocity and stress
+// updates are separate launches; they carry the source, receiver, energy
+// and rescale kernels too.  The fields may be stored in float32, float16
+// (with a power-of-two scale per field, chosen on the device from the
+// largest magnitude written in the previous step) or bfloat16; every
+// arithmetic operation is float32.
 //
 // The discrete operators are the staggered-grid form (Sec. 3) of Eq. (1):
 //   rho dv_r/dt = ds_rr/dr + (1/r)(ds_rt/dth + s_rr - s_tt) + ds_rz/dz
@@ -16,29 +18,26 @@
 // axis and the outer faces, and every r- or z-derivative term and 1/r
 // bracket passed through the absorbing layer's recursive convolution.
 #include "cwell_internal.hpp"
+#include "storage.hpp"
 
 namespace cw {
 
 namespace {
-
-__device__ __forceinline__ float ld(const float *f, const StepArgs &a, int i, int j, int k)
-{
-  if (i < 0 || i >= a.nr || k < 0 || k >= a.nz) return 0.0f;
-  return f[((size_t)i * a.nt + j) * a.nz + k];
-}
 
 __device__ __forceinline__ size_t at(const StepArgs &a, int i, int j, int k)
 {
   return ((size_t)i * a.nt + j) * a.nz + k;
 }
 
-// Reciprocal: the hardware v_rcp_f32 (1 ulp) by default, IEEE division
-// when CW_IEEE_DIV is set.
-#ifdef CW_IEEE_DIV
-__device__ __forceinline__ float rcp(float x) { return 1.0f / x; }
-#else
+template <class S>
+__device__ __forceinline__ float ld(const float *f, float s, const StepArgs &a, int i, int j, int k)
+{
+  if (i < 0 || i >= a.nr || k < 0 || k >= a.nz) return 0.0f;
+  return S::ld(f, at(a, i, j, k), s);
+}
+
+// Reciprocal: the hardware v_rcp_f32 (1 ulp).
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
-#endif
 
 // Harmonic mean of four moduli: 4 / (1/a + 1/b + 1/c + 1/d).  A zero
 // argument makes its reciprocal +inf and the mean exactly zero.
@@ -65,25 +64,42 @@ __device__ __forceinline__ float cpml(float *psi, size_t p, float ca, float cb, 
   return X + v;
 }
 
+// largest |x| over the wavefront into one of the field's slots: one
+// atomic per wavefront, spread over kMaxSlots addresses (float bits of a
+// non-negative float order like unsigned integers)
+__device__ __forceinline__ void track_max(unsigned *slots, float x)
+{
+  float m = fabsf(x);
+  for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
+  if ((threadIdx.x & 63) == 0 && m > 0.0f)
+    atomicMax(&slots[(blockIdx.x + (threadIdx.x >> 6)) & (kMaxSlots - 1)], __builtin_bit_cast(unsigned, m));
+}
+
+template <class S>
 __global__ void __launch_bounds__(256) k_velocity_basic(StepArgs a, int nbx)
 {
-  // 1-D grid remapped per XCD; logical tile = (depth chunk, row, ring)
   const int t = xcd_tile(blockIdx.x, gridDim.x);
   const int bx = t % nbx, ij = t / nbx;
   const int k = bx * 256 + threadIdx.x;
   const int j = ij % a.nt, i = ij / a.nt;
-  if (k >= a.nz) return;
+  const bool live = k < a.nz;
+  const int kk = live ? k : a.nz - 1;              // dead lanes compute on a valid cell, store nothing
   const int jm = j == 0 ? a.nt - 1 : j - 1;
   const int jp = j == a.nt - 1 ? 0 : j + 1;
   const float *sRR = a.in[SRR], *sTT = a.in[STT], *sZZ = a.in[SZZ];
   const float *sRT = a.in[SRT], *sRZ = a.in[SRZ], *sTZ = a.in[STZ];
+  const float *c = a.scl_in;
 
-  const float srr0 = ld(sRR, a, i, j, k), srr1 = ld(sRR, a, i + 1, j, k);
-  const float stt0 = ld(sTT, a, i, j, k), stt1 = ld(sTT, a, i + 1, j, k), stt_jp = ld(sTT, a, i, jp, k);
-  const float srt0 = ld(sRT, a, i, j, k), srt_jm = ld(sRT, a, i, jm, k), srt_im = ld(sRT, a, i - 1, j, k);
-  const float srz0 = ld(sRZ, a, i, j, k), srz_km = ld(sRZ, a, i, j, k - 1), srz_im = ld(sRZ, a, i - 1, j, k);
-  const float stz0 = ld(sTZ, a, i, j, k), stz_jm = ld(sTZ, a, i, jm, k), stz_km = ld(sTZ, a, i, j, k - 1);
-  const float szz0 = ld(sZZ, a, i, j, k), szz_kp = ld(sZZ, a, i, j, k + 1);
+  const float srr0 = ld<S>(sRR, c[SRR], a, i, j, kk), srr1 = ld<S>(sRR, c[SRR], a, i + 1, j, kk);
+  const float stt0 = ld<S>(sTT, c[STT], a, i, j, kk), stt1 = ld<S>(sTT, c[STT], a, i + 1, j, kk);
+  const float stt_jp = ld<S>(sTT, c[STT], a, i, jp, kk);
+  const float srt0 = ld<S>(sRT, c[SRT], a, i, j, kk), srt_jm = ld<S>(sRT, c[SRT], a, i, jm, kk);
+  const float srt_im = ld<S>(sRT, c[SRT], a, i - 1, j, kk);
+  const float srz0 = ld<S>(sRZ, c[SRZ], a, i, j, kk), srz_km = ld<S>(sRZ, c[SRZ], a, i, j, kk - 1);
+  const float srz_im = ld<S>(sRZ, c[SRZ], a, i - 1, j, kk);
+  const float stz0 = ld<S>(sTZ, c[STZ], a, i, j, kk), stz_jm = ld<S>(sTZ, c[STZ], a, i, jm, kk);
+  const float stz_km = ld<S>(sTZ, c[STZ], a, i, j, kk - 1);
+  const float szz0 = ld<S>(sZZ, c[SZZ], a, i, j, kk), szz_kp = ld<S>(sZZ, c[SZZ], a, i, j, kk + 1);
 
   const float irc = a.inv_rc[i], irf = a.inv_rf[i];
   // v_r at (R_i, th_j, z_k)
@@ -100,7 +116,7 @@ __global__ void __launch_bounds__(256) k_velocity_basic(StepArgs a, int nbx)
   float z_dz = (szz_kp - szz0) * a.inv_dz;
 
   const int ir = i - (a.nr - a.npr);
-  if (ir >= 0) {
+  if (ir >= 0 && live) {
     const size_t q = ((size_t)ir * a.nt + j) * a.nz + k;
     const float *T = a.tab_r;
     r_dr = cpml(a.psi_r[R_VR_DR], q, T[AR_F * a.nr + i], T[BR_F * a.nr + i], r_dr);
@@ -110,7 +126,7 @@ __global__ void __launch_bounds__(256) k_velocity_basic(StepArgs a, int nbx)
     z_dr = cpml(a.psi_r[R_VZ_DR], q, T[AR_C * a.nr + i], T[BR_C * a.nr + i], z_dr);
     z_b = cpml(a.psi_r[R_VZ_B], q, T[AT_C * a.nr + i], T[BT_C * a.nr + i], z_b);
   }
-  const int kz = zrow(a, k);
+  const int kz = live ? zrow(a, k) : -1;
   if (kz >= 0) {
     const size_t q = ((size_t)i * a.nt + j) * a.nzs + kz;
     const float *T = a.tab_z;
@@ -121,37 +137,50 @@ __global__ void __launch_bounds__(256) k_velocity_basic(StepArgs a, int nbx)
 
   // buoyancies: arithmetic mean of the two adjacent densities (clamped at the edges)
   const int i1 = i + 1 < a.nr ? i + 1 : a.nr - 1;
-  const int k1 = k + 1 < a.nz ? k + 1 : a.nz - 1;
-  const size_t p = at(a, i, j, k);
+  const int k1 = kk + 1 < a.nz ? kk + 1 : a.nz - 1;
+  const size_t p = at(a, i, j, kk);
   const float rho0 = a.rho[p];
-  const float b_r = 2.0f * rcp(rho0 + a.rho[at(a, i1, j, k)]);
-  const float b_t = 2.0f * rcp(rho0 + a.rho[at(a, i, jp, k)]);
+  const float b_r = 2.0f * rcp(rho0 + a.rho[at(a, i1, j, kk)]);
+  const float b_t = 2.0f * rcp(rho0 + a.rho[at(a, i, jp, kk)]);
   const float b_z = 2.0f * rcp(rho0 + a.rho[at(a, i, j, k1)]);
 
-  a.out[VR][p] = a.in[VR][p] + a.dt * b_r * (r_dr + r_b + r_dz);
-  a.out[VT][p] = a.in[VT][p] + a.dt * b_t * (t_dr + t_b + t_dz);
-  a.out[VZ][p] = a.in[VZ][p] + a.dt * b_z * (z_dr + z_b + z_dz);
+  const float vr = S::ld(a.in[VR], p, c[VR]) + a.dt * b_r * (r_dr + r_b + r_dz);
+  const float vt = S::ld(a.in[VT], p, c[VT]) + a.dt * b_t * (t_dr + t_b + t_dz);
+  const float vz = S::ld(a.in[VZ], p, c[VZ]) + a.dt * b_z * (z_dr + z_b + z_dz);
+  if (live) {
+    const float *o = a.scl_out;
+    S::st(a.out[VR], p, vr, 1.0f / o[VR]);
+    S::st(a.out[VT], p, vt, 1.0f / o[VT]);
+    S::st(a.out[VZ], p, vz, 1.0f / o[VZ]);
+  }
+  if (S::scaled) {
+    track_max(a.maxabs + VR * kMaxSlots, live ? vr : 0.0f);
+    track_max(a.maxabs + VT * kMaxSlots, live ? vt : 0.0f);
+    track_max(a.maxabs + VZ * kMaxSlots, live ? vz : 0.0f);
+  }
 }
 
+template <class S>
 __global__ void __launch_bounds__(256) k_stress_basic(StepArgs a, int nbx)
 {
-  // 1-D grid remapped per XCD; logical tile = (depth chunk, row, ring)
   const int t = xcd_tile(blockIdx.x, gridDim.x);
   const int bx = t % nbx, ij = t / nbx;
   const int k = bx * 256 + threadIdx.x;
   const int j = ij % a.nt, i = ij / a.nt;
-  if (k >= a.nz) return;
+  const bool live = k < a.nz;
+  const int kk = live ? k : a.nz - 1;
   const int jm = j == 0 ? a.nt - 1 : j - 1;
   const int jp = j == a.nt - 1 ? 0 : j + 1;
   // velocities at level n+1/2 are in the output buffer
   const float *vR = a.out[VR], *vT = a.out[VT], *vZ = a.out[VZ];
+  const float *o = a.scl_out;
 
-  const float vr0 = ld(vR, a, i, j, k), vr_im = ld(vR, a, i - 1, j, k);
-  const float vr_jp = ld(vR, a, i, jp, k), vr_kp = ld(vR, a, i, j, k + 1);
-  const float vt0 = ld(vT, a, i, j, k), vt_jm = ld(vT, a, i, jm, k);
-  const float vt_ip = ld(vT, a, i + 1, j, k), vt_kp = ld(vT, a, i, j, k + 1);
-  const float vz0 = ld(vZ, a, i, j, k), vz_km = ld(vZ, a, i, j, k - 1);
-  const float vz_ip = ld(vZ, a, i + 1, j, k), vz_jp = ld(vZ, a, i, jp, k);
+  const float vr0 = ld<S>(vR, o[VR], a, i, j, kk), vr_im = ld<S>(vR, o[VR], a, i - 1, j, kk);
+  const float vr_jp = ld<S>(vR, o[VR], a, i, jp, kk), vr_kp = ld<S>(vR, o[VR], a, i, j, kk + 1);
+  const float vt0 = ld<S>(vT, o[VT], a, i, j, kk), vt_jm = ld<S>(vT, o[VT], a, i, jm, kk);
+  const float vt_ip = ld<S>(vT, o[VT], a, i + 1, j, kk), vt_kp = ld<S>(vT, o[VT], a, i, j, kk + 1);
+  const float vz0 = ld<S>(vZ, o[VZ], a, i, j, kk), vz_km = ld<S>(vZ, o[VZ], a, i, j, kk - 1);
+  const float vz_ip = ld<S>(vZ, o[VZ], a, i + 1, j, kk), vz_jp = ld<S>(vZ, o[VZ], a, i, jp, kk);
 
   const float irc = a.inv_rc[i], irf = a.inv_rf[i];
   float err = (vr0 - vr_im) * a.inv_dr;
@@ -165,7 +194,7 @@ __global__ void __launch_bounds__(256) k_stress_basic(StepArgs a, int nbx)
   float tz_dz = (vt_kp - vt0) * a.inv_dz;
 
   const int ir = i - (a.nr - a.npr);
-  if (ir >= 0) {
+  if (ir >= 0 && live) {
     const size_t q = ((size_t)ir * a.nt + j) * a.nz + k;
     const float *T = a.tab_r;
     err = cpml(a.psi_r[R_N_DR], q, T[AR_C * a.nr + i], T[BR_C * a.nr + i], err);
@@ -175,7 +204,7 @@ __global__ void __launch_bounds__(256) k_stress_basic(StepArgs a, int nbx)
     rz_dr = cpml(a.psi_r[R_RZ_DR], q, T[AR_F * a.nr + i], T[BR_F * a.nr + i], rz_dr);
     tz_b = cpml(a.psi_r[R_TZ_B], q, T[AT_C * a.nr + i], T[BT_C * a.nr + i], tz_b);
   }
-  const int kz = zrow(a, k);
+  const int kz = live ? zrow(a, k) : -1;
   if (kz >= 0) {
     const size_t q = ((size_t)i * a.nt + j) * a.nzs + kz;
     const float *T = a.tab_z;
@@ -185,27 +214,45 @@ __global__ void __launch_bounds__(256) k_stress_basic(StepArgs a, int nbx)
   }
 
   const int i1 = i + 1 < a.nr ? i + 1 : a.nr - 1;
-  const int k1 = k + 1 < a.nz ? k + 1 : a.nz - 1;
-  const size_t p = at(a, i, j, k);
+  const int k1 = kk + 1 < a.nz ? kk + 1 : a.nz - 1;
+  const size_t p = at(a, i, j, kk);
   const float lam = a.lam[p], mu = a.mu[p];
-  const float mu_i1 = a.mu[at(a, i1, j, k)], mu_jp = a.mu[at(a, i, jp, k)];
+  const float mu_i1 = a.mu[at(a, i1, j, kk)], mu_jp = a.mu[at(a, i, jp, kk)];
   const float mu_k1 = a.mu[at(a, i, j, k1)];
-  const float mu_rt = hm4(mu, mu_i1, mu_jp, a.mu[at(a, i1, jp, k)]);
+  const float mu_rt = hm4(mu, mu_i1, mu_jp, a.mu[at(a, i1, jp, kk)]);
   const float mu_rz = hm4(mu, mu_i1, mu_k1, a.mu[at(a, i1, j, k1)]);
   const float mu_tz = hm4(mu, mu_jp, mu_k1, a.mu[at(a, i, jp, k1)]);
 
+  const float *c = a.scl_in;
   const float tr = err + ett + ezz;
   const float lt = lam * tr, m2 = 2.0f * mu;
-  a.out[SRR][p] = a.in[SRR][p] + a.dt * (lt + m2 * err);
-  a.out[STT][p] = a.in[STT][p] + a.dt * (lt + m2 * ett);
-  a.out[SZZ][p] = a.in[SZZ][p] + a.dt * (lt + m2 * ezz);
-  a.out[SRT][p] = a.in[SRT][p] + a.dt * mu_rt * (rt_dr + rt_b);
-  a.out[SRZ][p] = a.in[SRZ][p] + a.dt * mu_rz * (rz_dr + rz_dz);
-  a.out[STZ][p] = a.in[STZ][p] + a.dt * mu_tz * (tz_b + tz_dz);
+  const float s_rr = S::ld(a.in[SRR], p, c[SRR]) + a.dt * (lt + m2 * err);
+  const float s_tt = S::ld(a.in[STT], p, c[STT]) + a.dt * (lt + m2 * ett);
+  const float s_zz = S::ld(a.in[SZZ], p, c[SZZ]) + a.dt * (lt + m2 * ezz);
+  const float s_rt = S::ld(a.in[SRT], p, c[SRT]) + a.dt * mu_rt * (rt_dr + rt_b);
+  const float s_rz = S::ld(a.in[SRZ], p, c[SRZ]) + a.dt * mu_rz * (rz_dr + rz_dz);
+  const float s_tz = S::ld(a.in[STZ], p, c[STZ]) + a.dt * mu_tz * (tz_b + tz_dz);
+  if (live) {
+    S::st(a.out[SRR], p, s_rr, 1.0f / o[SRR]);
+    S::st(a.out[STT], p, s_tt, 1.0f / o[STT]);
+    S::st(a.out[SZZ], p, s_zz, 1.0f / o[SZZ]);
+    S::st(a.out[SRT], p, s_rt, 1.0f / o[SRT]);
+    S::st(a.out[SRZ], p, s_rz, 1.0f / o[SRZ]);
+    S::st(a.out[STZ], p, s_tz, 1.0f / o[STZ]);
+  }
+  if (S::scaled) {
+    track_max(a.maxabs + SRR * kMaxSlots, live ? s_rr : 0.0f);
+    track_max(a.maxabs + STT * kMaxSlots, live ? s_tt : 0.0f);
+    track_max(a.maxabs + SZZ * kMaxSlots, live ? s_zz : 0.0f);
+    track_max(a.maxabs + SRT * kMaxSlots, live ? s_rt : 0.0f);
+    track_max(a.maxabs + SRZ * kMaxSlots, live ? s_rz : 0.0f);
+    track_max(a.maxabs + STZ * kMaxSlots, live ? s_tz : 0.0f);
+  }
 }
 
 // One block applies every injection of the phase in list order, so two
 // sources hitting the same node add in a fixed order.
+template <class S>
 __global__ void __launch_bounds__(256) k_inject(const Inject *list, int ninj, int phase,
                                                 int64_t step, StepArgs a)
 {
@@ -214,10 +261,13 @@ __global__ void __launch_bounds__(256) k_inject(const Inject *list, int ninj, in
     if (e.phase == phase && step < e.nsamp) {
       const float amp = e.scale * e.amp[step];
       float *f = a.out[e.field];
-      if (e.j >= 0) {
-        if (threadIdx.x == 0) f[at(a, e.i, e.j, e.k)] += amp;
-      } else {
-        for (int j = threadIdx.x; j < a.nt; j += blockDim.x) f[at(a, e.i, j, e.k)] += amp;
+      const float s = a.scl_out[e.field];
+      const int j0 = e.j >= 0 ? e.j : 0, j1 = e.j >= 0 ? e.j + 1 : a.nt;
+      for (int j = j0 + (int)threadIdx.x; j < j1; j += blockDim.x) {
+        const size_t p = at(a, e.i, j, e.k);
+        const float v = S::ld(f, p, s) + amp;
+        S::st(f, p, v, 1.0f / s);
+        if (S::scaled) atomicMax(&a.maxabs[e.field * kMaxSlots], __builtin_bit_cast(unsigned, fabsf(v)));
       }
     }
     __syncthreads();
@@ -225,18 +275,21 @@ __global__ void __launch_bounds__(256) k_inject(const Inject *list, int ninj, in
 }
 
 // One wavefront per receiver; float64 sum over the ring in a fixed order.
+template <class S>
 __global__ void __launch_bounds__(64) k_record(const Receiver *rec, int64_t step, int64_t cap,
                                                StepArgs a, double *traces)
 {
   const Receiver r = rec[blockIdx.x];
   const int j0 = r.j < 0 ? 0 : r.j, j1 = r.j < 0 ? a.nt : r.j + 1;
+  const float *o = a.scl_out;
   double acc = 0.0;
   for (int j = j0 + (int)threadIdx.x; j < j1; j += 64) {
     const size_t p = at(a, r.i, j, r.k);
     if (r.kind == 0)
-      acc += (double)a.out[SRR][p] + (double)a.out[STT][p] + (double)a.out[SZZ][p];
+      acc += (double)S::ld(a.out[SRR], p, o[SRR]) + (double)S::ld(a.out[STT], p, o[STT]) +
+             (double)S::ld(a.out[SZZ], p, o[SZZ]);
     else
-      acc += (double)a.out[r.field][p];
+      acc += (double)S::ld(a.out[r.field], p, o[r.field]);
   }
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
   if (threadIdx.x == 0) {
@@ -246,23 +299,26 @@ __global__ void __launch_bounds__(64) k_record(const Receiver *rec, int64_t step
 }
 
 // Energy density of one cell in float64; a.in = level n, a.out = level n+1.
+template <class S>
 __device__ double cell_energy(const StepArgs &a, int i, int j, int k)
 {
   const int jp = j == a.nt - 1 ? 0 : j + 1;
   const int i1 = i + 1 < a.nr ? i + 1 : a.nr - 1;
   const int k1 = k + 1 < a.nz ? k + 1 : a.nz - 1;
   const size_t p = at(a, i, j, k);
+  const float *ci = a.scl_in, *co = a.scl_out;
   const double ri = (double)(i + 0.5), Ri = (double)(i + 1);   // radii in units of dr
   const double rho0 = a.rho[p];
   const double rr = 0.5 * (rho0 + a.rho[at(a, i1, j, k)]);
   const double rt = 0.5 * (rho0 + a.rho[at(a, i, jp, k)]);
   const double rz = 0.5 * (rho0 + a.rho[at(a, i, j, k1)]);
-  const double vr = a.out[VR][p], vt = a.out[VT][p], vz = a.out[VZ][p];
+  const double vr = S::ld(a.out[VR], p, co[VR]), vt = S::ld(a.out[VT], p, co[VT]);
+  const double vz = S::ld(a.out[VZ], p, co[VZ]);
   double E = 0.5 * (Ri * rr * vr * vr + ri * rt * vt * vt + ri * rz * vz * vz);
   const double lam = a.lam[p], mu = a.mu[p];
   const double K = lam + 2.0 * mu / 3.0;
-  const double n1[3] = {a.out[SRR][p], a.out[STT][p], a.out[SZZ][p]};
-  const double n0[3] = {a.in[SRR][p], a.in[STT][p], a.in[SZZ][p]};
+  const double n1[3] = {S::ld(a.out[SRR], p, co[SRR]), S::ld(a.out[STT], p, co[STT]), S::ld(a.out[SZZ], p, co[SZZ])};
+  const double n0[3] = {S::ld(a.in[SRR], p, ci[SRR]), S::ld(a.in[STT], p, ci[STT]), S::ld(a.in[SZZ], p, ci[SZZ])};
   const double t1 = n1[0] + n1[1] + n1[2], t0 = n0[0] + n0[1] + n0[2];
   E += 0.5 * ri * t1 * t0 / (9.0 * K);
   if (mu > 0.0) {
@@ -277,12 +333,13 @@ __device__ double cell_energy(const StepArgs &a, int i, int j, int k)
   const double mrt = hm(mu, m_i1, m_jp, a.mu[at(a, i1, jp, k)]);
   const double mrz = hm(mu, m_i1, m_k1, a.mu[at(a, i1, j, k1)]);
   const double mtz = hm(mu, m_jp, m_k1, a.mu[at(a, i, jp, k1)]);
-  if (mrt > 0.0) E += 0.5 * Ri * (double)a.out[SRT][p] * (double)a.in[SRT][p] / mrt;
-  if (mrz > 0.0) E += 0.5 * Ri * (double)a.out[SRZ][p] * (double)a.in[SRZ][p] / mrz;
-  if (mtz > 0.0) E += 0.5 * ri * (double)a.out[STZ][p] * (double)a.in[STZ][p] / mtz;
+  if (mrt > 0.0) E += 0.5 * Ri * (double)S::ld(a.out[SRT], p, co[SRT]) * (double)S::ld(a.in[SRT], p, ci[SRT]) / mrt;
+  if (mrz > 0.0) E += 0.5 * Ri * (double)S::ld(a.out[SRZ], p, co[SRZ]) * (double)S::ld(a.in[SRZ], p, ci[SRZ]) / mrz;
+  if (mtz > 0.0) E += 0.5 * ri * (double)S::ld(a.out[STZ], p, co[STZ]) * (double)S::ld(a.in[STZ], p, ci[STZ]) / mtz;
   return E;
 }
 
+template <class S>
 __global__ void __launch_bounds__(256) k_energy_partial(StepArgs a, double *partials)
 {
   __shared__ double red[256];
@@ -292,7 +349,7 @@ __global__ void __launch_bounds__(256) k_energy_partial(StepArgs a, double *part
     const int k = (int)(c % a.nz);
     const size_t ij = c / a.nz;
     const int j = (int)(ij % a.nt), i = (int)(ij / a.nt);
-    acc += cell_energy(a, i, j, k);
+    acc += cell_energy<S>(a, i, j, k);
   }
   red[threadIdx.x] = acc;
   __syncthreads();
@@ -318,49 +375,96 @@ __global__ void __launch_bounds__(256) k_energy_final(const double *partials, in
   if (threadIdx.x == 0) *result = red[0] * scale;
 }
 
-}  // namespace
-
-hipError_t launch_velocity_basic(const StepArgs &a, hipStream_t stream)
+// New float16 scale per field: 2^(e - target) with max|v| = f 2^e,
+// f in [0.5, 1); unchanged while a field is still identically zero.
+__global__ void k_rescale(float *scl_written, float *scl_next, unsigned *maxabs)
 {
-  const int nbx = (a.nz + 255) / 256;
-  const long g = (long)nbx * a.nt * a.nr;
-  if (g > 0x7fffffff) return hipErrorInvalidConfiguration;
-  hipLaunchKernelGGL(k_velocity_basic, dim3((unsigned)g), dim3(256), 0, stream, a, nbx);
-  return hipGetLastError();
+  const int q = threadIdx.x;
+  if (q >= NF) return;
+  scl_written[q] = scl_next[q];
+  unsigned mb = 0u;
+  for (int c = 0; c < kMaxSlots; c++) {
+    mb = max(mb, maxabs[q * kMaxSlots + c]);
+    maxabs[q * kMaxSlots + c] = 0u;
+  }
+  const float m = __builtin_bit_cast(float, mb);
+  if (m > 0.0f) {
+    int e;
+    frexpf(m, &e);
+    scl_next[q] = ldexpf(1.0f, e - kF16TargetExp);
+  }
 }
 
-hipError_t launch_stress_basic(const StepArgs &a, hipStream_t stream)
+template <class F>
+hipError_t dispatch(int storage, F &&f)
+{
+  switch (storage) {
+  case ST_F32: return f(StF32{});
+  case ST_F16: return f(StF16{});
+  case ST_BF16: return f(StBF16{});
+  default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_velocity_basic(const StepArgs &a, int storage, hipStream_t stream)
 {
   const int nbx = (a.nz + 255) / 256;
   const long g = (long)nbx * a.nt * a.nr;
   if (g > 0x7fffffff) return hipErrorInvalidConfiguration;
-  hipLaunchKernelGGL(k_stress_basic, dim3((unsigned)g), dim3(256), 0, stream, a, nbx);
-  return hipGetLastError();
+  return dispatch(storage, [&](auto s) {
+    hipLaunchKernelGGL(k_velocity_basic<decltype(s)>, dim3((unsigned)g), dim3(256), 0, stream, a, nbx);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_stress_basic(const StepArgs &a, int storage, hipStream_t stream)
+{
+  const int nbx = (a.nz + 255) / 256;
+  const long g = (long)nbx * a.nt * a.nr;
+  if (g > 0x7fffffff) return hipErrorInvalidConfiguration;
+  return dispatch(storage, [&](auto s) {
+    hipLaunchKernelGGL(k_stress_basic<decltype(s)>, dim3((unsigned)g), dim3(256), 0, stream, a, nbx);
+    return hipGetLastError();
+  });
 }
 
 hipError_t launch_inject(const Inject *dev_list, int ninj, int phase, int64_t step,
-                         const StepArgs &a, hipStream_t stream)
+                         const StepArgs &a, int storage, hipStream_t stream)
 {
   if (ninj == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_inject, dim3(1), dim3(256), 0, stream, dev_list, ninj, phase, step, a);
-  return hipGetLastError();
+  return dispatch(storage, [&](auto s) {
+    hipLaunchKernelGGL(k_inject<decltype(s)>, dim3(1), dim3(256), 0, stream, dev_list, ninj, phase, step, a);
+    return hipGetLastError();
+  });
 }
 
 hipError_t launch_record(const Receiver *dev_rec, int nrec, int64_t step, int64_t cap,
-                         const StepArgs &a, double *traces, hipStream_t stream)
+                         const StepArgs &a, int storage, double *traces, hipStream_t stream)
 {
   if (nrec == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_record, dim3(nrec), dim3(64), 0, stream, dev_rec, step, cap, a, traces);
+  return dispatch(storage, [&](auto s) {
+    hipLaunchKernelGGL(k_record<decltype(s)>, dim3(nrec), dim3(64), 0, stream, dev_rec, step, cap, a, traces);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_energy(const StepArgs &a, int storage, double *partials, int nblocks, double scale,
+                         double *result, hipStream_t stream)
+{
+  hipError_t e = dispatch(storage, [&](auto s) {
+    hipLaunchKernelGGL(k_energy_partial<decltype(s)>, dim3(nblocks), dim3(256), 0, stream, a, partials);
+    return hipGetLastError();
+  });
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(256), 0, stream, partials, nblocks, scale, result);
   return hipGetLastError();
 }
 
-hipError_t launch_energy(const StepArgs &a, double *partials, int nblocks, double scale,
-                         double *result, hipStream_t stream)
+hipError_t launch_rescale(float *scl_written, float *scl_next, unsigned *maxabs, hipStream_t stream)
 {
-  hipLaunchKernelGGL(k_energy_partial, dim3(nblocks), dim3(256), 0, stream, a, partials);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(256), 0, stream, partials, nblocks, scale, result);
+  hipLaunchKernelGGL(k_rescale, dim3(1), dim3(64), 0, stream, scl_written, scl_next, maxabs);
   return hipGetLastError();
 }
 

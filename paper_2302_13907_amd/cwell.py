@@ -31,7 +31,9 @@ EXPORTS = ("cw_create", "cw_set_material", "cw_set_material_rz", "cw_set_pml", "
            "cw_workspace_bytes", "cw_bind", "cw_step", "cw_sync", "cw_get_traces",
            "cw_get_field", "cw_set_field", "cw_energy", "cw_reset", "cw_steps_done",
            "cw_ricker", "cw_destroy", "cw_last_error", "cw_profile", "cw_profile_read",
-           "cw_set_path")
+           "cw_set_path", "cw_set_storage")
+
+STORAGE = {"f32": 0, "f16": 1, "bf16": 2}
 
 PATHS = {"auto": 0, "two-pass": 1, "fused": 2}
 
@@ -87,6 +89,7 @@ def load():
         "cw_ricker": [D, DP, I64, DP],
         "cw_profile": [P, I32],
         "cw_set_path": [P, I32],
+        "cw_set_storage": [P, I32],
         "cw_profile_read": [P, I32, DP, ctypes.POINTER(I64)],
     }
     for name, args in sig.items():
@@ -241,6 +244,10 @@ class Sim:
 
     def reset(self):
         _check(self.lib.cw_reset(self.h))
+
+    def set_storage(self, storage: str):
+        """Field storage: "f32", "f16" (per-field power-of-two scales) or "bf16"."""
+        _check(self.lib.cw_set_storage(self.h, STORAGE[storage]))
 
     def set_path(self, path: str):
         """Kernel path of step(): "auto", "two-pass" or "fused"."""
