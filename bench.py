@@ -63,17 +63,175 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel: str, workload: str):
+def measured_traffic(variant: str, kernel: str, workload: str):
     """HBM bytes per launch from the committed counter summary, if it was
     taken on the current kernel sources; else None."""
     try:
         d = json.load(open(PMC_FILE))
     except (OSError, ValueError):
         return None
-    e = d.get(kernel)
+    e = d.get(variant, {}).get(kernel)
     if not e or e.get("source_hash") != kernel_source_hash() or e.get("workload") != workload:
         return None
     return e.get("bytes_per_launch")
+
+
+# --- hardware-counter profiles ------------------------------------------------------------
+# Each profiled variant runs this script for a few steps under rocprofv3 three times: a
+# kernel trace with statistics, then FETCH_SIZE and WRITE_SIZE counter passes (each counter
+# in a run of its own), and a fourth pass counting L2-to-fabric read requests by size.  The
+# run ends with a 1 GiB device-to-device copy whose counter readings calibrate the counters
+# (bytes the copy must move / what the counter reports for it).
+PROFILE_VARIANTS = {
+    "two_pass_f32": "--path two-pass --storage f32",
+    "two_pass_f16": "--path two-pass --storage f16",
+    "two_pass_bf16": "--path two-pass --storage bf16",
+    "fused_f32": "--path fused --storage f32",
+}
+PROFILE_RUN = "python3 -u bench.py --steps 20 --warmup 5 --no-cpu-baseline --no-storage-forms --copy-gib 1"
+PROFILE_PASSES = (
+    ("stats", "--kernel-trace --stats"),
+    ("fetch", "--pmc FETCH_SIZE"),
+    ("write", "--pmc WRITE_SIZE"),
+    ("rdreq", "--pmc TCC_EA0_RDREQ_32B_sum TCC_EA0_RDREQ_64B_sum TCC_EA0_RDREQ_128B_sum"),
+)
+KERNEL_PATTERNS = (("velocity", "k_velocity_"), ("stress", "k_stress_"), ("fused", "k_step_fused"),
+                   ("inject", "k_inject"), ("record", "k_record"), ("rescale", "k_rescale"),
+                   ("copy", "copyBuffer"))
+
+
+def profile_commands(variant: str, outdir: str):
+    run = "%s %s" % (PROFILE_RUN, PROFILE_VARIANTS[variant])
+    return [(name, "rocprofv3 %s --output-format csv -d %s/%s -o p -- %s" % (opts, outdir, name, run))
+            for name, opts in PROFILE_PASSES]
+
+
+def _kernel_key(name: str):
+    for key, pat in KERNEL_PATTERNS:
+        if pat in name:
+            return key
+    return None
+
+
+def _read_csv(path):
+    import csv
+    with open(path, newline="") as f:
+        return list(csv.DictReader(f))
+
+
+def ingest_profiles(variant: str, outdir: str):
+    """Turn the four rocprofv3 passes of `variant` (made by the commands of
+    profile_commands) into profiles/<kernels>_<variant>_production.txt and the
+    variant's entry of profiles/hbm_traffic.json."""
+    from paper_2302_13907_amd import inputs
+    w = inputs.production_case()
+    cmds = dict(profile_commands(variant, outdir))
+    # kernel statistics
+    stats = {}
+    for r in _read_csv(os.path.join(outdir, "stats", "p_kernel_stats.csv")):
+        k = _kernel_key(r["Name"])
+        if k is None:
+            continue
+        e = stats.setdefault(k, {"calls": 0, "total_ns": 0.0, "min_ns": float("inf"), "max_ns": 0.0})
+        e["calls"] += int(r["Calls"])
+        e["total_ns"] += float(r["TotalDurationNs"])
+        e["min_ns"] = min(e["min_ns"], float(r["MinNs"]))
+        e["max_ns"] = max(e["max_ns"], float(r["MaxNs"]))
+    live = None
+    try:
+        for line in open(os.path.join(outdir, "stats.log")):
+            if line.startswith("{"):
+                live = json.loads(line)
+    except OSError:
+        pass
+    # counters: per kernel class, the mean over dispatches; the copy reference is the
+    # largest copy dispatch (the 1 GiB copy at the end of the run)
+    counters = {}
+    for name in ("fetch", "write", "rdreq"):
+        per = {}
+        for r in _read_csv(os.path.join(outdir, name, "p_counter_collection.csv")):
+            k = _kernel_key(r["Kernel_Name"])
+            if k is None:
+                continue
+            per.setdefault((k, r["Counter_Name"]), {}).setdefault(r["Dispatch_Id"], 0.0)
+            per[(k, r["Counter_Name"])][r["Dispatch_Id"]] += float(r["Counter_Value"])
+        for (k, c), disp in per.items():
+            vals = list(disp.values())
+            counters[(k, c)] = {"mean": sum(vals) / len(vals), "max": max(vals), "n": len(vals)}
+    copy_bytes = float(1 << 30)
+    f_fetch = copy_bytes / (counters[("copy", "FETCH_SIZE")]["max"] * 1024.0)
+    f_write = copy_bytes / (counters[("copy", "WRITE_SIZE")]["max"] * 1024.0)
+
+    def rd_bytes(k, agg="mean"):
+        try:
+            return sum(sz * counters[(k, "TCC_EA0_RDREQ_%dB_sum" % sz)][agg] for sz in (32, 64, 128))
+        except KeyError:
+            return None
+
+    copy_rd = rd_bytes("copy", "max")
+    storage = PROFILE_VARIANTS[variant].split()[-1]
+    fb = 4 if storage == "f32" else 2
+    n_r, n_z = w.layer_cells
+    entry = {}
+    lines = ["rocprofv3 summary: %s, workload %s" % (variant, w.name), "",
+             "Commands (from the repository root; the outputs land under %s):" % outdir]
+    lines += ["  %s" % cmds[n] for n, _ in PROFILE_PASSES]
+    lines += ["", "Calibration with a 1 GiB device-to-device copy (1073741824 B read, "
+              "1073741824 B written):",
+              "  FETCH_SIZE read %.0f KiB -> factor %.4f" % (counters[("copy", "FETCH_SIZE")]["max"], f_fetch),
+              "  WRITE_SIZE read %.0f KiB -> factor %.4f" % (counters[("copy", "WRITE_SIZE")]["max"], f_write)]
+    if copy_rd:
+        lines.append("  read requests by size (32/64/128 B) sum to %.0f B = %.4f x the copy's reads"
+                     % (copy_rd, copy_rd / copy_bytes))
+    if "copy" in stats:
+        c = stats["copy"]
+        lines.append("  copy kernel: %d dispatches, max %.1f us (%.2f TB/s for the 2 GiB moved)"
+                     % (c["calls"], c["max_ns"] / 1e3, 2 * copy_bytes / c["max_ns"] / 1e3))
+    lines += ["", "%-10s %6s %12s %12s %12s %14s %14s %14s %10s"
+              % ("kernel", "calls", "avg_us", "min_us", "max_us", "alg_B/launch", "fetch_B", "write_B",
+                 "HBM_TB/s")]
+    for k in ("velocity", "stress", "fused", "inject", "record", "rescale"):
+        if k not in stats:
+            continue
+        st = stats[k]
+        avg_ns = st["total_ns"] / st["calls"]
+        fe = counters.get((k, "FETCH_SIZE"))
+        wr = counters.get((k, "WRITE_SIZE"))
+        fetch_b = fe["mean"] * 1024.0 * f_fetch if fe else float("nan")
+        write_b = wr["mean"] * 1024.0 * f_write if wr else float("nan")
+        alg = algorithmic_bytes(k, w, n_r, n_z, fb) if k in ("velocity", "stress", "fused") else float("nan")
+        lines.append("%-10s %6d %12.1f %12.1f %12.1f %14.4g %14.4g %14.4g %10.3f"
+                     % (k, st["calls"], avg_ns / 1e3, st["min_ns"] / 1e3, st["max_ns"] / 1e3, alg,
+                        fetch_b, write_b, (fetch_b + write_b) / avg_ns / 1e3))
+        if k in ("velocity", "stress", "fused") and fe and wr:
+            rd = rd_bytes(k)
+            entry[k] = {"bytes_per_launch": fetch_b + write_b, "fetch_bytes": fetch_b,
+                        "write_bytes": write_b, "alg_bytes": alg, "avg_ns": avg_ns,
+                        "fetch_factor": f_fetch, "write_factor": f_write,
+                        "read_request_bytes": rd * copy_bytes / copy_rd if rd and copy_rd else None,
+                        "workload": w.name, "source_hash": kernel_source_hash()}
+    if live:
+        lines += ["", "Same run, HIP events recorded by the benchmark around each launch "
+                  "(warm-up excluded): " + ", ".join(
+                      "%s %.1f us" % (k, v[0] * 1e3 / v[1]) for k, v in live.get("kernel_ms", {}).items()),
+                  "Benchmark line of that run: %s Gcell-updates/s, %s ms per step"
+                  % (live.get("value"), live.get("ms_per_step"))]
+    if any(e.get("read_request_bytes") for e in entry.values()):
+        lines += ["", "Reads from the request-size pass, scaled by the copy's reading: "
+                  + ", ".join("%s %.4g B" % (k, e["read_request_bytes"]) for k, e in entry.items()
+                              if e.get("read_request_bytes"))]
+    lines.append("")
+    kern = "fused_step_%s" % storage if "fused" in entry else "velocity_stress_%s" % variant
+    out = os.path.join(ROOT, "profiles", "%s_production.txt" % kern)
+    open(out, "w").write("\n".join(lines))
+    try:
+        d = json.load(open(PMC_FILE))
+    except (OSError, ValueError):
+        d = {}
+    d[variant] = entry
+    with open(PMC_FILE, "w") as f:
+        json.dump(d, f, indent=1, sort_keys=True)
+    print("\n".join(lines))
 
 
 def cpu_baseline(w, target_s: float):
@@ -106,6 +264,67 @@ def cpu_baseline(w, target_s: float):
                       "no z layer), %d FP64 steps in %.1f s" % (w.nr, w.nt, nzs, steps, el)}
 
 
+def run_steps(w, storage: str, path: str, warmup: int, steps: int):
+    """Set up workload w, bind it, run warmup + timed steps; returns
+    (seconds for the timed steps, {kernel: (ms, launches)}, traces)."""
+    import numpy as np
+    import torch
+    from paper_2302_13907_amd import cwell
+    total = warmup + steps
+    s = cwell.Sim(w.nr, w.nt, w.nz, w.dr, w.dz)
+    if w.rock_jitter == 0:
+        s.set_material(*w.medium_rz())
+    else:
+        s.set_material(*w.medium())
+    s.set_pml(w.npml, w.npml, w.pml_rc, math.pi * w.f0)
+    dt = w.cfl_fraction * s.cfl_dt()
+    s.set_dt(dt)
+    s.add_source("volume", 0, -1, w.src_k, cwell.ricker(w.f0, (np.arange(total) + 0.5) * dt))
+    for k in w.rec_k:
+        s.add_receiver("pressure", 0, -1, k)
+    s.set_trace_capacity(total)
+    s.set_path(path)
+    s.set_storage(storage)
+    log("binding %.2f GB workspace (%s storage)" % (s.workspace_bytes() / 1e9, storage))
+    s.bind("cuda:0")
+    log("warm-up %d steps" % warmup)
+    s.step(warmup)
+    s.sync()
+    torch.cuda.synchronize()
+    s.profile(True)
+    log("timing %d steps" % steps)
+    t0 = time.perf_counter()
+    s.step(steps)
+    s.sync()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    times = {k: s.kernel_time(k) for k in ("velocity", "stress", "fused", "inject", "record")}
+    s.profile(False)
+    tr = s.traces()
+    s.close()
+    del s
+    torch.cuda.empty_cache()
+    if not np.all(np.isfinite(tr)):
+        raise RuntimeError("non-finite traces (%s storage)" % storage)
+    return el, times, tr
+
+
+def storage_forms(path: str, warmup: int = 10, steps: int = 100):
+    """Gcell-updates/s of the mixed-precision workload with float32, float16
+    and bfloat16 field storage (float32 arithmetic in every case)."""
+    from paper_2302_13907_amd import inputs
+    w = inputs.mixed_precision_case()
+    log("storage forms on %s" % w.name)
+    res = {"workload": w.name, "steps": steps, "warmup": warmup}
+    for st in ("f32", "f16", "bf16"):
+        el, times, _ = run_steps(w, st, path, warmup, steps)
+        res[st] = {"value": round(w.cells * steps / el / 1e9, 3),
+                   "ms_per_step": round(el / steps * 1e3, 4)}
+    for st in ("f16", "bf16"):
+        res[st]["speedup_vs_f32"] = round(res[st]["value"] / res["f32"]["value"], 3)
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -121,55 +340,40 @@ def main():
     ap.add_argument("--copy-gib", type=float, default=0.0,
                     help="after the run, copy this many GiB device-to-device once (a known-size "
                          "reference dispatch for hardware byte counters)")
+    ap.add_argument("--no-storage-forms", action="store_true",
+                    help="skip the float32 / float16 / bfloat16 storage comparison on the "
+                         "192 x 96 x 4096 mixed-precision workload")
+    ap.add_argument("--print-profile-commands", nargs=2, metavar=("VARIANT", "OUTDIR"),
+                    help="print the rocprofv3 commands that profile VARIANT (%s), one "
+                         "'name command' per line, and exit" % ", ".join(PROFILE_VARIANTS))
+    ap.add_argument("--ingest-profiles", nargs=2, metavar=("VARIANT", "OUTDIR"),
+                    help="summarise the outputs of those commands into profiles/ and exit")
     args = ap.parse_args()
+    if args.print_profile_commands:
+        for name, cmd in profile_commands(*args.print_profile_commands):
+            print(name, cmd)
+        return
+    if args.ingest_profiles:
+        ingest_profiles(*args.ingest_profiles)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(the z-slab decomposition is a design, not code); run with --gpus 1",
               file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
-    from paper_2302_13907_amd import cwell, inputs
+    from paper_2302_13907_amd import inputs
 
     if not torch.cuda.is_available():
         print("no HIP device visible", file=sys.stderr)
         sys.exit(1)
     w = inputs.production_case() if args.workload == "production" else inputs.parity_case()
-    total = args.warmup + args.steps
-    log("workload %s: building the medium" % w.name)
-    s = cwell.Sim(w.nr, w.nt, w.nz, w.dr, w.dz)
-    if w.rock_jitter == 0:
-        s.set_material(*w.medium_rz())
-    else:
-        s.set_material(*w.medium())
-    s.set_pml(w.npml, w.npml, w.pml_rc, math.pi * w.f0)
-    dt = w.cfl_fraction * s.cfl_dt()
-    s.set_dt(dt)
-    s.add_source("volume", 0, -1, w.src_k, cwell.ricker(w.f0, (np.arange(total) + 0.5) * dt))
-    for k in w.rec_k:
-        s.add_receiver("pressure", 0, -1, k)
-    s.set_trace_capacity(total)
-    s.set_path(args.path)
-    s.set_storage(args.storage)
-    log("binding %.2f GB workspace" % (s.workspace_bytes() / 1e9))
-    s.bind("cuda:0")
-    log("warm-up %d steps" % args.warmup)
-    s.step(args.warmup)
-    s.sync()
-    torch.cuda.synchronize()
-    s.profile(True)
-    log("timing %d steps" % args.steps)
-    t0 = time.perf_counter()
-    s.step(args.steps)
-    s.sync()
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    times = {k: s.kernel_time(k) for k in ("velocity", "stress", "fused", "inject", "record")}
-    s.profile(False)
-    tr = s.traces()
-    if not np.all(np.isfinite(tr)):
-        print("non-finite traces", file=sys.stderr)
+    log("workload %s" % w.name)
+    try:
+        el, times, _ = run_steps(w, args.storage, args.path, args.warmup, args.steps)
+    except RuntimeError as e:
+        print(str(e), file=sys.stderr)
         sys.exit(1)
     value = w.cells * args.steps / el / 1e9
     dom = max(("velocity", "stress", "fused"), key=lambda k: times[k][0])
@@ -179,7 +383,11 @@ def main():
     fb = 4 if args.storage == "f32" else 2
     alg = algorithmic_bytes(dom, w, n_r, n_z, fb)
     achieved = alg / avg_s / 1e9
-    traffic = measured_traffic(dom, w.name)
+    variant = "%s_%s" % ("fused" if dom == "fused" else "two_pass", args.storage)
+    traffic = measured_traffic(variant, dom, w.name)
+    # the whole step against the single-pass floor: every field read and written once,
+    # the moduli read once, each layer memory variable read and written once
+    step_bytes = algorithmic_bytes("fused", w, n_r, n_z, fb) / w.cells
     out = {
         "metric": METRIC,
         "value": round(value, 3),
@@ -201,11 +409,11 @@ def main():
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "alg_bytes_per_launch": alg,
                      "avg_launch_ms": round(avg_s * 1e3, 4)},
+        "step_roofline": {"bytes_per_cell_update": round(step_bytes, 2),
+                          "achieved": round(value * step_bytes, 1), "peak": HBM_PEAK_GBS,
+                          "unit": "GB/s", "frac": round(value * step_bytes / HBM_PEAK_GBS, 4)},
         "kernel_ms": {k: [round(v[0], 3), v[1]] for k, v in times.items() if v[1]},
     }
-    s.close()
-    del s
-    torch.cuda.empty_cache()
     if args.copy_gib > 0:
         nb = int(args.copy_gib * (1 << 30))
         src = torch.ones(nb // 4, dtype=torch.float32, device="cuda:0")
@@ -216,6 +424,8 @@ def main():
         out["copy_reference_bytes"] = nb
         del src, dst
         torch.cuda.empty_cache()
+    if not args.no_storage_forms:
+        out["storage_forms"] = storage_forms(args.path)
     if not args.no_cpu_baseline:
         log("CPU baseline: FP64 oracle for about %.0f s" % args.cpu_seconds)
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)

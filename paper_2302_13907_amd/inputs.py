@@ -178,6 +178,18 @@ def production_case() -> Workload:
                     z_top=(nz // 2) * 2e-3, ramp=0.3)
 
 
+def mixed_precision_case() -> Workload:
+    """192 x 96 x 4096 cells of 5 mm, 3000 steps, 20-cell layer, 15 kHz axis
+    source at k = 1024, 32 axis receivers every 20 mm below it, cement top at
+    k = 2048 with a shear ramp whose length is drawn uniformly from
+    [0.05, 0.5] m (seed 3)."""
+    ramp = float(np.random.default_rng(3).uniform(0.05, 0.5))
+    return Workload("cased-well 192x96x4096 (5 mm), 3000 steps", 192, 96, 4096, 5e-3, 5e-3,
+                    steps=3000, npml=20, f0=15e3, src_k=1024,
+                    rec_k=[1024 + 4 * (m + 1) for m in range(32)],
+                    z_top=2048 * 5e-3, ramp=ramp)
+
+
 def scaled_case(nr: int, nt: int, nz: int, steps: int = 50) -> Workload:
     """The production medium on a smaller grid (same 2 mm cells and layout
     fractions); used for parity at sizes the oracle finishes quickly."""
