@@ -32,7 +32,7 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes(kernel: str, w, n_r: int, n_z: int, fb: int = 4) -> float:
+def algorithmic_bytes(kernel: str, w, n_r: int, n_z: int, fb: int = 4, axisym: bool = False) -> float:
     """Algorithmic HBM bytes of one launch of `kernel` over workload w.
 
     One cell-update reads the 9 fields and the 3 moduli (rho, lambda, mu) and
@@ -43,14 +43,16 @@ def algorithmic_bytes(kernel: str, w, n_r: int, n_z: int, fb: int = 4) -> float:
     separate stress pass 3 velocities + 6 stresses in, 6 out, lambda and mu
     (68 B, the other 6 radial / 3 z variables).  With fb-byte field storage
     the field terms scale by fb/4 (the moduli and layer memory stay
-    float32)."""
+    float32).  A medium that does not vary along theta is stored once per
+    (ring, depth): its bytes per cell-update are divided by Nt."""
     n = w.cells
+    m = 1.0 / w.nt if axisym else 1.0
     if kernel == "fused":
-        return (18 * fb + 12.0) * n + 96.0 * n_r + 48.0 * n_z
+        return (18 * fb + 12.0 * m) * n + 96.0 * n_r + 48.0 * n_z
     if kernel == "velocity":
-        return (12 * fb + 4.0) * n + 48.0 * n_r + 24.0 * n_z
+        return (12 * fb + 4.0 * m) * n + 48.0 * n_r + 24.0 * n_z
     if kernel == "stress":
-        return (15 * fb + 8.0) * n + 48.0 * n_r + 24.0 * n_z
+        return (15 * fb + 8.0 * m) * n + 48.0 * n_r + 24.0 * n_z
     raise ValueError(kernel)
 
 
@@ -199,7 +201,8 @@ def ingest_profiles(variant: str, outdir: str):
         wr = counters.get((k, "WRITE_SIZE"))
         fetch_b = fe["mean"] * 1024.0 * f_fetch if fe else float("nan")
         write_b = wr["mean"] * 1024.0 * f_write if wr else float("nan")
-        alg = algorithmic_bytes(k, w, n_r, n_z, fb) if k in ("velocity", "stress", "fused") else float("nan")
+        alg = (algorithmic_bytes(k, w, n_r, n_z, fb, w.rock_jitter == 0)
+               if k in ("velocity", "stress", "fused") else float("nan"))
         lines.append("%-10s %6d %12.1f %12.1f %12.1f %14.4g %14.4g %14.4g %10.3f"
                      % (k, st["calls"], avg_ns / 1e3, st["min_ns"] / 1e3, st["max_ns"] / 1e3, alg,
                         fetch_b, write_b, (fetch_b + write_b) / avg_ns / 1e3))
@@ -333,7 +336,7 @@ def main():
     ap.add_argument("--workload", choices=("production", "parity"), default="production")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--path", choices=("auto", "fused", "two-pass"), default="auto",
+    ap.add_argument("--path", choices=("auto", "fused", "two-pass", "march"), default="auto",
                     help="kernel path of the step")
     ap.add_argument("--storage", choices=("f32", "f16", "bf16"), default="f32",
                     help="field storage (arithmetic is float32 in every case)")
@@ -381,13 +384,14 @@ def main():
     avg_s = ms / 1e3 / max(launches, 1)
     n_r, n_z = w.layer_cells
     fb = 4 if args.storage == "f32" else 2
-    alg = algorithmic_bytes(dom, w, n_r, n_z, fb)
+    axisym = w.rock_jitter == 0          # the medium is then stored once per (ring, depth)
+    alg = algorithmic_bytes(dom, w, n_r, n_z, fb, axisym)
     achieved = alg / avg_s / 1e9
     variant = "%s_%s" % ("fused" if dom == "fused" else "two_pass", args.storage)
     traffic = measured_traffic(variant, dom, w.name)
     # the whole step against the single-pass floor: every field read and written once,
     # the moduli read once, each layer memory variable read and written once
-    step_bytes = algorithmic_bytes("fused", w, n_r, n_z, fb) / w.cells
+    step_bytes = algorithmic_bytes("fused", w, n_r, n_z, fb, axisym) / w.cells
     out = {
         "metric": METRIC,
         "value": round(value, 3),
@@ -403,6 +407,7 @@ def main():
         "storage": args.storage,
         "data": "synthetic",
         "config": {"workload": w.name, "cells": w.cells, "grid": [w.nr, w.nt, w.nz],
+                   "medium": "axisymmetric" if axisym else "3-D",
                    "cell_m": w.dr, "layer_cells": w.npml, "receivers": len(w.rec_k),
                    "kernel_path": "two-pass" if dom != "fused" else "fused"},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),

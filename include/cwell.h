@@ -187,16 +187,25 @@ cw_status cw_steps_done(const cw_sim *s, int64_t *n);
 enum { CW_STORE_F32 = 0, CW_STORE_F16, CW_STORE_BF16 };
 cw_status cw_set_storage(cw_sim *s, int32_t storage);
 
-/* Kernel path of cw_step.  CW_PATH_TWO_PASS: a velocity launch and a
-   stress launch per step (plus source launches), one thread per cell, any
-   number of sources.  CW_PATH_FUSED: one launch per step that marches each
-   theta x depth tile outward through the rings and reads the state, the
-   medium and the layer memory once (float32 storage only, at most 12
-   source injections -- 3 per volume source, 2 per torsion source, 1 per
-   force -- and nr <= 2048).  CW_PATH_AUTO (default): the path measured
-   fastest on MI355X, the two-pass one.  Both compute the same scheme;
-   results agree to float32 rounding. */
-enum { CW_PATH_AUTO = 0, CW_PATH_TWO_PASS, CW_PATH_FUSED };
+/* Kernel path of cw_step.  All paths compute the same scheme; results
+   agree to float32 rounding.
+   CW_PATH_TWO_PASS: a velocity launch and a stress launch per step (plus
+   source launches), any number of sources and any storage; one workgroup
+   per (ring, theta row) depth segment, 4 depth cells per thread when nz is
+   a multiple of 4, one cell per thread otherwise.
+   CW_PATH_MARCH: the same two launches in radial-march form (when nz is a
+   multiple of 4 and a ring of one array is under 2 GiB; otherwise as
+   CW_PATH_TWO_PASS): each wavefront owns one theta row and 256 depth cells
+   and walks outward through a range of rings, keeping the radial
+   neighbours in registers.  Measured slower than CW_PATH_TWO_PASS on
+   MI355X; kept for comparison.
+   CW_PATH_FUSED: one launch per step that marches each theta x depth tile
+   outward through the rings and reads the state, the medium and the layer
+   memory once (float32 storage only, at most 12 source injections -- 3 per
+   volume source, 2 per torsion source, 1 per force -- and nr <= 2048).
+   CW_PATH_AUTO (default): the path measured fastest on MI355X,
+   CW_PATH_TWO_PASS. */
+enum { CW_PATH_AUTO = 0, CW_PATH_TWO_PASS, CW_PATH_FUSED, CW_PATH_MARCH };
 cw_status cw_set_path(cw_sim *s, int32_t path);
 
 /* Kernel timing.  With enable = 1, cw_step brackets every launch of the

@@ -82,6 +82,8 @@ struct cw_sim {
   uint64_t ws_bytes = 0;
   float *fields[2][NF] = {};
   float *d_rho = nullptr, *d_lam = nullptr, *d_mu = nullptr;
+  bool med_rz = false;          // medium identical along theta: stored [nr][nz]
+  size_t nm = 0;                // values per medium array (n, or nr nz)
   float *d_inv_rc = nullptr, *d_inv_rf = nullptr, *d_tab_r = nullptr, *d_tab_z = nullptr;
   float *psi_r[2][NPSI_R] = {};  // two copies: the fused step reads one, writes the other
   float *psi_z[2][NPSI_Z] = {};
@@ -146,7 +148,7 @@ Layout layout(const cw_sim *s)
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off += align256(bytes); return o; };
   L.fields = take(2 * NF * s->n * field_bytes(s));
-  L.material = take(3 * s->n * sizeof(float));
+  L.material = take(3 * s->nm * sizeof(float));
   L.metric = take(2 * (size_t)s->nr * sizeof(float));
   L.tabr = take(NTAB_R * (size_t)s->nr * sizeof(float));
   L.tabz = take(NTAB_Z * (size_t)s->nz * sizeof(float));
@@ -257,6 +259,8 @@ StepArgs step_args(const cw_sim *s, int in, int out)
   a.inv_dth = (float)(1.0 / s->dth);
   a.inv_rc = s->d_inv_rc; a.inv_rf = s->d_inv_rf;
   a.rho = s->d_rho; a.lam = s->d_lam; a.mu = s->d_mu;
+  a.m_ring = s->med_rz ? (size_t)s->nz : (size_t)s->nt * s->nz;
+  a.m_row = s->med_rz ? 0 : s->nz;
   for (int q = 0; q < NF; q++) { a.in[q] = s->fields[in][q]; a.out[q] = s->fields[out][q]; }
   for (int q = 0; q < NPSI_R; q++) a.psi_r[q] = s->psi_r[s->psi_cur][q];
   for (int q = 0; q < NPSI_Z; q++) a.psi_z[q] = s->psi_z[s->psi_cur][q];
@@ -340,6 +344,12 @@ cw_status cw_create(const cw_grid *g, cw_sim **out)
 
 void cw_destroy(cw_sim *s) { delete s; }
 
+// index of cell (i, j, k) in the stored medium arrays
+static size_t mat_index(const cw_sim *s, int i, int j, int k)
+{
+  return s->med_rz ? (size_t)i * s->nz + k : ((size_t)i * s->nt + j) * s->nz + k;
+}
+
 static cw_status set_medium(cw_sim *s, const double *rho, const double *lam, const double *mu, bool rz)
 {
   cw_status st;
@@ -347,23 +357,44 @@ static cw_status set_medium(cw_sim *s, const double *rho, const double *lam, con
   if (!rho || !lam || !mu) return fail(CW_ERR_ARG, "null medium array");
   const size_t nin = rz ? (size_t)s->nr * s->nz : s->n;
   if ((st = check_medium(nin, rho, lam, mu)) != CW_OK) return st;
+  // a 3-D medium identical along theta (bitwise) is stored like an axisymmetric one:
+  // the kernels then read [nr][nz] tables, which stay in cache, instead of full arrays
+  bool axisym = rz;
+  if (!rz) {
+    axisym = true;
+    for (int i = 0; i < s->nr && axisym; i++)
+      for (int j = 1; j < s->nt && axisym; j++) {
+        const size_t a = (size_t)i * s->nt * s->nz, b = ((size_t)i * s->nt + j) * s->nz;
+        for (int k = 0; k < s->nz; k++)
+          if (rho[a + k] != rho[b + k] || lam[a + k] != lam[b + k] || mu[a + k] != mu[b + k]) {
+            axisym = false;
+            break;
+          }
+      }
+  }
+  const size_t nm = axisym ? (size_t)s->nr * s->nz : s->n;
   try {
-    s->rho.resize(s->n); s->lam.resize(s->n); s->mu.resize(s->n);
+    s->rho.assign(nm, 0.0f); s->lam.assign(nm, 0.0f); s->mu.assign(nm, 0.0f);
   } catch (...) {
     return fail(CW_ERR_NOMEM, "out of host memory for the medium");
   }
   double vmax = 0;
   for (size_t p = 0; p < nin; p++) vmax = std::max(vmax, std::sqrt((lam[p] + 2 * mu[p]) / rho[p]));
+  // source row: the input's (i, 0, k) for an axisymmetric store (rz input: (i, k))
+  const int nrow = axisym ? 1 : s->nt;
+  const size_t in_ring = rz ? (size_t)s->nz : (size_t)s->nt * s->nz;
   for (int i = 0; i < s->nr; i++)
-    for (int j = 0; j < s->nt; j++) {
-      const size_t dst = ((size_t)i * s->nt + j) * s->nz;
-      const size_t src = rz ? (size_t)i * s->nz : dst;
+    for (int j = 0; j < nrow; j++) {
+      const size_t dst = ((size_t)i * nrow + j) * s->nz;
+      const size_t src = (size_t)i * in_ring + (size_t)j * s->nz;
       for (int k = 0; k < s->nz; k++) {
         s->rho[dst + k] = (float)rho[src + k];
         s->lam[dst + k] = (float)lam[src + k];
         s->mu[dst + k] = (float)mu[src + k];
       }
     }
+  s->med_rz = axisym;
+  s->nm = nm;
   s->vp_max = vmax;
   s->dt_cfl = courant(s, rho, lam, mu, rz);
   s->have_material = true;
@@ -492,8 +523,8 @@ cw_status cw_bind(cw_sim *s, void *workspace, uint64_t bytes, void *stream)
   s->d_scl = (float *)(w + L.scales);
   s->d_maxabs = (unsigned *)(s->d_scl + 3 * NF);
   s->d_rho = (float *)(w + L.material);
-  s->d_lam = s->d_rho + s->n;
-  s->d_mu = s->d_lam + s->n;
+  s->d_lam = s->d_rho + s->nm;
+  s->d_mu = s->d_lam + s->nm;
   s->d_inv_rc = (float *)(w + L.metric);
   s->d_inv_rf = s->d_inv_rc + s->nr;
   s->d_tab_r = (float *)(w + L.tabr);
@@ -534,10 +565,9 @@ cw_status cw_bind(cw_sim *s, void *workspace, uint64_t bytes, void *stream)
         // buoyancy at the node: 2 / (rho + rho of the next cell in r or z, clamped);
         // a ring source takes the ring's first cell, the medium being that of the caller
         const int jj = src.j < 0 ? 0 : src.j;
-        const size_t p = ((size_t)src.i * s->nt + jj) * s->nz + src.k;
+        const size_t p = mat_index(s, src.i, jj, src.k);
         const int i1 = std::min(src.i + 1, s->nr - 1), k1 = std::min(src.k + 1, s->nz - 1);
-        const size_t p1 = t.field == VR ? ((size_t)i1 * s->nt + jj) * s->nz + src.k
-                                        : ((size_t)src.i * s->nt + jj) * s->nz + k1;
+        const size_t p1 = t.field == VR ? mat_index(s, i1, jj, src.k) : mat_index(s, src.i, jj, k1);
         scale = 2.0 / ((double)s->rho[p] + (double)s->rho[p1]);
       }
       Inject e{};
@@ -553,9 +583,9 @@ cw_status cw_bind(cw_sim *s, void *workspace, uint64_t bytes, void *stream)
   }
   s->ninject = (int)s->inject_host.size();
 
-  HIPCHK(hipMemcpyAsync(s->d_rho, s->rho.data(), s->n * sizeof(float), hipMemcpyHostToDevice, s->stream));
-  HIPCHK(hipMemcpyAsync(s->d_lam, s->lam.data(), s->n * sizeof(float), hipMemcpyHostToDevice, s->stream));
-  HIPCHK(hipMemcpyAsync(s->d_mu, s->mu.data(), s->n * sizeof(float), hipMemcpyHostToDevice, s->stream));
+  HIPCHK(hipMemcpyAsync(s->d_rho, s->rho.data(), s->nm * sizeof(float), hipMemcpyHostToDevice, s->stream));
+  HIPCHK(hipMemcpyAsync(s->d_lam, s->lam.data(), s->nm * sizeof(float), hipMemcpyHostToDevice, s->stream));
+  HIPCHK(hipMemcpyAsync(s->d_mu, s->mu.data(), s->nm * sizeof(float), hipMemcpyHostToDevice, s->stream));
   HIPCHK(hipMemcpyAsync(s->d_inv_rc, s->inv_rc.data(), s->nr * sizeof(float), hipMemcpyHostToDevice, s->stream));
   HIPCHK(hipMemcpyAsync(s->d_inv_rf, s->inv_rf.data(), s->nr * sizeof(float), hipMemcpyHostToDevice, s->stream));
   HIPCHK(hipMemcpyAsync(s->d_tab_r, s->tab_r.data(), s->tab_r.size() * sizeof(float), hipMemcpyHostToDevice, s->stream));
@@ -595,7 +625,19 @@ cw_status cw_step(cw_sim *s, int64_t nsteps)
                 s->ninject, s->nr);
   FusedArgs f{};
   if (fused) fused_tiles(s->nt, s->nz, &f.own_rows, &f.ntile_z);
+  // two-pass kernel form: one workgroup per column segment (default) or the
+  // radial march, both with 4 depth cells per thread; one thread per cell
+  // when nz is not a multiple of 4
   const bool vec = kUseVec && vec_applies(s->nz);
+  const bool march = vec && s->path == CW_PATH_MARCH && march_applies(s->nt, s->nz);
+  auto velocity = [&](const StepArgs &a) {
+    return march ? launch_velocity_march(a, s->storage, s->stream)
+                 : vec ? launch_velocity_vec(a, s->storage, s->stream) : launch_velocity_basic(a, s->storage, s->stream);
+  };
+  auto stress = [&](const StepArgs &a) {
+    return march ? launch_stress_march(a, s->storage, s->stream)
+                 : vec ? launch_stress_vec(a, s->storage, s->stream) : launch_stress_basic(a, s->storage, s->stream);
+  };
   for (int64_t t = 0; t < nsteps; t++) {
     const StepArgs a = step_args(s, s->cur, 1 - s->cur);
     const int64_t n = s->nstep;
@@ -608,6 +650,9 @@ cw_status cw_step(cw_sim *s, int64_t nsteps)
       f.in = s->fields[s->cur][0];
       f.out = s->fields[1 - s->cur][0];
       f.med = s->d_rho;
+      f.m_n = s->nm;
+      f.m_ring = a.m_ring;
+      f.m_row = a.m_row;
       f.psi_r_in = s->psi_r[s->psi_cur][0]; f.psi_r_out = s->psi_r[1 - s->psi_cur][0];
       f.psi_z_in = s->psi_z[s->psi_cur][0]; f.psi_z_out = s->psi_z[1 - s->psi_cur][0];
       f.inv_rc = s->d_inv_rc; f.inv_rf = s->d_inv_rf; f.tab_r = s->d_tab_r; f.tab_z = s->d_tab_z;
@@ -622,16 +667,10 @@ cw_status cw_step(cw_sim *s, int64_t nsteps)
       if ((st = timed(s, CW_K_FUSED, [&] { return launch_fused(f, s->stream); })) != CW_OK) return st;
       s->psi_cur = 1 - s->psi_cur;
     } else {
-      if ((st = timed(s, CW_K_VELOCITY, [&] {
-            return vec ? launch_velocity_vec(a, s->storage, s->stream) : launch_velocity_basic(a, s->storage, s->stream);
-          })) != CW_OK)
-        return st;
+      if ((st = timed(s, CW_K_VELOCITY, [&] { return velocity(a); })) != CW_OK) return st;
       if (s->ninject && (st = timed(s, CW_K_INJECT, [&] {
             return launch_inject(s->d_inject, s->ninject, 0, n, a, s->storage, s->stream); })) != CW_OK) return st;
-      if ((st = timed(s, CW_K_STRESS, [&] {
-            return vec ? launch_stress_vec(a, s->storage, s->stream) : launch_stress_basic(a, s->storage, s->stream);
-          })) != CW_OK)
-        return st;
+      if ((st = timed(s, CW_K_STRESS, [&] { return stress(a); })) != CW_OK) return st;
       if (s->ninject && (st = timed(s, CW_K_INJECT, [&] {
             return launch_inject(s->d_inject, s->ninject, 1, n, a, s->storage, s->stream); })) != CW_OK) return st;
     }
@@ -789,7 +828,7 @@ cw_status cw_set_storage(cw_sim *s, int32_t storage)
 cw_status cw_set_path(cw_sim *s, int32_t path)
 {
   if (!s) return fail(CW_ERR_ARG, "null simulation");
-  if (path < CW_PATH_AUTO || path > CW_PATH_FUSED) return fail(CW_ERR_ARG, "bad path %d", path);
+  if (path < CW_PATH_AUTO || path > CW_PATH_MARCH) return fail(CW_ERR_ARG, "bad path %d", path);
   s->path = path;
   return CW_OK;
 }

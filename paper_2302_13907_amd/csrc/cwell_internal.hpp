@@ -35,7 +35,11 @@ struct StepArgs {
   float dt, inv_dr, inv_dz, inv_dth;
   const float *inv_rc;      // 1 / r_i  [nr]
   const float *inv_rf;      // 1 / R_i  [nr]
+  // medium at cell (i, j, k): index i m_ring + j m_row + k (m_row = 0 for a
+  // medium stored once per (ring, depth) because it does not vary along theta)
   const float *rho, *lam, *mu;
+  size_t m_ring;
+  int m_row;
   const float *in[NF];      // state at level n (v^{n-1/2}, sigma^n)
   float *out[NF];           // state at level n+1
   float *psi_r[NPSI_R];     // [npr][nt][nz]
@@ -84,6 +88,33 @@ __device__ __forceinline__ int xcd_tile_remap(int b, int G)
 #endif
 __device__ __forceinline__ int xcd_tile(int b, int G) { return CW_XCD_REMAP ? xcd_tile_remap(b, G) : b; }
 
+// Column order of the column-form two-pass kernels.  A column is the depth
+// line of one (ring i, azimuth j) pair; the kernels read the columns next to
+// their own in radius and azimuth as well.  With kStripW > 0 columns are
+// visited in strips of kStripW azimuth rows, ring by ring within a strip,
+// which shortens the distance between the two reads of a radial neighbour
+// column.  Measured on MI355X at 256 x 128 x 8192: strips of 8 to 32 rows
+// fetch up to 11 % fewer bytes but run 20-40 % slower than whole rings
+// (kStripW = 0), which keep the working set of the chip in a few megabytes
+// of each array; whole rings are the default.
+#ifndef CW_STRIP_W
+#define CW_STRIP_W 0
+#endif
+constexpr int kStripW = CW_STRIP_W;
+__device__ __forceinline__ void strip_column(int c, int nr, int nt, int &i, int &j)
+{
+  if (kStripW <= 0 || kStripW >= nt) {
+    i = c / nt;
+    j = c - i * nt;
+    return;
+  }
+  const int per = nr * kStripW;
+  const int s = c / per, rem = c - s * per;
+  const int w = nt - s * kStripW < kStripW ? nt - s * kStripW : kStripW;
+  i = rem / w;
+  j = s * kStripW + (rem - i * w);
+}
+
 // One injection of the current step, as the fused kernel applies it.
 struct InjectStep {
   int field, i, j, k, phase;
@@ -104,6 +135,8 @@ struct FusedArgs {
   const float *in;
   float *out;
   const float *med;
+  size_t m_n, m_ring;       // medium: stride between rho, lambda, mu; values per ring
+  int m_row;                //   values per theta row (0 when the medium does not vary along theta)
   const float *psi_r_in;
   float *psi_r_out;
   const float *psi_z_in;
@@ -133,6 +166,9 @@ hipError_t launch_rescale(float *scl_written, float *scl_next, unsigned *maxabs,
 constexpr int kF16TargetExp = 11;   // scaled float16 maxima land in [2^10, 2^11)
 // depth-vectorized two-pass kernels (4 cells per thread), when nz % 4 == 0
 bool vec_applies(int nz);
+bool march_applies(int nt, int nz);
+hipError_t launch_velocity_march(const StepArgs &a, int storage, hipStream_t stream);
+hipError_t launch_stress_march(const StepArgs &a, int storage, hipStream_t stream);
 hipError_t launch_velocity_vec(const StepArgs &a, int storage, hipStream_t stream);
 hipError_t launch_stress_vec(const StepArgs &a, int storage, hipStream_t stream);
 

@@ -29,6 +29,12 @@ __device__ __forceinline__ size_t at(const StepArgs &a, int i, int j, int k)
   return ((size_t)i * a.nt + j) * a.nz + k;
 }
 
+// index of cell (i, j, k) in the medium arrays
+__device__ __forceinline__ size_t mat(const StepArgs &a, int i, int j, int k)
+{
+  return (size_t)i * a.m_ring + (size_t)j * a.m_row + k;
+}
+
 template <class S>
 __device__ __forceinline__ float ld(const float *f, float s, const StepArgs &a, int i, int j, int k)
 {
@@ -79,9 +85,10 @@ template <class S>
 __global__ void __launch_bounds__(256) k_velocity_basic(StepArgs a, int nbx)
 {
   const int t = xcd_tile(blockIdx.x, gridDim.x);
-  const int bx = t % nbx, ij = t / nbx;
+  const int bx = t % nbx;
   const int k = bx * 256 + threadIdx.x;
-  const int j = ij % a.nt, i = ij / a.nt;
+  int i, j;
+  strip_column(t / nbx, a.nr, a.nt, i, j);
   const bool live = k < a.nz;
   const int kk = live ? k : a.nz - 1;              // dead lanes compute on a valid cell, store nothing
   const int jm = j == 0 ? a.nt - 1 : j - 1;
@@ -139,10 +146,10 @@ __global__ void __launch_bounds__(256) k_velocity_basic(StepArgs a, int nbx)
   const int i1 = i + 1 < a.nr ? i + 1 : a.nr - 1;
   const int k1 = kk + 1 < a.nz ? kk + 1 : a.nz - 1;
   const size_t p = at(a, i, j, kk);
-  const float rho0 = a.rho[p];
-  const float b_r = 2.0f * rcp(rho0 + a.rho[at(a, i1, j, kk)]);
-  const float b_t = 2.0f * rcp(rho0 + a.rho[at(a, i, jp, kk)]);
-  const float b_z = 2.0f * rcp(rho0 + a.rho[at(a, i, j, k1)]);
+  const float rho0 = a.rho[mat(a, i, j, kk)];
+  const float b_r = 2.0f * rcp(rho0 + a.rho[mat(a, i1, j, kk)]);
+  const float b_t = 2.0f * rcp(rho0 + a.rho[mat(a, i, jp, kk)]);
+  const float b_z = 2.0f * rcp(rho0 + a.rho[mat(a, i, j, k1)]);
 
   const float vr = S::ld(a.in[VR], p, c[VR]) + a.dt * b_r * (r_dr + r_b + r_dz);
   const float vt = S::ld(a.in[VT], p, c[VT]) + a.dt * b_t * (t_dr + t_b + t_dz);
@@ -164,9 +171,10 @@ template <class S>
 __global__ void __launch_bounds__(256) k_stress_basic(StepArgs a, int nbx)
 {
   const int t = xcd_tile(blockIdx.x, gridDim.x);
-  const int bx = t % nbx, ij = t / nbx;
+  const int bx = t % nbx;
   const int k = bx * 256 + threadIdx.x;
-  const int j = ij % a.nt, i = ij / a.nt;
+  int i, j;
+  strip_column(t / nbx, a.nr, a.nt, i, j);
   const bool live = k < a.nz;
   const int kk = live ? k : a.nz - 1;
   const int jm = j == 0 ? a.nt - 1 : j - 1;
@@ -216,12 +224,13 @@ __global__ void __launch_bounds__(256) k_stress_basic(StepArgs a, int nbx)
   const int i1 = i + 1 < a.nr ? i + 1 : a.nr - 1;
   const int k1 = kk + 1 < a.nz ? kk + 1 : a.nz - 1;
   const size_t p = at(a, i, j, kk);
-  const float lam = a.lam[p], mu = a.mu[p];
-  const float mu_i1 = a.mu[at(a, i1, j, kk)], mu_jp = a.mu[at(a, i, jp, kk)];
-  const float mu_k1 = a.mu[at(a, i, j, k1)];
-  const float mu_rt = hm4(mu, mu_i1, mu_jp, a.mu[at(a, i1, jp, kk)]);
-  const float mu_rz = hm4(mu, mu_i1, mu_k1, a.mu[at(a, i1, j, k1)]);
-  const float mu_tz = hm4(mu, mu_jp, mu_k1, a.mu[at(a, i, jp, k1)]);
+  const size_t pm = mat(a, i, j, kk);
+  const float lam = a.lam[pm], mu = a.mu[pm];
+  const float mu_i1 = a.mu[mat(a, i1, j, kk)], mu_jp = a.mu[mat(a, i, jp, kk)];
+  const float mu_k1 = a.mu[mat(a, i, j, k1)];
+  const float mu_rt = hm4(mu, mu_i1, mu_jp, a.mu[mat(a, i1, jp, kk)]);
+  const float mu_rz = hm4(mu, mu_i1, mu_k1, a.mu[mat(a, i1, j, k1)]);
+  const float mu_tz = hm4(mu, mu_jp, mu_k1, a.mu[mat(a, i, jp, k1)]);
 
   const float *c = a.scl_in;
   const float tr = err + ett + ezz;
@@ -308,14 +317,15 @@ __device__ double cell_energy(const StepArgs &a, int i, int j, int k)
   const size_t p = at(a, i, j, k);
   const float *ci = a.scl_in, *co = a.scl_out;
   const double ri = (double)(i + 0.5), Ri = (double)(i + 1);   // radii in units of dr
-  const double rho0 = a.rho[p];
-  const double rr = 0.5 * (rho0 + a.rho[at(a, i1, j, k)]);
-  const double rt = 0.5 * (rho0 + a.rho[at(a, i, jp, k)]);
-  const double rz = 0.5 * (rho0 + a.rho[at(a, i, j, k1)]);
+  const size_t pm = mat(a, i, j, k);
+  const double rho0 = a.rho[pm];
+  const double rr = 0.5 * (rho0 + a.rho[mat(a, i1, j, k)]);
+  const double rt = 0.5 * (rho0 + a.rho[mat(a, i, jp, k)]);
+  const double rz = 0.5 * (rho0 + a.rho[mat(a, i, j, k1)]);
   const double vr = S::ld(a.out[VR], p, co[VR]), vt = S::ld(a.out[VT], p, co[VT]);
   const double vz = S::ld(a.out[VZ], p, co[VZ]);
   double E = 0.5 * (Ri * rr * vr * vr + ri * rt * vt * vt + ri * rz * vz * vz);
-  const double lam = a.lam[p], mu = a.mu[p];
+  const double lam = a.lam[pm], mu = a.mu[pm];
   const double K = lam + 2.0 * mu / 3.0;
   const double n1[3] = {S::ld(a.out[SRR], p, co[SRR]), S::ld(a.out[STT], p, co[STT]), S::ld(a.out[SZZ], p, co[SZZ])};
   const double n0[3] = {S::ld(a.in[SRR], p, ci[SRR]), S::ld(a.in[STT], p, ci[STT]), S::ld(a.in[SZZ], p, ci[SZZ])};
@@ -326,13 +336,13 @@ __device__ double cell_energy(const StepArgs &a, int i, int j, int k)
     for (int q = 0; q < 3; q++) d += (n1[q] - t1 / 3.0) * (n0[q] - t0 / 3.0);
     E += 0.5 * ri * d / (2.0 * mu);
   }
-  const double m_i1 = a.mu[at(a, i1, j, k)], m_jp = a.mu[at(a, i, jp, k)], m_k1 = a.mu[at(a, i, j, k1)];
+  const double m_i1 = a.mu[mat(a, i1, j, k)], m_jp = a.mu[mat(a, i, jp, k)], m_k1 = a.mu[mat(a, i, j, k1)];
   auto hm = [](double w, double x, double y, double z) {
     return (w == 0.0 || x == 0.0 || y == 0.0 || z == 0.0) ? 0.0 : 4.0 / (1.0 / w + 1.0 / x + 1.0 / y + 1.0 / z);
   };
-  const double mrt = hm(mu, m_i1, m_jp, a.mu[at(a, i1, jp, k)]);
-  const double mrz = hm(mu, m_i1, m_k1, a.mu[at(a, i1, j, k1)]);
-  const double mtz = hm(mu, m_jp, m_k1, a.mu[at(a, i, jp, k1)]);
+  const double mrt = hm(mu, m_i1, m_jp, a.mu[mat(a, i1, jp, k)]);
+  const double mrz = hm(mu, m_i1, m_k1, a.mu[mat(a, i1, j, k1)]);
+  const double mtz = hm(mu, m_jp, m_k1, a.mu[mat(a, i, jp, k1)]);
   if (mrt > 0.0) E += 0.5 * Ri * (double)S::ld(a.out[SRT], p, co[SRT]) * (double)S::ld(a.in[SRT], p, ci[SRT]) / mrt;
   if (mrz > 0.0) E += 0.5 * Ri * (double)S::ld(a.out[SRZ], p, co[SRZ]) * (double)S::ld(a.in[SRZ], p, ci[SRZ]) / mrz;
   if (mtz > 0.0) E += 0.5 * ri * (double)S::ld(a.out[STZ], p, co[STZ]) * (double)S::ld(a.in[STZ], p, ci[STZ]) / mtz;

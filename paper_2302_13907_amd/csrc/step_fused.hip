@@ -119,8 +119,11 @@ __global__ void __launch_bounds__(TJ * 64) k_step_fused(FusedArgs F)
     const float v = ldo(fin + q * n + (size_t)(i < nr ? i : nr - 1) * plane, o);
     return (kin && i < nr) ? v : 0.0f;
   };
-  auto mat = [&](int q, int i, uint32_t o) -> float {   // medium q (0 rho, 1 lambda, 2 mu) at ring min(i, nr-1)
-    return ldo(med + q * n + (size_t)(i < nr ? i : nr - 1) * plane, o);
+  // byte offset of this lane's cell in a ring of the medium (no theta term when the
+  // medium does not vary along theta)
+  const uint32_t moff0 = (uint32_t)(j * F.m_row + kc) * 4u;
+  auto mat = [&](int q, int i, uint32_t) -> float {   // medium q (0 rho, 1 lambda, 2 mu) at ring min(i, nr-1)
+    return ldo(med + q * F.m_n + (size_t)(i < nr ? i : nr - 1) * F.m_ring, moff0);
   };
   auto six = [&](int i, uint32_t o) -> Six {
     return Six{fld(SRR, i, o), fld(STT, i, o), fld(SZZ, i, o), fld(SRT, i, o), fld(SRZ, i, o), fld(STZ, i, o)};

@@ -7,97 +7,21 @@
 // group itself; the one before and the one after the group are single
 // loads.  Used when nz is a multiple of VW; the operators, the storage
 // policies and the float16 scale tracking are those of the scalar kernels.
-#include "cwell_internal.hpp"
-#include "storage.hpp"
+#include "vec_common.hpp"
 
 namespace cw {
 
 namespace {
 
-constexpr int VW = 4;
-
-__device__ __forceinline__ size_t at(const StepArgs &a, int i, int j, int k)
-{
-  return ((size_t)i * a.nt + j) * a.nz + k;
-}
-
-__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
-
-__device__ __forceinline__ int zrow(const StepArgs &a, int k)
-{
-  if (a.npz == 0) return -1;
-  if (k < a.npz) return k;
-  const int lo = a.nz - 1 - a.npz;
-  return k >= lo ? k - lo + a.npz : -1;
-}
-
-// VW physical values of field f at (i, j, k0..k0+VW-1); zero for a ring
-// outside [0, nr)
-template <class S>
-__device__ __forceinline__ void ldv(float (&o)[VW], const float *f, float s, const StepArgs &a, int i, int j, int k0)
-{
-  if (i < 0 || i >= a.nr) {
-#pragma unroll
-    for (int e = 0; e < VW; e++) o[e] = 0.0f;
-    return;
-  }
-  S::template ldv<VW>(o, f, at(a, i, j, k0), s);
-}
-
-// one value at (i, j, k), zero for k outside [0, nz)
-template <class S>
-__device__ __forceinline__ float ld1(const float *f, float s, const StepArgs &a, int i, int j, int k)
-{
-  const int kc = k < 0 ? 0 : (k >= a.nz ? a.nz - 1 : k);
-  const float v = S::ld(f, at(a, i, j, kc), s);
-  return (k >= 0 && k < a.nz) ? v : 0.0f;
-}
-
-__device__ __forceinline__ void ldv4(float (&o)[VW], const float *f, size_t p)
-{
-  const float4 v = *reinterpret_cast<const float4 *>(f + p);
-  o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
-}
-__device__ __forceinline__ void stv4(float *f, size_t p, const float (&v)[VW])
-{
-  *reinterpret_cast<float4 *>(f + p) = make_float4(v[0], v[1], v[2], v[3]);
-}
-
-// layer memory update of VW consecutive values in the radial slab: psi <- b psi + a X, X += psi
-__device__ __forceinline__ void cpml_v(float *psi, size_t q, float ca, float cb, float (&X)[VW])
-{
-  float p[VW];
-  ldv4(p, psi, q);
-#pragma unroll
-  for (int e = 0; e < VW; e++) {
-    p[e] = cb * p[e] + ca * X[e];
-    X[e] += p[e];
-  }
-  stv4(psi, q, p);
-}
-
-__device__ __forceinline__ float cpml1(float *psi, size_t q, float ca, float cb, float X)
-{
-  const float v = cb * psi[q] + ca * X;
-  psi[q] = v;
-  return X + v;
-}
-
-// largest |x| of the wavefront into one of 64 slots of a field (spreads
-// the atomics of a launch over 64 addresses)
-__device__ __forceinline__ void track_max(unsigned *slots, float m)
-{
-  for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
-  if ((threadIdx.x & 63) == 0 && m > 0.0f)
-    atomicMax(&slots[(blockIdx.x + (threadIdx.x >> 6)) & (kMaxSlots - 1)], __builtin_bit_cast(unsigned, m));
-}
+using namespace vec;
 
 template <class S>
 __global__ void __launch_bounds__(256) k_velocity_vec(StepArgs a, int nbx)
 {
-  const int bx = blockIdx.x % nbx, ij = blockIdx.x / nbx;
+  const int bx = blockIdx.x % nbx;
   const int k0 = (bx * 256 + threadIdx.x) * VW;
-  const int j = ij % a.nt, i = ij / a.nt;
+  int i, j;
+  strip_column(blockIdx.x / nbx, a.nr, a.nt, i, j);
   const bool live = k0 < a.nz;
   const int kb = live ? k0 : a.nz - VW;            // dead lanes compute on a valid group, store nothing
   const int jm = j == 0 ? a.nt - 1 : j - 1;
@@ -123,10 +47,10 @@ __global__ void __launch_bounds__(256) k_velocity_vec(StepArgs a, int nbx)
   const float szz_a = ld1<S>(a.in[SZZ], c[SZZ], a, i, j, kb + VW);
   const int i1 = i + 1 < a.nr ? i + 1 : a.nr - 1;
   float rho0[VW], rho_i1[VW], rho_jp[VW];
-  ldv4(rho0, a.rho, at(a, i, j, kb));
-  ldv4(rho_i1, a.rho, at(a, i1, j, kb));
-  ldv4(rho_jp, a.rho, at(a, i, jp, kb));
-  const float rho_a = a.rho[at(a, i, j, kb + VW < a.nz ? kb + VW : a.nz - 1)];
+  ldv4(rho0, a.rho, mat(a, i, j, kb));
+  ldv4(rho_i1, a.rho, mat(a, i1, j, kb));
+  ldv4(rho_jp, a.rho, mat(a, i, jp, kb));
+  const float rho_a = a.rho[mat(a, i, j, kb + VW < a.nz ? kb + VW : a.nz - 1)];
 
   const float irc = a.inv_rc[i], irf = a.inv_rf[i];
   float r_dr[VW], r_b[VW], r_dz[VW], t_dr[VW], t_b[VW], t_dz[VW], z_dr[VW], z_b[VW], z_dz[VW];
@@ -201,9 +125,10 @@ __global__ void __launch_bounds__(256) k_velocity_vec(StepArgs a, int nbx)
 template <class S>
 __global__ void __launch_bounds__(256) k_stress_vec(StepArgs a, int nbx)
 {
-  const int bx = blockIdx.x % nbx, ij = blockIdx.x / nbx;
+  const int bx = blockIdx.x % nbx;
   const int k0 = (bx * 256 + threadIdx.x) * VW;
-  const int j = ij % a.nt, i = ij / a.nt;
+  int i, j;
+  strip_column(blockIdx.x / nbx, a.nr, a.nt, i, j);
   const bool live = k0 < a.nz;
   const int kb = live ? k0 : a.nz - VW;
   const int jm = j == 0 ? a.nt - 1 : j - 1;
@@ -268,13 +193,13 @@ __global__ void __launch_bounds__(256) k_stress_vec(StepArgs a, int nbx)
   const int i1 = i + 1 < a.nr ? i + 1 : a.nr - 1;
   const int ka = kb + VW < a.nz ? kb + VW : a.nz - 1;   // depth neighbour of the group, clamped
   float lam[VW], mu[VW], m_i1[VW], m_jp[VW], m_i1jp[VW];
-  ldv4(lam, a.lam, at(a, i, j, kb));
-  ldv4(mu, a.mu, at(a, i, j, kb));
-  ldv4(m_i1, a.mu, at(a, i1, j, kb));
-  ldv4(m_jp, a.mu, at(a, i, jp, kb));
-  ldv4(m_i1jp, a.mu, at(a, i1, jp, kb));
-  const float ia = rcp(a.mu[at(a, i, j, ka)]), ia_i1 = rcp(a.mu[at(a, i1, j, ka)]);
-  const float ia_jp = rcp(a.mu[at(a, i, jp, ka)]);
+  ldv4(lam, a.lam, mat(a, i, j, kb));
+  ldv4(mu, a.mu, mat(a, i, j, kb));
+  ldv4(m_i1, a.mu, mat(a, i1, j, kb));
+  ldv4(m_jp, a.mu, mat(a, i, jp, kb));
+  ldv4(m_i1jp, a.mu, mat(a, i1, jp, kb));
+  const float ia = rcp(a.mu[mat(a, i, j, ka)]), ia_i1 = rcp(a.mu[mat(a, i1, j, ka)]);
+  const float ia_jp = rcp(a.mu[mat(a, i, jp, ka)]);
   float im[VW], im_i1[VW], im_jp[VW];
 #pragma unroll
   for (int e = 0; e < VW; e++) { im[e] = rcp(mu[e]); im_i1[e] = rcp(m_i1[e]); im_jp[e] = rcp(m_jp[e]); }

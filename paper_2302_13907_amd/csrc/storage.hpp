@@ -9,9 +9,47 @@
 
 namespace cw {
 
+// Buffer accesses: a wavefront-uniform resource (base address and size in
+// scalar registers), a per-lane byte offset and a uniform byte offset.
+// Raw buffer reads beyond the resource's size return zero.
+typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+typedef __amdgpu_buffer_rsrc_t rsrc_t;
+__device__ __forceinline__ rsrc_t make_rsrc(const void *base, unsigned nbytes)
+{
+  // word 3: 32-bit data format, which untyped loads and stores require on this family
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)nbytes, 0x00020000);
+}
+__device__ __forceinline__ void ldb4(float (&o)[4], rsrc_t r, unsigned voff, unsigned soff)
+{
+  const u32x4 u = __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0);
+  // copy the elements out first: a bit cast of a vector-element lvalue reads element 0
+  const unsigned x = u.x, y = u.y, z = u.z, w = u.w;
+  o[0] = __builtin_bit_cast(float, x); o[1] = __builtin_bit_cast(float, y);
+  o[2] = __builtin_bit_cast(float, z); o[3] = __builtin_bit_cast(float, w);
+}
+__device__ __forceinline__ void stb4(rsrc_t r, unsigned voff, unsigned soff, const float (&v)[4])
+{
+  u32x4 u;
+  u.x = __builtin_bit_cast(unsigned, v[0]); u.y = __builtin_bit_cast(unsigned, v[1]);
+  u.z = __builtin_bit_cast(unsigned, v[2]); u.w = __builtin_bit_cast(unsigned, v[3]);
+  __builtin_amdgcn_raw_buffer_store_b128(u, r, voff, soff, 0);
+}
+__device__ __forceinline__ float ldb1(rsrc_t r, unsigned voff, unsigned soff)
+{
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+
 struct StF32 {
   static constexpr bool scaled = false;
+  static constexpr unsigned bytes = 4;   // bytes per stored value
+  // f advanced by p stored values
+  __device__ static const float *adv(const float *f, size_t p) { return f + p; }
+  __device__ static float *adv(float *f, size_t p) { return f + p; }
   __device__ static float ld(const float *f, size_t p, float) { return f[p]; }
+  __device__ static void ldb(float (&o)[4], rsrc_t r, unsigned voff, unsigned soff, float) { ldb4(o, r, voff, soff); }
+  __device__ static float ldb1(rsrc_t r, unsigned voff, unsigned soff, float) { return cw::ldb1(r, voff, soff); }
+  __device__ static void stb(rsrc_t r, unsigned voff, unsigned soff, const float (&v)[4], float) { stb4(r, voff, soff, v); }
   __device__ static void st(float *f, size_t p, float v, float) { f[p] = v; }
   template <int V>
   __device__ static void ldv(float (&o)[V], const float *f, size_t p, float)
@@ -31,10 +69,35 @@ struct StF32 {
 // float16 with a per-field power-of-two scale; conversion rounds to nearest even
 struct StF16 {
   static constexpr bool scaled = true;
+  static constexpr unsigned bytes = 2;
+  __device__ static const float *adv(const float *f, size_t p)
+  {
+    return reinterpret_cast<const float *>(reinterpret_cast<const unsigned short *>(f) + p);
+  }
+  __device__ static float *adv(float *f, size_t p)
+  {
+    return reinterpret_cast<float *>(reinterpret_cast<unsigned short *>(f) + p);
+  }
   typedef _Float16 h4 __attribute__((ext_vector_type(4)));
   __device__ static float ld(const float *f, size_t p, float s)
   {
     return (float)reinterpret_cast<const _Float16 *>(f)[p] * s;
+  }
+  __device__ static void ldb(float (&o)[4], rsrc_t r, unsigned voff, unsigned soff, float s)
+  {
+    const h4 v = __builtin_bit_cast(h4, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+    o[0] = (float)v[0] * s; o[1] = (float)v[1] * s; o[2] = (float)v[2] * s; o[3] = (float)v[3] * s;
+  }
+  __device__ static float ldb1(rsrc_t r, unsigned voff, unsigned soff, float s)
+  {
+    return (float)__builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0)) * s;
+  }
+  __device__ static void stb(rsrc_t r, unsigned voff, unsigned soff, const float (&v)[4], float is)
+  {
+    h4 h;
+    h[0] = (_Float16)(v[0] * is); h[1] = (_Float16)(v[1] * is);
+    h[2] = (_Float16)(v[2] * is); h[3] = (_Float16)(v[3] * is);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, h), r, voff, soff, 0);
   }
   __device__ static void st(float *f, size_t p, float v, float is)
   {
@@ -62,6 +125,15 @@ struct StF16 {
 // conversion rounds to nearest even on the dropped bits (fields stay finite)
 struct StBF16 {
   static constexpr bool scaled = false;
+  static constexpr unsigned bytes = 2;
+  __device__ static const float *adv(const float *f, size_t p)
+  {
+    return reinterpret_cast<const float *>(reinterpret_cast<const unsigned short *>(f) + p);
+  }
+  __device__ static float *adv(float *f, size_t p)
+  {
+    return reinterpret_cast<float *>(reinterpret_cast<unsigned short *>(f) + p);
+  }
   __device__ static unsigned short pack(float v)
   {
     unsigned u = __builtin_bit_cast(unsigned, v);
@@ -72,6 +144,23 @@ struct StBF16 {
   __device__ static float ld(const float *f, size_t p, float)
   {
     return unpack(reinterpret_cast<const unsigned short *>(f)[p]);
+  }
+  __device__ static void ldb(float (&o)[4], rsrc_t r, unsigned voff, unsigned soff, float)
+  {
+    const u32x2 u = __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0);
+    o[0] = __builtin_bit_cast(float, u.x << 16); o[1] = __builtin_bit_cast(float, u.x & 0xffff0000u);
+    o[2] = __builtin_bit_cast(float, u.y << 16); o[3] = __builtin_bit_cast(float, u.y & 0xffff0000u);
+  }
+  __device__ static float ldb1(rsrc_t r, unsigned voff, unsigned soff, float)
+  {
+    return unpack(__builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0));
+  }
+  __device__ static void stb(rsrc_t r, unsigned voff, unsigned soff, const float (&v)[4], float)
+  {
+    u32x2 u;
+    u.x = (unsigned)pack(v[0]) | ((unsigned)pack(v[1]) << 16);
+    u.y = (unsigned)pack(v[2]) | ((unsigned)pack(v[3]) << 16);
+    __builtin_amdgcn_raw_buffer_store_b64(u, r, voff, soff, 0);
   }
   __device__ static void st(float *f, size_t p, float v, float)
   {

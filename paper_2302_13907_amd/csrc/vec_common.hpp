@@ -1,0 +1,96 @@
+// Device helpers shared by the depth-vectorized step kernels (column and
+// radial-march forms): VW consecutive depth cells per thread, zero ghosts
+// outside the grid, layer memory updates, float16 scale tracking.
+#pragma once
+#include "cwell_internal.hpp"
+#include "storage.hpp"
+
+namespace cw {
+namespace vec {
+
+constexpr int VW = 4;
+
+__device__ __forceinline__ size_t at(const StepArgs &a, int i, int j, int k)
+{
+  return ((size_t)i * a.nt + j) * a.nz + k;
+}
+
+// index of cell (i, j, k) in the medium arrays
+__device__ __forceinline__ size_t mat(const StepArgs &a, int i, int j, int k)
+{
+  return (size_t)i * a.m_ring + (size_t)j * a.m_row + k;
+}
+
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+__device__ __forceinline__ int zrow(const StepArgs &a, int k)
+{
+  if (a.npz == 0) return -1;
+  if (k < a.npz) return k;
+  const int lo = a.nz - 1 - a.npz;
+  return k >= lo ? k - lo + a.npz : -1;
+}
+
+// VW physical values of field f at (i, j, k0..k0+VW-1); zero for a ring
+// outside [0, nr)
+template <class S>
+__device__ __forceinline__ void ldv(float (&o)[VW], const float *f, float s, const StepArgs &a, int i, int j, int k0)
+{
+  if (i < 0 || i >= a.nr) {
+#pragma unroll
+    for (int e = 0; e < VW; e++) o[e] = 0.0f;
+    return;
+  }
+  S::template ldv<VW>(o, f, at(a, i, j, k0), s);
+}
+
+// one value at (i, j, k), zero for k outside [0, nz)
+template <class S>
+__device__ __forceinline__ float ld1(const float *f, float s, const StepArgs &a, int i, int j, int k)
+{
+  const int kc = k < 0 ? 0 : (k >= a.nz ? a.nz - 1 : k);
+  const float v = S::ld(f, at(a, i, j, kc), s);
+  return (k >= 0 && k < a.nz) ? v : 0.0f;
+}
+
+__device__ __forceinline__ void ldv4(float (&o)[VW], const float *f, size_t p)
+{
+  const float4 v = *reinterpret_cast<const float4 *>(f + p);
+  o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
+}
+__device__ __forceinline__ void stv4(float *f, size_t p, const float (&v)[VW])
+{
+  *reinterpret_cast<float4 *>(f + p) = make_float4(v[0], v[1], v[2], v[3]);
+}
+
+// layer memory update of VW consecutive values in the radial slab: psi <- b psi + a X, X += psi
+__device__ __forceinline__ void cpml_v(float *psi, size_t q, float ca, float cb, float (&X)[VW])
+{
+  float p[VW];
+  ldv4(p, psi, q);
+#pragma unroll
+  for (int e = 0; e < VW; e++) {
+    p[e] = cb * p[e] + ca * X[e];
+    X[e] += p[e];
+  }
+  stv4(psi, q, p);
+}
+
+__device__ __forceinline__ float cpml1(float *psi, size_t q, float ca, float cb, float X)
+{
+  const float v = cb * psi[q] + ca * X;
+  psi[q] = v;
+  return X + v;
+}
+
+// largest |x| of the wavefront into one of 64 slots of a field (spreads
+// the atomics of a launch over 64 addresses)
+__device__ __forceinline__ void track_max(unsigned *slots, float m)
+{
+  for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
+  if ((threadIdx.x & 63) == 0 && m > 0.0f)
+    atomicMax(&slots[(blockIdx.x + (threadIdx.x >> 6)) & (kMaxSlots - 1)], __builtin_bit_cast(unsigned, m));
+}
+
+}  // namespace vec
+}  // namespace cw

@@ -35,7 +35,7 @@ EXPORTS = ("cw_create", "cw_set_material", "cw_set_material_rz", "cw_set_pml", "
 
 STORAGE = {"f32": 0, "f16": 1, "bf16": 2}
 
-PATHS = {"auto": 0, "two-pass": 1, "fused": 2}
+PATHS = {"auto": 0, "two-pass": 1, "fused": 2, "march": 3}
 
 KERNELS = {"velocity": 0, "stress": 1, "fused": 2, "inject": 3, "record": 4}
 

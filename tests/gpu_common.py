@@ -30,6 +30,7 @@ class Scenario:
     receivers: List[tuple] = field(default_factory=list)   # (kind, i, j, k, field)
     initial: Optional[dict] = None                          # field -> array
     path: str = "auto"                                      # kernel path of cw_step
+    storage: str = "f32"                                    # field storage on the device
 
 
 def announce(msg: str):
@@ -56,6 +57,7 @@ def run_gpu(sc: Scenario, keep_sim: bool = False):
         s.add_receiver(kind, i, j, k, fld)
     s.set_trace_capacity(sc.steps)
     s.set_path(sc.path)
+    s.set_storage(sc.storage)
     s.bind()
     if sc.initial:
         for name, a in sc.initial.items():

@@ -116,7 +116,9 @@ def test_validation_errors():
 
 def test_workspace_size_accounts_for_everything():
     shape = (10, 4, 24)
-    s, _ = _sim(shape)
+    h = 5e-3
+    s = cwell.Sim(*shape, h, h)
+    s.set_material(*inputs.random_medium(*shape, seed=1))   # varies along theta
     base = s.workspace_bytes()
     n = 10 * 4 * 24
     assert base >= (2 * 9 + 3) * n * 4
@@ -127,3 +129,10 @@ def test_workspace_size_accounts_for_everything():
     s.add_receiver("pressure", 0, -1, 5)
     s.set_trace_capacity(1000)
     assert s.workspace_bytes() - with_pml >= 8000
+    # a medium that does not vary along theta is stored once per (ring, depth),
+    # whether it is given as [nr][nz] or as a full [nr][nt][nz] array
+    rz = inputs.cased_well_rz(10, 24, h, h, z_top=0.05)
+    for full in (False, True):
+        s2 = cwell.Sim(*shape, h, h)
+        s2.set_material(*[np.repeat(m[:, None, :], 4, axis=1) for m in rz] if full else rz)
+        assert base - s2.workspace_bytes() >= 3 * (n - 10 * 24) * 4 - 3 * 256
