@@ -90,7 +90,8 @@ PROFILE_VARIANTS = {
     "two_pass_bf16": "--path two-pass --storage bf16",
     "fused_f32": "--path fused --storage f32",
 }
-PROFILE_RUN = "python3 -u bench.py --steps 20 --warmup 5 --no-cpu-baseline --no-storage-forms --copy-gib 1"
+PROFILE_RUN = ("python3 -u bench.py --steps 20 --warmup 5 --no-cpu-baseline --no-storage-forms --no-stream-ceiling "
+               "--copy-gib 1")
 PROFILE_PASSES = (
     ("stats", "--kernel-trace --stats"),
     ("fetch", "--pmc FETCH_SIZE"),
@@ -312,6 +313,23 @@ def run_steps(w, storage: str, path: str, warmup: int, steps: int):
     return el, times, tr
 
 
+# (reads, writes) of 4-byte streams per cell of each step kernel, 3-D medium / axisymmetric medium
+STREAM_MIX = {"velocity": ((10, 3), (9, 3)), "stress": ((11, 6), (9, 6)), "fused": ((12, 9), (9, 9))}
+
+
+def stream_ceiling(kernel: str, axisym: bool, roofline: dict):
+    """What HBM delivers to a kernel that only streams the dominant kernel's
+    read/write mix (1 GiB per array), and a plain 1 + 1 copy; the dominant
+    kernel's algorithmic rate as a fraction of the former."""
+    from paper_2302_13907_amd import cwell
+    r, w = STREAM_MIX[kernel][1 if axisym else 0]
+    log("stream ceiling: %d reads + %d writes" % (r, w))
+    mix = cwell.stream_probe(r, w) / 1e9
+    copy = cwell.stream_probe(1, 1) / 1e9
+    return {"kernel": kernel, "reads": r, "writes": w, "GBps": round(mix, 1), "copy_GBps": round(copy, 1),
+            "frac_of_ceiling": round(roofline["achieved"] / mix, 4)}
+
+
 def storage_forms(path: str, warmup: int = 10, steps: int = 100):
     """Gcell-updates/s of the mixed-precision workload with float32, float16
     and bfloat16 field storage (float32 arithmetic in every case)."""
@@ -346,6 +364,8 @@ def main():
     ap.add_argument("--no-storage-forms", action="store_true",
                     help="skip the float32 / float16 / bfloat16 storage comparison on the "
                          "192 x 96 x 4096 mixed-precision workload")
+    ap.add_argument("--no-stream-ceiling", action="store_true",
+                    help="skip the streaming-bandwidth reference for the step kernels' read/write mixes")
     ap.add_argument("--print-profile-commands", nargs=2, metavar=("VARIANT", "OUTDIR"),
                     help="print the rocprofv3 commands that profile VARIANT (%s), one "
                          "'name command' per line, and exit" % ", ".join(PROFILE_VARIANTS))
@@ -429,6 +449,8 @@ def main():
         out["copy_reference_bytes"] = nb
         del src, dst
         torch.cuda.empty_cache()
+    if not args.no_stream_ceiling:
+        out["stream_ceiling"] = stream_ceiling(dom, axisym, out["roofline"])
     if not args.no_storage_forms:
         out["storage_forms"] = storage_forms(args.path)
     if not args.no_cpu_baseline:

@@ -222,6 +222,19 @@ cw_status cw_profile_read(cw_sim *s, int32_t kernel, double *total_ms, int64_t *
    out[m] = f(t[m]). */
 cw_status cw_ricker(double f0, const double *t, int64_t n, double *out);
 
+/* Bandwidth reference (measurement only, not part of the scheme): stream
+   nread + nwrite arrays of bytes_per_array bytes each, laid out back to
+   back in the caller's device buffer `dev` (16-byte aligned, at least
+   (nread + nwrite) * bytes_per_array bytes; its contents are overwritten):
+   every 16-byte group of the write arrays receives the sum of the same
+   group of the read arrays.  Runs 2 untimed passes and `reps` timed ones
+   on `stream` (a hipStream_t, NULL for the default stream), waits, and
+   returns the average milliseconds per pass.  Supported (nread, nwrite):
+   (1, 1), (9, 3), (10, 3), (9, 6), (11, 6), (9, 9), (12, 9) -- the stream
+   mixes of the step kernels; others give CW_ERR_RANGE. */
+cw_status cw_stream_probe(void *dev, uint64_t bytes_per_array, int32_t nread, int32_t nwrite, int32_t reps,
+                          void *stream, double *ms_per_pass);
+
 void cw_destroy(cw_sim *s);
 const char *cw_last_error(void);
 

@@ -167,6 +167,8 @@ constexpr int kF16TargetExp = 11;   // scaled float16 maxima land in [2^10, 2^11
 // depth-vectorized two-pass kernels (4 cells per thread), when nz % 4 == 0
 bool vec_applies(int nz);
 bool march_applies(int nt, int nz);
+bool stream_mix_supported(int r, int w);
+hipError_t launch_stream(const void *base, size_t n4, int r, int w, hipStream_t stream);
 hipError_t launch_velocity_march(const StepArgs &a, int storage, hipStream_t stream);
 hipError_t launch_stress_march(const StepArgs &a, int storage, hipStream_t stream);
 hipError_t launch_velocity_vec(const StepArgs &a, int storage, hipStream_t stream);

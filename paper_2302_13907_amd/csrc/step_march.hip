@@ -58,74 +58,6 @@ __device__ __forceinline__ void march_decode(const StepArgs &a, int nzb, int njt
   i1 = i0 + rseg < a.nr ? i0 + rseg : a.nr;
 }
 
-// Addressing of one wavefront.  Every access goes through a buffer
-// resource spanning one ring of one array (base and size in scalar
-// registers); the theta row is a uniform byte offset and the lane's depth
-// position a per-lane byte offset, the same for every array of a width.
-template <class S>
-struct Lanes {
-  unsigned v0, vb, va;      // field bytes: the lane's group, the cell before it, the cell after it
-  unsigned m0, ma;          // float32 bytes: the lane's group, the clamped cell after it
-  bool has_b, has_a;        // the cell before / after the group is inside the grid
-  unsigned sj, sjm, sjp;    // field bytes of rows j, j - 1, j + 1 within a ring
-  unsigned tj, tjm, tjp;    // float32 bytes of the same rows (layer memory)
-  unsigned mj, mjp;         // medium bytes of rows j, j + 1 (0 when the medium does not vary along theta)
-  size_t ring;              // values per ring
-  unsigned ringb, ringm;    // bytes per ring: fields, float32 arrays
-  size_t mring;             // medium values per ring
-  unsigned mringb;
-
-  __device__ Lanes(const StepArgs &a, int kb, int j, int jm, int jp)
-  {
-    ring = (size_t)a.nt * a.nz;
-    ringb = (unsigned)(ring * S::bytes);
-    ringm = (unsigned)(ring * 4);
-    has_b = kb > 0;
-    has_a = kb + VW < a.nz;
-    v0 = (unsigned)kb * S::bytes;
-    vb = has_b ? v0 - S::bytes : v0;
-    va = has_a ? v0 + VW * S::bytes : v0;
-    m0 = (unsigned)kb * 4u;
-    ma = has_a ? m0 + VW * 4u : (unsigned)(a.nz - 1) * 4u;
-    sj = (unsigned)j * a.nz * S::bytes; sjm = (unsigned)jm * a.nz * S::bytes; sjp = (unsigned)jp * a.nz * S::bytes;
-    tj = (unsigned)j * a.nz * 4u; tjm = (unsigned)jm * a.nz * 4u; tjp = (unsigned)jp * a.nz * 4u;
-    mj = (unsigned)j * a.m_row * 4u; mjp = (unsigned)jp * a.m_row * 4u;
-    mring = a.m_ring;
-    mringb = (unsigned)(mring * 4);
-  }
-  // resource of ring i of a field array / a float32 array
-  __device__ rsrc_t field(const float *f, int i) const { return make_rsrc(S::adv(f, (size_t)i * ring), ringb); }
-  __device__ rsrc_t fieldw(float *f, int i) const { return make_rsrc(S::adv(f, (size_t)i * ring), ringb); }
-  __device__ rsrc_t f32(const float *f, int i) const { return make_rsrc(f + (size_t)i * ring, ringm); }
-  __device__ rsrc_t med(const float *f, int i) const { return make_rsrc(f + (size_t)i * mring, mringb); }
-};
-
-// VW values of a field at ring i (zero for a ring outside [0, nr)), row offset soff
-template <class S>
-__device__ __forceinline__ void ldf(float (&o)[VW], const Lanes<S> &L, const StepArgs &a, const float *f, float s,
-                                    int i, unsigned soff)
-{
-  if (i < 0 || i >= a.nr) {
-#pragma unroll
-    for (int e = 0; e < VW; e++) o[e] = 0.0f;
-    return;
-  }
-  S::ldb(o, L.field(f, i), L.v0, soff, s);
-}
-
-// layer memory update of the lane's VW values of one radial-slab array: psi <- b psi + a X, X += psi
-__device__ __forceinline__ void cpml_b(rsrc_t r, unsigned voff, unsigned soff, float ca, float cb, float (&X)[VW])
-{
-  float p[VW];
-  ldb4(p, r, voff, soff);
-#pragma unroll
-  for (int e = 0; e < VW; e++) {
-    p[e] = cb * p[e] + ca * X[e];
-    X[e] += p[e];
-  }
-  stb4(r, voff, soff, p);
-}
-
 template <class S>
 __global__ void __launch_bounds__(TJ * 64) __attribute__((amdgpu_waves_per_eu(CW_MARCH_WAVES)))
 k_velocity_march(StepArgs a, int nzb, int njt, int rseg)

@@ -15,42 +15,64 @@ namespace {
 
 using namespace vec;
 
+// Theta rows per workgroup.  Measured on MI355X: 2 to 8 rows done one after
+// the other by the same wavefronts (set-up paid once) are 10-55 % slower
+// than one row, as the compiler then keeps two rows' loads in flight and
+// the register growth costs more occupancy than it saves.
+#ifndef CW_VEC_ROWS
+#define CW_VEC_ROWS 1
+#endif
+constexpr int kRows = CW_VEC_ROWS;
+// Minimum wavefronts per SIMD the compiler sizes each kernel's registers
+// for (1: no constraint).  Measured on MI355X at 256 x 128 x 8192: asking
+// for 6 makes the 16-bit velocity kernels and the bfloat16 stress kernel
+// 10-20 % faster; it gains nothing in float32, and the float16 stress
+// kernel, whose scale tracking needs more registers, then spills and slows.
+#ifndef CW_VEC_WAVES
+template <class S> struct Occupancy { static constexpr int vel = 1, str = 1; };
+template <> struct Occupancy<StF16> { static constexpr int vel = 6, str = 1; };
+template <> struct Occupancy<StBF16> { static constexpr int vel = 6, str = 6; };
+#else
+template <class S> struct Occupancy { static constexpr int vel = CW_VEC_WAVES, str = CW_VEC_WAVES; };
+#endif
+
+// velocity update of the lane's VW cells of column (i, j); mr, mt, mz collect |v| maxima
 template <class S>
-__global__ void __launch_bounds__(256) k_velocity_vec(StepArgs a, int nbx)
+__device__ __forceinline__ void velocity_column(const StepArgs &a, int i, int j, int kb, bool live, float &mr,
+                                                float &mt, float &mz)
 {
-  const int bx = blockIdx.x % nbx;
-  const int k0 = (bx * 256 + threadIdx.x) * VW;
-  int i, j;
-  strip_column(blockIdx.x / nbx, a.nr, a.nt, i, j);
-  const bool live = k0 < a.nz;
-  const int kb = live ? k0 : a.nz - VW;            // dead lanes compute on a valid group, store nothing
   const int jm = j == 0 ? a.nt - 1 : j - 1;
   const int jp = j == a.nt - 1 ? 0 : j + 1;
+  const Lanes<S> L(a, kb, j, jm, jp);
   const float *c = a.scl_in;
+  const int i1 = i + 1 < a.nr ? i + 1 : a.nr - 1;
   float srr0[VW], srr1[VW], stt0[VW], stt1[VW], stt_jp[VW], srt0[VW], srt_jm[VW], srt_im[VW];
   float srz0[VW], srz_im[VW], stz0[VW], stz_jm[VW], szz0[VW];
-  ldv<S>(srr0, a.in[SRR], c[SRR], a, i, j, kb);
-  ldv<S>(srr1, a.in[SRR], c[SRR], a, i + 1, j, kb);
-  ldv<S>(stt0, a.in[STT], c[STT], a, i, j, kb);
-  ldv<S>(stt1, a.in[STT], c[STT], a, i + 1, j, kb);
-  ldv<S>(stt_jp, a.in[STT], c[STT], a, i, jp, kb);
-  ldv<S>(srt0, a.in[SRT], c[SRT], a, i, j, kb);
-  ldv<S>(srt_jm, a.in[SRT], c[SRT], a, i, jm, kb);
-  ldv<S>(srt_im, a.in[SRT], c[SRT], a, i - 1, j, kb);
-  ldv<S>(srz0, a.in[SRZ], c[SRZ], a, i, j, kb);
-  ldv<S>(srz_im, a.in[SRZ], c[SRZ], a, i - 1, j, kb);
-  ldv<S>(stz0, a.in[STZ], c[STZ], a, i, j, kb);
-  ldv<S>(stz_jm, a.in[STZ], c[STZ], a, i, jm, kb);
-  ldv<S>(szz0, a.in[SZZ], c[SZZ], a, i, j, kb);
-  const float srz_b = ld1<S>(a.in[SRZ], c[SRZ], a, i, j, kb - 1);     // depth neighbours of the group
-  const float stz_b = ld1<S>(a.in[STZ], c[STZ], a, i, j, kb - 1);
-  const float szz_a = ld1<S>(a.in[SZZ], c[SZZ], a, i, j, kb + VW);
-  const int i1 = i + 1 < a.nr ? i + 1 : a.nr - 1;
+  const rsrc_t R_srr = L.field(a.in[SRR], i), R_stt = L.field(a.in[STT], i), R_srt = L.field(a.in[SRT], i);
+  const rsrc_t R_srz = L.field(a.in[SRZ], i), R_stz = L.field(a.in[STZ], i), R_szz = L.field(a.in[SZZ], i);
+  S::ldb(srr0, R_srr, L.v0, L.sj, c[SRR]);
+  ldf<S>(srr1, L, a, a.in[SRR], c[SRR], i + 1, L.sj);      // zero beyond the last ring
+  S::ldb(stt0, R_stt, L.v0, L.sj, c[STT]);
+  ldf<S>(stt1, L, a, a.in[STT], c[STT], i + 1, L.sj);
+  S::ldb(stt_jp, R_stt, L.v0, L.sjp, c[STT]);
+  S::ldb(srt0, R_srt, L.v0, L.sj, c[SRT]);
+  S::ldb(srt_jm, R_srt, L.v0, L.sjm, c[SRT]);
+  ldf<S>(srt_im, L, a, a.in[SRT], c[SRT], i - 1, L.sj);    // zero on the axis side of ring 0
+  S::ldb(srz0, R_srz, L.v0, L.sj, c[SRZ]);
+  ldf<S>(srz_im, L, a, a.in[SRZ], c[SRZ], i - 1, L.sj);
+  S::ldb(stz0, R_stz, L.v0, L.sj, c[STZ]);
+  S::ldb(stz_jm, R_stz, L.v0, L.sjm, c[STZ]);
+  S::ldb(szz0, R_szz, L.v0, L.sj, c[SZZ]);
+  // depth neighbours of the group (zero outside the grid)
+  const float srz_b = L.has_b ? S::ldb1(R_srz, L.vb, L.sj, c[SRZ]) : 0.0f;
+  const float stz_b = L.has_b ? S::ldb1(R_stz, L.vb, L.sj, c[STZ]) : 0.0f;
+  const float szz_a = L.has_a ? S::ldb1(R_szz, L.va, L.sj, c[SZZ]) : 0.0f;
   float rho0[VW], rho_i1[VW], rho_jp[VW];
-  ldv4(rho0, a.rho, mat(a, i, j, kb));
-  ldv4(rho_i1, a.rho, mat(a, i1, j, kb));
-  ldv4(rho_jp, a.rho, mat(a, i, jp, kb));
-  const float rho_a = a.rho[mat(a, i, j, kb + VW < a.nz ? kb + VW : a.nz - 1)];
+  const rsrc_t R_rho = L.med(a.rho, i);
+  ldb4(rho0, R_rho, L.m0, L.mj);
+  ldb4(rho_i1, L.med(a.rho, i1), L.m0, L.mj);              // medium index clamped at the edge
+  ldb4(rho_jp, R_rho, L.m0, L.mjp);
+  const float rho_a = ldb1(R_rho, L.ma, L.mj);
 
   const float irc = a.inv_rc[i], irf = a.inv_rf[i];
   float r_dr[VW], r_b[VW], r_dz[VW], t_dr[VW], t_b[VW], t_dz[VW], z_dr[VW], z_b[VW], z_dz[VW];
@@ -71,14 +93,13 @@ __global__ void __launch_bounds__(256) k_velocity_vec(StepArgs a, int nbx)
   }
   const int ir = i - (a.nr - a.npr);
   if (ir >= 0 && live) {
-    const size_t q = ((size_t)ir * a.nt + j) * a.nz + kb;
     const float *T = a.tab_r;
-    cpml_v(a.psi_r[R_VR_DR], q, T[AR_F * a.nr + i], T[BR_F * a.nr + i], r_dr);
-    cpml_v(a.psi_r[R_VR_B], q, T[AT_F * a.nr + i], T[BT_F * a.nr + i], r_b);
-    cpml_v(a.psi_r[R_VT_DR], q, T[AR_C * a.nr + i], T[BR_C * a.nr + i], t_dr);
-    cpml_v(a.psi_r[R_VT_B], q, T[AT_C * a.nr + i], T[BT_C * a.nr + i], t_b);
-    cpml_v(a.psi_r[R_VZ_DR], q, T[AR_C * a.nr + i], T[BR_C * a.nr + i], z_dr);
-    cpml_v(a.psi_r[R_VZ_B], q, T[AT_C * a.nr + i], T[BT_C * a.nr + i], z_b);
+    cpml_b(L.f32(a.psi_r[R_VR_DR], ir), L.m0, L.tj, T[AR_F * a.nr + i], T[BR_F * a.nr + i], r_dr);
+    cpml_b(L.f32(a.psi_r[R_VR_B], ir), L.m0, L.tj, T[AT_F * a.nr + i], T[BT_F * a.nr + i], r_b);
+    cpml_b(L.f32(a.psi_r[R_VT_DR], ir), L.m0, L.tj, T[AR_C * a.nr + i], T[BR_C * a.nr + i], t_dr);
+    cpml_b(L.f32(a.psi_r[R_VT_B], ir), L.m0, L.tj, T[AT_C * a.nr + i], T[BT_C * a.nr + i], t_b);
+    cpml_b(L.f32(a.psi_r[R_VZ_DR], ir), L.m0, L.tj, T[AR_C * a.nr + i], T[BR_C * a.nr + i], z_dr);
+    cpml_b(L.f32(a.psi_r[R_VZ_B], ir), L.m0, L.tj, T[AT_C * a.nr + i], T[BT_C * a.nr + i], z_b);
   }
   if (live && a.npz > 0 && (kb < a.npz || kb + VW - 1 >= a.nz - 1 - a.npz)) {
     const float *T = a.tab_z;
@@ -92,12 +113,11 @@ __global__ void __launch_bounds__(256) k_velocity_vec(StepArgs a, int nbx)
       z_dz[e] = cpml1(a.psi_z[Z_VZ_DZ], q, T[AZ_H * a.nz + k], T[BZ_H * a.nz + k], z_dz[e]);
     }
   }
-  const size_t p = at(a, i, j, kb);
+  const rsrc_t R_vr = L.field(a.in[VR], i), R_vt = L.field(a.in[VT], i), R_vz = L.field(a.in[VZ], i);
   float vr[VW], vt[VW], vz[VW];
-  S::template ldv<VW>(vr, a.in[VR], p, c[VR]);
-  S::template ldv<VW>(vt, a.in[VT], p, c[VT]);
-  S::template ldv<VW>(vz, a.in[VZ], p, c[VZ]);
-  float mr = 0.0f, mt = 0.0f, mz = 0.0f;
+  S::ldb(vr, R_vr, L.v0, L.sj, c[VR]);
+  S::ldb(vt, R_vt, L.v0, L.sj, c[VT]);
+  S::ldb(vz, R_vz, L.v0, L.sj, c[VZ]);
 #pragma unroll
   for (int e = 0; e < VW; e++) {
     const float rho_kp = e == VW - 1 ? rho_a : rho0[e + 1];
@@ -111,10 +131,28 @@ __global__ void __launch_bounds__(256) k_velocity_vec(StepArgs a, int nbx)
   }
   if (live) {
     const float *o = a.scl_out;
-    S::template stv<VW>(a.out[VR], p, vr, 1.0f / o[VR]);
-    S::template stv<VW>(a.out[VT], p, vt, 1.0f / o[VT]);
-    S::template stv<VW>(a.out[VZ], p, vz, 1.0f / o[VZ]);
+    S::stb(L.fieldw(a.out[VR], i), L.v0, L.sj, vr, S::scaled ? inv_pow2(o[VR]) : 1.0f);
+    S::stb(L.fieldw(a.out[VT], i), L.v0, L.sj, vt, S::scaled ? inv_pow2(o[VT]) : 1.0f);
+    S::stb(L.fieldw(a.out[VZ], i), L.v0, L.sj, vz, S::scaled ? inv_pow2(o[VZ]) : 1.0f);
   }
+}
+
+// One workgroup per (ring, CW_VEC_ROWS theta rows, depth segment of 1024
+// cells): the rows are done one after the other, so each wavefront lives
+// several column segments long and its set-up is paid once.
+template <class S>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Occupancy<S>::vel)))
+k_velocity_vec(StepArgs a, int nbx)
+{
+  const int bx = blockIdx.x % nbx;
+  const int k0 = (bx * 256 + threadIdx.x) * VW;
+  const int njt = (a.nt + kRows - 1) / kRows;
+  const int c = blockIdx.x / nbx, i = c / njt, j0 = (c - i * njt) * kRows;
+  const int j1 = j0 + kRows < a.nt ? j0 + kRows : a.nt;
+  const bool live = k0 < a.nz;
+  const int kb = live ? k0 : a.nz - VW;            // dead lanes compute on a valid group, store nothing
+  float mr = 0.0f, mt = 0.0f, mz = 0.0f;
+  for (int j = j0; j < j1; j++) velocity_column<S>(a, i, j, kb, live, mr, mt, mz);
   if (S::scaled) {
     track_max(a.maxabs + VR * kMaxSlots, live ? mr : 0.0f);
     track_max(a.maxabs + VT * kMaxSlots, live ? mt : 0.0f);
@@ -122,32 +160,29 @@ __global__ void __launch_bounds__(256) k_velocity_vec(StepArgs a, int nbx)
   }
 }
 
+// stress update of the lane's VW cells of column (i, j); mx collects |sigma| maxima
 template <class S>
-__global__ void __launch_bounds__(256) k_stress_vec(StepArgs a, int nbx)
+__device__ __forceinline__ void stress_column(const StepArgs &a, int i, int j, int kb, bool live, float (&mx)[6])
 {
-  const int bx = blockIdx.x % nbx;
-  const int k0 = (bx * 256 + threadIdx.x) * VW;
-  int i, j;
-  strip_column(blockIdx.x / nbx, a.nr, a.nt, i, j);
-  const bool live = k0 < a.nz;
-  const int kb = live ? k0 : a.nz - VW;
   const int jm = j == 0 ? a.nt - 1 : j - 1;
   const int jp = j == a.nt - 1 ? 0 : j + 1;
+  const Lanes<S> L(a, kb, j, jm, jp);
   const float *o = a.scl_out;                      // velocities at level n+1/2 (output buffer)
   const float *vR = a.out[VR], *vT = a.out[VT], *vZ = a.out[VZ];
+  const rsrc_t R_vr = L.field(vR, i), R_vt = L.field(vT, i), R_vz = L.field(vZ, i);
   float vr0[VW], vr_im[VW], vr_jp[VW], vt0[VW], vt_jm[VW], vt_ip[VW], vz0[VW], vz_ip[VW], vz_jp[VW];
-  ldv<S>(vr0, vR, o[VR], a, i, j, kb);
-  ldv<S>(vr_im, vR, o[VR], a, i - 1, j, kb);
-  ldv<S>(vr_jp, vR, o[VR], a, i, jp, kb);
-  ldv<S>(vt0, vT, o[VT], a, i, j, kb);
-  ldv<S>(vt_jm, vT, o[VT], a, i, jm, kb);
-  ldv<S>(vt_ip, vT, o[VT], a, i + 1, j, kb);
-  ldv<S>(vz0, vZ, o[VZ], a, i, j, kb);
-  ldv<S>(vz_ip, vZ, o[VZ], a, i + 1, j, kb);
-  ldv<S>(vz_jp, vZ, o[VZ], a, i, jp, kb);
-  const float vr_a = ld1<S>(vR, o[VR], a, i, j, kb + VW);
-  const float vt_a = ld1<S>(vT, o[VT], a, i, j, kb + VW);
-  const float vz_b = ld1<S>(vZ, o[VZ], a, i, j, kb - 1);
+  S::ldb(vr0, R_vr, L.v0, L.sj, o[VR]);
+  ldf<S>(vr_im, L, a, vR, o[VR], i - 1, L.sj);              // zero on the axis side of ring 0
+  S::ldb(vr_jp, R_vr, L.v0, L.sjp, o[VR]);
+  S::ldb(vt0, R_vt, L.v0, L.sj, o[VT]);
+  S::ldb(vt_jm, R_vt, L.v0, L.sjm, o[VT]);
+  ldf<S>(vt_ip, L, a, vT, o[VT], i + 1, L.sj);              // zero beyond the last ring
+  S::ldb(vz0, R_vz, L.v0, L.sj, o[VZ]);
+  ldf<S>(vz_ip, L, a, vZ, o[VZ], i + 1, L.sj);
+  S::ldb(vz_jp, R_vz, L.v0, L.sjp, o[VZ]);
+  const float vr_a = L.has_a ? S::ldb1(R_vr, L.va, L.sj, o[VR]) : 0.0f;
+  const float vt_a = L.has_a ? S::ldb1(R_vt, L.va, L.sj, o[VT]) : 0.0f;
+  const float vz_b = L.has_b ? S::ldb1(R_vz, L.vb, L.sj, o[VZ]) : 0.0f;
 
   const float irc = a.inv_rc[i], irf = a.inv_rf[i];
   float err[VW], ett[VW], ezz[VW], rt_dr[VW], rt_b[VW], rz_dr[VW], rz_dz[VW], tz_b[VW], tz_dz[VW];
@@ -168,14 +203,13 @@ __global__ void __launch_bounds__(256) k_stress_vec(StepArgs a, int nbx)
   }
   const int ir = i - (a.nr - a.npr);
   if (ir >= 0 && live) {
-    const size_t q = ((size_t)ir * a.nt + j) * a.nz + kb;
     const float *T = a.tab_r;
-    cpml_v(a.psi_r[R_N_DR], q, T[AR_C * a.nr + i], T[BR_C * a.nr + i], err);
-    cpml_v(a.psi_r[R_N_B], q, T[AT_C * a.nr + i], T[BT_C * a.nr + i], ett);
-    cpml_v(a.psi_r[R_RT_DR], q, T[AR_F * a.nr + i], T[BR_F * a.nr + i], rt_dr);
-    cpml_v(a.psi_r[R_RT_B], q, T[AT_F * a.nr + i], T[BT_F * a.nr + i], rt_b);
-    cpml_v(a.psi_r[R_RZ_DR], q, T[AR_F * a.nr + i], T[BR_F * a.nr + i], rz_dr);
-    cpml_v(a.psi_r[R_TZ_B], q, T[AT_C * a.nr + i], T[BT_C * a.nr + i], tz_b);
+    cpml_b(L.f32(a.psi_r[R_N_DR], ir), L.m0, L.tj, T[AR_C * a.nr + i], T[BR_C * a.nr + i], err);
+    cpml_b(L.f32(a.psi_r[R_N_B], ir), L.m0, L.tj, T[AT_C * a.nr + i], T[BT_C * a.nr + i], ett);
+    cpml_b(L.f32(a.psi_r[R_RT_DR], ir), L.m0, L.tj, T[AR_F * a.nr + i], T[BR_F * a.nr + i], rt_dr);
+    cpml_b(L.f32(a.psi_r[R_RT_B], ir), L.m0, L.tj, T[AT_F * a.nr + i], T[BT_F * a.nr + i], rt_b);
+    cpml_b(L.f32(a.psi_r[R_RZ_DR], ir), L.m0, L.tj, T[AR_F * a.nr + i], T[BR_F * a.nr + i], rz_dr);
+    cpml_b(L.f32(a.psi_r[R_TZ_B], ir), L.m0, L.tj, T[AT_C * a.nr + i], T[BT_C * a.nr + i], tz_b);
   }
   if (live && a.npz > 0 && (kb < a.npz || kb + VW - 1 >= a.nz - 1 - a.npz)) {
     const float *T = a.tab_z;
@@ -191,29 +225,29 @@ __global__ void __launch_bounds__(256) k_stress_vec(StepArgs a, int nbx)
   }
   // moduli: reciprocals of mu at the cell and its neighbours (r, theta, depth)
   const int i1 = i + 1 < a.nr ? i + 1 : a.nr - 1;
-  const int ka = kb + VW < a.nz ? kb + VW : a.nz - 1;   // depth neighbour of the group, clamped
+  const rsrc_t R_mu = L.med(a.mu, i), R_mu1 = L.med(a.mu, i1);   // medium index clamped at the edge
   float lam[VW], mu[VW], m_i1[VW], m_jp[VW], m_i1jp[VW];
-  ldv4(lam, a.lam, mat(a, i, j, kb));
-  ldv4(mu, a.mu, mat(a, i, j, kb));
-  ldv4(m_i1, a.mu, mat(a, i1, j, kb));
-  ldv4(m_jp, a.mu, mat(a, i, jp, kb));
-  ldv4(m_i1jp, a.mu, mat(a, i1, jp, kb));
-  const float ia = rcp(a.mu[mat(a, i, j, ka)]), ia_i1 = rcp(a.mu[mat(a, i1, j, ka)]);
-  const float ia_jp = rcp(a.mu[mat(a, i, jp, ka)]);
+  ldb4(lam, L.med(a.lam, i), L.m0, L.mj);
+  ldb4(mu, R_mu, L.m0, L.mj);
+  ldb4(m_i1, R_mu1, L.m0, L.mj);
+  ldb4(m_jp, R_mu, L.m0, L.mjp);
+  ldb4(m_i1jp, R_mu1, L.m0, L.mjp);
+  const float ia = rcp(ldb1(R_mu, L.ma, L.mj)), ia_i1 = rcp(ldb1(R_mu1, L.ma, L.mj));
+  const float ia_jp = rcp(ldb1(R_mu, L.ma, L.mjp));
   float im[VW], im_i1[VW], im_jp[VW];
 #pragma unroll
   for (int e = 0; e < VW; e++) { im[e] = rcp(mu[e]); im_i1[e] = rcp(m_i1[e]); im_jp[e] = rcp(m_jp[e]); }
 
-  const size_t p = at(a, i, j, kb);
   const float *c = a.scl_in;
+  const rsrc_t R_srr = L.field(a.in[SRR], i), R_stt = L.field(a.in[STT], i), R_szz = L.field(a.in[SZZ], i);
+  const rsrc_t R_srt = L.field(a.in[SRT], i), R_srz = L.field(a.in[SRZ], i), R_stz = L.field(a.in[STZ], i);
   float srr[VW], stt[VW], szz[VW], srt[VW], srz[VW], stz[VW];
-  S::template ldv<VW>(srr, a.in[SRR], p, c[SRR]);
-  S::template ldv<VW>(stt, a.in[STT], p, c[STT]);
-  S::template ldv<VW>(szz, a.in[SZZ], p, c[SZZ]);
-  S::template ldv<VW>(srt, a.in[SRT], p, c[SRT]);
-  S::template ldv<VW>(srz, a.in[SRZ], p, c[SRZ]);
-  S::template ldv<VW>(stz, a.in[STZ], p, c[STZ]);
-  float mx[6] = {0, 0, 0, 0, 0, 0};
+  S::ldb(srr, R_srr, L.v0, L.sj, c[SRR]);
+  S::ldb(stt, R_stt, L.v0, L.sj, c[STT]);
+  S::ldb(szz, R_szz, L.v0, L.sj, c[SZZ]);
+  S::ldb(srt, R_srt, L.v0, L.sj, c[SRT]);
+  S::ldb(srz, R_srz, L.v0, L.sj, c[SRZ]);
+  S::ldb(stz, R_stz, L.v0, L.sj, c[STZ]);
 #pragma unroll
   for (int e = 0; e < VW; e++) {
     const float ik = e == VW - 1 ? ia : im[e + 1];            // 1/mu at k+1
@@ -236,13 +270,28 @@ __global__ void __launch_bounds__(256) k_stress_vec(StepArgs a, int nbx)
     mx[4] = fmaxf(mx[4], fabsf(srz[e])); mx[5] = fmaxf(mx[5], fabsf(stz[e]));
   }
   if (live) {
-    S::template stv<VW>(a.out[SRR], p, srr, 1.0f / o[SRR]);
-    S::template stv<VW>(a.out[STT], p, stt, 1.0f / o[STT]);
-    S::template stv<VW>(a.out[SZZ], p, szz, 1.0f / o[SZZ]);
-    S::template stv<VW>(a.out[SRT], p, srt, 1.0f / o[SRT]);
-    S::template stv<VW>(a.out[SRZ], p, srz, 1.0f / o[SRZ]);
-    S::template stv<VW>(a.out[STZ], p, stz, 1.0f / o[STZ]);
+    S::stb(L.fieldw(a.out[SRR], i), L.v0, L.sj, srr, S::scaled ? inv_pow2(o[SRR]) : 1.0f);
+    S::stb(L.fieldw(a.out[STT], i), L.v0, L.sj, stt, S::scaled ? inv_pow2(o[STT]) : 1.0f);
+    S::stb(L.fieldw(a.out[SZZ], i), L.v0, L.sj, szz, S::scaled ? inv_pow2(o[SZZ]) : 1.0f);
+    S::stb(L.fieldw(a.out[SRT], i), L.v0, L.sj, srt, S::scaled ? inv_pow2(o[SRT]) : 1.0f);
+    S::stb(L.fieldw(a.out[SRZ], i), L.v0, L.sj, srz, S::scaled ? inv_pow2(o[SRZ]) : 1.0f);
+    S::stb(L.fieldw(a.out[STZ], i), L.v0, L.sj, stz, S::scaled ? inv_pow2(o[STZ]) : 1.0f);
   }
+}
+
+template <class S>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Occupancy<S>::str)))
+k_stress_vec(StepArgs a, int nbx)
+{
+  const int bx = blockIdx.x % nbx;
+  const int k0 = (bx * 256 + threadIdx.x) * VW;
+  const int njt = (a.nt + kRows - 1) / kRows;
+  const int c = blockIdx.x / nbx, i = c / njt, j0 = (c - i * njt) * kRows;
+  const int j1 = j0 + kRows < a.nt ? j0 + kRows : a.nt;
+  const bool live = k0 < a.nz;
+  const int kb = live ? k0 : a.nz - VW;
+  float mx[6] = {0, 0, 0, 0, 0, 0};
+  for (int j = j0; j < j1; j++) stress_column<S>(a, i, j, kb, live, mx);
   if (S::scaled) {
 #pragma unroll
     for (int q = 0; q < 6; q++) track_max(a.maxabs + (SRR + q) * kMaxSlots, live ? mx[q] : 0.0f);
@@ -267,7 +316,7 @@ bool vec_applies(int nz) { return nz % VW == 0 && nz >= VW; }
 hipError_t launch_velocity_vec(const StepArgs &a, int storage, hipStream_t stream)
 {
   const int nbx = (a.nz / VW + 255) / 256;
-  const long g = (long)nbx * a.nt * a.nr;
+  const long g = (long)nbx * ((a.nt + kRows - 1) / kRows) * a.nr;
   if (g > 0x7fffffff || !vec_applies(a.nz)) return hipErrorInvalidConfiguration;
   return dispatch(storage, [&](auto s) {
     hipLaunchKernelGGL(k_velocity_vec<decltype(s)>, dim3((unsigned)g), dim3(256), 0, stream, a, nbx);
@@ -278,7 +327,7 @@ hipError_t launch_velocity_vec(const StepArgs &a, int storage, hipStream_t strea
 hipError_t launch_stress_vec(const StepArgs &a, int storage, hipStream_t stream)
 {
   const int nbx = (a.nz / VW + 255) / 256;
-  const long g = (long)nbx * a.nt * a.nr;
+  const long g = (long)nbx * ((a.nt + kRows - 1) / kRows) * a.nr;
   if (g > 0x7fffffff || !vec_applies(a.nz)) return hipErrorInvalidConfiguration;
   return dispatch(storage, [&](auto s) {
     hipLaunchKernelGGL(k_stress_vec<decltype(s)>, dim3((unsigned)g), dim3(256), 0, stream, a, nbx);

@@ -31,7 +31,7 @@ EXPORTS = ("cw_create", "cw_set_material", "cw_set_material_rz", "cw_set_pml", "
            "cw_workspace_bytes", "cw_bind", "cw_step", "cw_sync", "cw_get_traces",
            "cw_get_field", "cw_set_field", "cw_energy", "cw_reset", "cw_steps_done",
            "cw_ricker", "cw_destroy", "cw_last_error", "cw_profile", "cw_profile_read",
-           "cw_set_path", "cw_set_storage")
+           "cw_set_path", "cw_set_storage", "cw_stream_probe")
 
 STORAGE = {"f32": 0, "f16": 1, "bf16": 2}
 
@@ -91,6 +91,7 @@ def load():
         "cw_set_path": [P, I32],
         "cw_set_storage": [P, I32],
         "cw_profile_read": [P, I32, DP, ctypes.POINTER(I64)],
+        "cw_stream_probe": [P, ctypes.c_uint64, I32, I32, I32, P, DP],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -123,6 +124,26 @@ def ricker(f0: float, t) -> np.ndarray:
     out = np.empty_like(t)
     _check(load().cw_ricker(float(f0), _dp(t), len(t), _dp(out)))
     return out
+
+
+def stream_probe(nread: int, nwrite: int, bytes_per_array: int = 1 << 30, reps: int = 10,
+                 device: str = "cuda") -> float:
+    """Achieved bytes per second of a kernel that only streams nread arrays
+    in and nwrite arrays out (the access pattern of a step kernel without
+    its stencil), on a torch-allocated buffer on the current stream."""
+    import torch
+    lib = load()
+    n = nread + nwrite
+    buf = torch.empty(n * bytes_per_array + 256, dtype=torch.uint8, device=device)
+    ptr = buf.data_ptr()
+    ptr += (-ptr) % 256
+    buf[:].zero_()
+    stream = torch.cuda.current_stream(buf.device).cuda_stream
+    ms = ctypes.c_double()
+    _check(lib.cw_stream_probe(ctypes.c_void_p(ptr), int(bytes_per_array), int(nread), int(nwrite),
+                               int(reps), ctypes.c_void_p(stream), ctypes.byref(ms)))
+    del buf
+    return n * bytes_per_array / (ms.value * 1e-3)
 
 
 class Sim:

@@ -114,6 +114,18 @@ def test_validation_errors():
     assert lib.cw_bind(s.h, None, 0, None) == -1
 
 
+def test_stream_probe_validation():
+    """The bandwidth reference rejects bad arguments before touching the device."""
+    lib = cwell.load()
+    ms = ctypes.c_double()
+    assert lib.cw_stream_probe(None, 1 << 20, 9, 3, 1, None, ctypes.byref(ms)) == -1
+    assert lib.cw_stream_probe(ctypes.c_void_p(4096 + 8), 1 << 20, 9, 3, 1, None, ctypes.byref(ms)) == -1
+    assert lib.cw_stream_probe(ctypes.c_void_p(4096), 1000, 9, 3, 1, None, ctypes.byref(ms)) == -1
+    assert lib.cw_stream_probe(ctypes.c_void_p(4096), 1 << 20, 9, 3, 0, None, ctypes.byref(ms)) == -1
+    assert lib.cw_stream_probe(ctypes.c_void_p(4096), 1 << 20, 7, 2, 1, None, ctypes.byref(ms)) == -2
+    assert b"7 reads" in lib.cw_last_error()
+
+
 def test_workspace_size_accounts_for_everything():
     shape = (10, 4, 24)
     h = 5e-3
