@@ -89,9 +89,10 @@ PROFILE_VARIANTS = {
     "two_pass_f16": "--path two-pass --storage f16",
     "two_pass_bf16": "--path two-pass --storage bf16",
     "fused_f32": "--path fused --storage f32",
+    "march_f32": "--path march --storage f32",
 }
 PROFILE_RUN = ("python3 -u bench.py --steps 20 --warmup 5 --no-cpu-baseline --no-storage-forms --no-stream-ceiling "
-               "--copy-gib 1")
+               "--no-graph-replay --copy-gib 1")
 PROFILE_PASSES = (
     ("stats", "--kernel-trace --stats"),
     ("fetch", "--pmc FETCH_SIZE"),
@@ -268,9 +269,11 @@ def cpu_baseline(w, target_s: float):
                       "no z layer), %d FP64 steps in %.1f s" % (w.nr, w.nt, nzs, steps, el)}
 
 
-def run_steps(w, storage: str, path: str, warmup: int, steps: int):
+def run_steps(w, storage: str, path: str, warmup: int, steps: int, graph: int = 0, profile: bool = True):
     """Set up workload w, bind it, run warmup + timed steps; returns
-    (seconds for the timed steps, {kernel: (ms, launches)}, traces)."""
+    (seconds for the timed steps, {kernel: (ms, launches)}, traces).  With
+    graph > 0 the steps are replayed from a captured graph of that many
+    steps; per-launch timing (profile) needs ordinary launches."""
     import numpy as np
     import torch
     from paper_2302_13907_amd import cwell
@@ -289,20 +292,21 @@ def run_steps(w, storage: str, path: str, warmup: int, steps: int):
     s.set_trace_capacity(total)
     s.set_path(path)
     s.set_storage(storage)
+    s.set_graph(graph)
     log("binding %.2f GB workspace (%s storage)" % (s.workspace_bytes() / 1e9, storage))
     s.bind("cuda:0")
     log("warm-up %d steps" % warmup)
     s.step(warmup)
     s.sync()
     torch.cuda.synchronize()
-    s.profile(True)
+    s.profile(profile)
     log("timing %d steps" % steps)
     t0 = time.perf_counter()
     s.step(steps)
     s.sync()
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
-    times = {k: s.kernel_time(k) for k in ("velocity", "stress", "fused", "inject", "record")}
+    times = {k: s.kernel_time(k) for k in ("velocity", "stress", "fused", "inject", "record")} if profile else {}
     s.profile(False)
     tr = s.traces()
     s.close()
@@ -328,6 +332,20 @@ def stream_ceiling(kernel: str, axisym: bool, roofline: dict):
     copy = cwell.stream_probe(1, 1) / 1e9
     return {"kernel": kernel, "reads": r, "writes": w, "GBps": round(mix, 1), "copy_GBps": round(copy, 1),
             "frac_of_ceiling": round(roofline["achieved"] / mix, 4)}
+
+
+def graph_replay(path: str, graph: int = 20, steps: int = 300):
+    """The parity-size workload (48 x 32 x 192, launch-bound) with ordinary
+    launches and with graph replay of `graph` steps, Gcell-updates/s."""
+    from paper_2302_13907_amd import inputs
+    w = inputs.parity_case()
+    res = {"workload": w.name, "steps": steps, "graph_steps": graph}
+    for g in (0, graph):
+        el, _, _ = run_steps(w, "f32", path, 2 * graph, steps, graph=g, profile=False)
+        res["graph" if g else "ordinary"] = {"value": round(w.cells * steps / el / 1e9, 3),
+                                             "us_per_step": round(el / steps * 1e6, 2)}
+    res["speedup"] = round(res["graph"]["value"] / res["ordinary"]["value"], 3)
+    return res
 
 
 def storage_forms(path: str, warmup: int = 10, steps: int = 100):
@@ -364,6 +382,8 @@ def main():
     ap.add_argument("--no-storage-forms", action="store_true",
                     help="skip the float32 / float16 / bfloat16 storage comparison on the "
                          "192 x 96 x 4096 mixed-precision workload")
+    ap.add_argument("--no-graph-replay", action="store_true",
+                    help="skip the ordinary-launch / graph-replay comparison on the parity-size workload")
     ap.add_argument("--no-stream-ceiling", action="store_true",
                     help="skip the streaming-bandwidth reference for the step kernels' read/write mixes")
     ap.add_argument("--print-profile-commands", nargs=2, metavar=("VARIANT", "OUTDIR"),
@@ -407,7 +427,8 @@ def main():
     axisym = w.rock_jitter == 0          # the medium is then stored once per (ring, depth)
     alg = algorithmic_bytes(dom, w, n_r, n_z, fb, axisym)
     achieved = alg / avg_s / 1e9
-    variant = "%s_%s" % ("fused" if dom == "fused" else "two_pass", args.storage)
+    form = "fused" if dom == "fused" else ("march" if args.path == "march" else "two_pass")
+    variant = "%s_%s" % (form, args.storage)
     traffic = measured_traffic(variant, dom, w.name)
     # the whole step against the single-pass floor: every field read and written once,
     # the moduli read once, each layer memory variable read and written once
@@ -453,6 +474,8 @@ def main():
         out["stream_ceiling"] = stream_ceiling(dom, axisym, out["roofline"])
     if not args.no_storage_forms:
         out["storage_forms"] = storage_forms(args.path)
+    if not args.no_graph_replay:
+        out["graph_replay"] = graph_replay(args.path)
     if not args.no_cpu_baseline:
         log("CPU baseline: FP64 oracle for about %.0f s" % args.cpu_seconds)
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)

@@ -208,6 +208,19 @@ cw_status cw_set_storage(cw_sim *s, int32_t storage);
 enum { CW_PATH_AUTO = 0, CW_PATH_TWO_PASS, CW_PATH_FUSED, CW_PATH_MARCH };
 cw_status cw_set_path(cw_sim *s, int32_t path);
 
+/* Graph replay of the two-pass step.  With steps > 0 (even, at most 4096),
+   cw_step records the kernel launches of `steps` consecutive steps into a
+   HIP graph the first time it needs them and then advances the simulation
+   by replaying that graph, one launch per `steps` steps; step counts that
+   are not a whole number of graphs, and a start on an odd step, are done
+   with ordinary launches.  Results are bitwise those of ordinary launches
+   (the source and receiver kernels read the step number from device
+   memory).  0 (default) switches it off.  Kernel timing (cw_profile) and
+   CW_PATH_FUSED always use ordinary launches.  The graph belongs to the
+   simulation and stays valid across cw_reset; changing the path drops it.
+   Callable at any time; CW_ERR_RANGE for an odd or too large count. */
+cw_status cw_set_graph(cw_sim *s, int32_t steps);
+
 /* Kernel timing.  With enable = 1, cw_step brackets every launch of the
    step kernels with HIP events on the simulation's stream (a few
    microseconds of overhead per launch); enable = 0 stops recording and

@@ -18,6 +18,7 @@ namespace {
 
 constexpr double kPi = 3.14159265358979323846;
 constexpr int kEnergyBlocks = 1024;
+constexpr int kMaxGraphSteps = 4096;
 #ifndef CW_AUTO_FUSED
 #define CW_AUTO_FUSED 0
 #endif
@@ -99,6 +100,19 @@ struct cw_sim {
   Receiver *d_rec = nullptr;
   double *d_traces = nullptr;
   double *d_energy = nullptr;   // kEnergyBlocks partials + 1 result
+  int64_t *d_step = nullptr;    // steps done, as the injection and receiver kernels read it
+  // graph replay of the two-pass step (cw_set_graph)
+  int graph_steps = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  hipStream_t capture_stream = nullptr;   // captures run here: the caller's stream may be the null stream
+  void drop_graph()
+  {
+    if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    graph_exec = nullptr;
+    graph = nullptr;
+  }
   int cur = 0;                  // fields[cur] holds the current state
   int64_t nstep = 0;
   // kernel timing: (kernel id, start, stop) per recorded launch
@@ -108,6 +122,8 @@ struct cw_sim {
   std::vector<hipEvent_t> event_pool;
   ~cw_sim()
   {
+    drop_graph();
+    if (capture_stream) (void)hipStreamDestroy(capture_stream);
     for (auto &r : prof) { event_pool.push_back(r.start); event_pool.push_back(r.stop); }
     for (hipEvent_t e : event_pool) (void)hipEventDestroy(e);
   }
@@ -139,7 +155,7 @@ int inject_count(const cw_sim *s)
 }
 
 struct Layout {
-  size_t fields, material, metric, tabr, tabz, psir, psiz, inject, amp, rec, traces, energy, scales, total;
+  size_t fields, material, metric, tabr, tabz, psir, psiz, inject, amp, rec, traces, energy, scales, step, total;
 };
 
 Layout layout(const cw_sim *s)
@@ -160,6 +176,7 @@ Layout layout(const cw_sim *s)
   L.traces = take(s->receivers.size() * (size_t)s->trace_cap * sizeof(double));
   L.energy = take((kEnergyBlocks + 1) * sizeof(double));
   L.scales = take(3 * NF * sizeof(float) + NF * kMaxSlots * sizeof(unsigned));
+  L.step = take(sizeof(int64_t));
   L.total = off;
   return L;
 }
@@ -314,6 +331,7 @@ cw_status zero_state(cw_sim *s)
   if (psiz) HIPCHK(hipMemsetAsync(s->ws + L.psiz, 0, psiz, s->stream));
   const size_t tb = s->receivers.size() * (size_t)s->trace_cap * sizeof(double);
   if (tb) HIPCHK(hipMemsetAsync(s->ws + L.traces, 0, tb, s->stream));
+  HIPCHK(hipMemsetAsync(s->d_step, 0, sizeof(int64_t), s->stream));
   s->cur = 0;
   s->psi_cur = 0;
   s->nstep = 0;
@@ -507,6 +525,7 @@ cw_status cw_bind(cw_sim *s, void *workspace, uint64_t bytes, void *stream)
   if (!s->have_material) return fail(CW_ERR_STATE, "medium not set");
   if (!(s->dt > 0)) return fail(CW_ERR_STATE, "dt not set");
   if (!workspace) return fail(CW_ERR_ARG, "null workspace");
+  s->drop_graph();
   if (((uintptr_t)workspace & 255) != 0) return fail(CW_ERR_ARG, "workspace not 256-byte aligned");
   const Layout L = layout(s);
   if (bytes < L.total)
@@ -540,6 +559,7 @@ cw_status cw_bind(cw_sim *s, void *workspace, uint64_t bytes, void *stream)
   s->d_rec = (Receiver *)(w + L.rec);
   s->d_traces = (double *)(w + L.traces);
   s->d_energy = (double *)(w + L.energy);
+  s->d_step = (int64_t *)(w + L.step);
 
   // injections: dt * w[n] / V per target node, V the node (or ring) volume
   std::vector<float> amps(amp_floats(s));
@@ -638,48 +658,105 @@ cw_status cw_step(cw_sim *s, int64_t nsteps)
     return march ? launch_stress_march(a, s->storage, s->stream)
                  : vec ? launch_stress_vec(a, s->storage, s->stream) : launch_stress_basic(a, s->storage, s->stream);
   };
-  for (int64_t t = 0; t < nsteps; t++) {
-    const StepArgs a = step_args(s, s->cur, 1 - s->cur);
-    const int64_t n = s->nstep;
-    if (fused) {
-      f.nr = s->nr; f.nt = s->nt; f.nz = s->nz; f.npr = s->npr; f.npz = s->npz; f.nzs = nzs_of(s);
-      f.dt = a.dt; f.inv_dr = a.inv_dr; f.inv_dz = a.inv_dz; f.inv_dth = a.inv_dth;
-      f.n = s->n;
-      f.slab_r = (size_t)s->npr * s->nt * s->nz;
-      f.slab_z = (size_t)s->nr * s->nt * nzs_of(s);
-      f.in = s->fields[s->cur][0];
-      f.out = s->fields[1 - s->cur][0];
-      f.med = s->d_rho;
-      f.m_n = s->nm;
-      f.m_ring = a.m_ring;
-      f.m_row = a.m_row;
-      f.psi_r_in = s->psi_r[s->psi_cur][0]; f.psi_r_out = s->psi_r[1 - s->psi_cur][0];
-      f.psi_z_in = s->psi_z[s->psi_cur][0]; f.psi_z_out = s->psi_z[1 - s->psi_cur][0];
-      f.inv_rc = s->d_inv_rc; f.inv_rf = s->d_inv_rf; f.tab_r = s->d_tab_r; f.tab_z = s->d_tab_z;
-      f.ninj = 0;
-      for (int e = 0; e < s->ninject; e++) {
-        const Inject &in = s->inject_host[e];
-        if (n >= in.nsamp) continue;
-        InjectStep &o = f.inj[f.ninj++];
-        o.field = in.field; o.i = in.i; o.j = in.j; o.k = in.k; o.phase = in.phase;
-        o.amp = in.scale * s->inject_amp[e][n];
-      }
-      if ((st = timed(s, CW_K_FUSED, [&] { return launch_fused(f, s->stream); })) != CW_OK) return st;
-      s->psi_cur = 1 - s->psi_cur;
-    } else {
-      if ((st = timed(s, CW_K_VELOCITY, [&] { return velocity(a); })) != CW_OK) return st;
-      if (s->ninject && (st = timed(s, CW_K_INJECT, [&] {
-            return launch_inject(s->d_inject, s->ninject, 0, n, a, s->storage, s->stream); })) != CW_OK) return st;
-      if ((st = timed(s, CW_K_STRESS, [&] { return stress(a); })) != CW_OK) return st;
-      if (s->ninject && (st = timed(s, CW_K_INJECT, [&] {
-            return launch_inject(s->d_inject, s->ninject, 1, n, a, s->storage, s->stream); })) != CW_OK) return st;
-    }
+  // One step's launches.  Nothing in them depends on the host's step count
+  // (the injection and receiver kernels read the device counter, which the
+  // last launch advances), so the launches of an even number of two-pass
+  // steps can be captured once and replayed.
+  auto finish_step = [&](const StepArgs &a) -> cw_status {
     if (nrec && (st = timed(s, CW_K_RECORD, [&] {
-          return launch_record(s->d_rec, nrec, n, s->trace_cap, a, s->storage, s->d_traces, s->stream); })) != CW_OK)
+          return launch_record(s->d_rec, nrec, s->d_step, s->trace_cap, a, s->storage, s->d_traces, s->stream);
+        })) != CW_OK)
       return st;
     if (s->storage == ST_F16)
       HIPCHK(launch_rescale(s->d_scl + (1 - s->cur) * NF, s->d_scl + 2 * NF, s->d_maxabs, s->stream));
+    HIPCHK(launch_step_done(s->d_step, s->stream));
     s->cur = 1 - s->cur;
+    return CW_OK;
+  };
+  auto two_pass_step = [&]() -> cw_status {
+    const StepArgs a = step_args(s, s->cur, 1 - s->cur);
+    if ((st = timed(s, CW_K_VELOCITY, [&] { return velocity(a); })) != CW_OK) return st;
+    if (s->ninject && (st = timed(s, CW_K_INJECT, [&] {
+          return launch_inject(s->d_inject, s->ninject, 0, s->d_step, a, s->storage, s->stream); })) != CW_OK)
+      return st;
+    if ((st = timed(s, CW_K_STRESS, [&] { return stress(a); })) != CW_OK) return st;
+    if (s->ninject && (st = timed(s, CW_K_INJECT, [&] {
+          return launch_inject(s->d_inject, s->ninject, 1, s->d_step, a, s->storage, s->stream); })) != CW_OK)
+      return st;
+    return finish_step(a);
+  };
+  auto fused_step = [&](int64_t n) -> cw_status {   // source amplitudes of step n go in as arguments
+    const StepArgs a = step_args(s, s->cur, 1 - s->cur);
+    f.nr = s->nr; f.nt = s->nt; f.nz = s->nz; f.npr = s->npr; f.npz = s->npz; f.nzs = nzs_of(s);
+    f.dt = a.dt; f.inv_dr = a.inv_dr; f.inv_dz = a.inv_dz; f.inv_dth = a.inv_dth;
+    f.n = s->n;
+    f.slab_r = (size_t)s->npr * s->nt * s->nz;
+    f.slab_z = (size_t)s->nr * s->nt * nzs_of(s);
+    f.in = s->fields[s->cur][0];
+    f.out = s->fields[1 - s->cur][0];
+    f.med = s->d_rho;
+    f.m_n = s->nm;
+    f.m_ring = a.m_ring;
+    f.m_row = a.m_row;
+    f.psi_r_in = s->psi_r[s->psi_cur][0]; f.psi_r_out = s->psi_r[1 - s->psi_cur][0];
+    f.psi_z_in = s->psi_z[s->psi_cur][0]; f.psi_z_out = s->psi_z[1 - s->psi_cur][0];
+    f.inv_rc = s->d_inv_rc; f.inv_rf = s->d_inv_rf; f.tab_r = s->d_tab_r; f.tab_z = s->d_tab_z;
+    f.ninj = 0;
+    for (int e = 0; e < s->ninject; e++) {
+      const Inject &in = s->inject_host[e];
+      if (n >= in.nsamp) continue;
+      InjectStep &o = f.inj[f.ninj++];
+      o.field = in.field; o.i = in.i; o.j = in.j; o.k = in.k; o.phase = in.phase;
+      o.amp = in.scale * s->inject_amp[e][n];
+    }
+    if ((st = timed(s, CW_K_FUSED, [&] { return launch_fused(f, s->stream); })) != CW_OK) return st;
+    s->psi_cur = 1 - s->psi_cur;
+    return finish_step(a);
+  };
+
+  if (fused) {
+    for (int64_t t = 0; t < nsteps; t++) {
+      if ((st = fused_step(s->nstep)) != CW_OK) return st;
+      s->nstep++;
+    }
+    return CW_OK;
+  }
+  const bool use_graph = s->graph_steps > 0 && !s->profiling;
+  int64_t done = 0;
+  while (done < nsteps) {
+    if (use_graph && s->cur == 0 && nsteps - done >= s->graph_steps) {
+      if (!s->graph_exec) {
+        // capture (nothing runs) on a stream of our own, since the caller's may be
+        // the null stream, which cannot be captured; an even step count leaves the
+        // buffers as they were
+        if (!s->capture_stream) HIPCHK(hipStreamCreateWithFlags(&s->capture_stream, hipStreamNonBlocking));
+        hipStream_t user = s->stream;
+        s->stream = s->capture_stream;
+        const hipError_t eb = hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal);
+        cw_status cst = eb == hipSuccess ? CW_OK : fail(CW_ERR_HIP, "graph capture: %s", hipGetErrorString(eb));
+        for (int g = 0; g < s->graph_steps && cst == CW_OK; g++) cst = two_pass_step();
+        hipGraph_t gr = nullptr;
+        const hipError_t ee = eb == hipSuccess ? hipStreamEndCapture(s->stream, &gr) : hipSuccess;
+        s->stream = user;
+        s->cur = 0;
+        if (cst != CW_OK || ee != hipSuccess) {
+          if (gr) (void)hipGraphDestroy(gr);
+          return cst != CW_OK ? cst : fail(CW_ERR_HIP, "graph capture failed: %s", hipGetErrorString(ee));
+        }
+        s->graph = gr;
+        const hipError_t ei = hipGraphInstantiate(&s->graph_exec, gr, nullptr, nullptr, 0);
+        if (ei != hipSuccess) {
+          s->drop_graph();
+          return fail(CW_ERR_HIP, "graph instantiation failed: %s", hipGetErrorString(ei));
+        }
+      }
+      HIPCHK(hipGraphLaunch(s->graph_exec, s->stream));
+      done += s->graph_steps;
+      s->nstep += s->graph_steps;
+      continue;
+    }
+    if ((st = two_pass_step()) != CW_OK) return st;
+    done++;
     s->nstep++;
   }
   return CW_OK;
@@ -829,7 +906,18 @@ cw_status cw_set_path(cw_sim *s, int32_t path)
 {
   if (!s) return fail(CW_ERR_ARG, "null simulation");
   if (path < CW_PATH_AUTO || path > CW_PATH_MARCH) return fail(CW_ERR_ARG, "bad path %d", path);
+  if (path != s->path) s->drop_graph();
   s->path = path;
+  return CW_OK;
+}
+
+cw_status cw_set_graph(cw_sim *s, int32_t steps)
+{
+  if (!s) return fail(CW_ERR_ARG, "null simulation");
+  if (steps < 0 || steps % 2 || steps > kMaxGraphSteps)
+    return fail(CW_ERR_RANGE, "graph steps must be even and in [0, %d] (have %d)", kMaxGraphSteps, steps);
+  s->drop_graph();
+  s->graph_steps = steps;
   return CW_OK;
 }
 

@@ -154,14 +154,15 @@ constexpr int kMaxFusedRings = 2048;            // nr limit of the fused step (L
 hipError_t launch_fused(const FusedArgs &f, hipStream_t stream);
 hipError_t launch_velocity_basic(const StepArgs &a, int storage, hipStream_t stream);
 hipError_t launch_stress_basic(const StepArgs &a, int storage, hipStream_t stream);
-hipError_t launch_inject(const Inject *dev_list, int ninj, int phase, int64_t step,
+hipError_t launch_inject(const Inject *dev_list, int ninj, int phase, const int64_t *step,
                          const StepArgs &a, int storage, hipStream_t stream);
-hipError_t launch_record(const Receiver *dev_rec, int nrec, int64_t step, int64_t cap,
+hipError_t launch_record(const Receiver *dev_rec, int nrec, const int64_t *step, int64_t cap,
                          const StepArgs &a, int storage, double *traces, hipStream_t stream);
 hipError_t launch_energy(const StepArgs &a, int storage, double *partials, int nblocks, double scale,
                          double *result, hipStream_t stream);
 // After a float16 step: record the scale the level-n+1 buffer was written
 // with (scl_written = scl_next), derive the next scale from maxabs, clear it.
+hipError_t launch_step_done(int64_t *step, hipStream_t stream);
 hipError_t launch_rescale(float *scl_written, float *scl_next, unsigned *maxabs, hipStream_t stream);
 constexpr int kF16TargetExp = 11;   // scaled float16 maxima land in [2^10, 2^11)
 // depth-vectorized two-pass kernels (4 cells per thread), when nz % 4 == 0

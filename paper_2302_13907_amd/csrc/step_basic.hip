@@ -263,8 +263,9 @@ __global__ void __launch_bounds__(256) k_stress_basic(StepArgs a, int nbx)
 // sources hitting the same node add in a fixed order.
 template <class S>
 __global__ void __launch_bounds__(256) k_inject(const Inject *list, int ninj, int phase,
-                                                int64_t step, StepArgs a)
+                                                const int64_t *stepp, StepArgs a)
 {
+  const int64_t step = *stepp;                     // steps done (device counter)
   for (int m = 0; m < ninj; m++) {
     const Inject e = list[m];
     if (e.phase == phase && step < e.nsamp) {
@@ -285,9 +286,10 @@ __global__ void __launch_bounds__(256) k_inject(const Inject *list, int ninj, in
 
 // One wavefront per receiver; float64 sum over the ring in a fixed order.
 template <class S>
-__global__ void __launch_bounds__(64) k_record(const Receiver *rec, int64_t step, int64_t cap,
+__global__ void __launch_bounds__(64) k_record(const Receiver *rec, const int64_t *stepp, int64_t cap,
                                                StepArgs a, double *traces)
 {
+  const int64_t step = *stepp;
   const Receiver r = rec[blockIdx.x];
   const int j0 = r.j < 0 ? 0 : r.j, j1 = r.j < 0 ? a.nt : r.j + 1;
   const float *o = a.scl_out;
@@ -440,7 +442,7 @@ hipError_t launch_stress_basic(const StepArgs &a, int storage, hipStream_t strea
   });
 }
 
-hipError_t launch_inject(const Inject *dev_list, int ninj, int phase, int64_t step,
+hipError_t launch_inject(const Inject *dev_list, int ninj, int phase, const int64_t *step,
                          const StepArgs &a, int storage, hipStream_t stream)
 {
   if (ninj == 0) return hipSuccess;
@@ -450,7 +452,7 @@ hipError_t launch_inject(const Inject *dev_list, int ninj, int phase, int64_t st
   });
 }
 
-hipError_t launch_record(const Receiver *dev_rec, int nrec, int64_t step, int64_t cap,
+hipError_t launch_record(const Receiver *dev_rec, int nrec, const int64_t *step, int64_t cap,
                          const StepArgs &a, int storage, double *traces, hipStream_t stream)
 {
   if (nrec == 0) return hipSuccess;
@@ -469,6 +471,18 @@ hipError_t launch_energy(const StepArgs &a, int storage, double *partials, int n
   });
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(256), 0, stream, partials, nblocks, scale, result);
+  return hipGetLastError();
+}
+
+// the step counter the injection and receiver kernels read, advanced once per step
+__global__ void k_step_done(int64_t *step)
+{
+  if (threadIdx.x == 0) *step += 1;
+}
+
+hipError_t launch_step_done(int64_t *step, hipStream_t stream)
+{
+  hipLaunchKernelGGL(k_step_done, dim3(1), dim3(64), 0, stream, step);
   return hipGetLastError();
 }
 

@@ -34,7 +34,10 @@ namespace {
 #ifndef FUSED_PREFETCH_DEPTH
 #define FUSED_PREFETCH_DEPTH 1
 #endif
-constexpr int TJ = 10;          // wavefronts (theta rows) per workgroup, 2 of them halo
+#ifndef FUSED_TJ
+#define FUSED_TJ 10
+#endif
+constexpr int TJ = FUSED_TJ;    // wavefronts (theta rows) per workgroup, 2 of them halo
 constexpr int ZT = 62;          // depth cells owned per wavefront (64 lanes - 2 halo)
 constexpr int NX = 8;           // floats exchanged per lane and ring through LDS
 constexpr int DEPTH = FUSED_PREFETCH_DEPTH;   // rings loaded ahead of use

@@ -31,7 +31,7 @@ EXPORTS = ("cw_create", "cw_set_material", "cw_set_material_rz", "cw_set_pml", "
            "cw_workspace_bytes", "cw_bind", "cw_step", "cw_sync", "cw_get_traces",
            "cw_get_field", "cw_set_field", "cw_energy", "cw_reset", "cw_steps_done",
            "cw_ricker", "cw_destroy", "cw_last_error", "cw_profile", "cw_profile_read",
-           "cw_set_path", "cw_set_storage", "cw_stream_probe")
+           "cw_set_path", "cw_set_storage", "cw_stream_probe", "cw_set_graph")
 
 STORAGE = {"f32": 0, "f16": 1, "bf16": 2}
 
@@ -92,6 +92,7 @@ def load():
         "cw_set_storage": [P, I32],
         "cw_profile_read": [P, I32, DP, ctypes.POINTER(I64)],
         "cw_stream_probe": [P, ctypes.c_uint64, I32, I32, I32, P, DP],
+        "cw_set_graph": [P, I32],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -271,8 +272,13 @@ class Sim:
         _check(self.lib.cw_set_storage(self.h, STORAGE[storage]))
 
     def set_path(self, path: str):
-        """Kernel path of step(): "auto", "two-pass" or "fused"."""
+        """Kernel path of step(): "auto", "two-pass", "fused" or "march"."""
         _check(self.lib.cw_set_path(self.h, PATHS[path]))
+
+    def set_graph(self, steps: int):
+        """Replay the two-pass step's launches as a HIP graph of `steps`
+        (even) steps; 0 switches graph replay off."""
+        _check(self.lib.cw_set_graph(self.h, int(steps)))
 
     def profile(self, enable: bool = True):
         """Start (or stop and clear) per-launch HIP-event timing of the step kernels."""

@@ -44,7 +44,8 @@ def _times(kind, n, dt):
     return (np.arange(n) + off) * dt
 
 
-def run_gpu(sc: Scenario, keep_sim: bool = False):
+def make_sim(sc: Scenario):
+    """A bound simulation of scenario sc (not yet stepped; sources cover sc.steps)."""
     s = cwell.Sim(*sc.shape, *sc.h)
     s.set_material(*sc.medium)
     if sc.npml != (0, 0):
@@ -62,6 +63,11 @@ def run_gpu(sc: Scenario, keep_sim: bool = False):
     if sc.initial:
         for name, a in sc.initial.items():
             s.set_field(name, a)
+    return s
+
+
+def run_gpu(sc: Scenario, keep_sim: bool = False):
+    s = make_sim(sc)
     s.step(sc.steps)
     s.sync()
     tr = s.traces()

@@ -126,6 +126,16 @@ def test_stream_probe_validation():
     assert b"7 reads" in lib.cw_last_error()
 
 
+def test_graph_steps_validation():
+    s = cwell.Sim(6, 4, 10, 5e-3, 5e-3)
+    for bad in (-2, 3, 4098):
+        with pytest.raises(cwell.CwellError) as e:
+            s.set_graph(bad)
+        assert e.value.status == -2
+    s.set_graph(0)
+    s.set_graph(100)
+
+
 def test_workspace_size_accounts_for_everything():
     shape = (10, 4, 24)
     h = 5e-3

@@ -12,7 +12,7 @@ import pytest
 
 from paper_2302_13907_amd import cwell, inputs
 
-from gpu_common import (FIELDS, STRESS, VEL, Scenario, announce, field_errors, parity_scenario,
+from gpu_common import (FIELDS, STRESS, VEL, Scenario, announce, field_errors, make_sim, parity_scenario,
                         rel_l2, run_gpu, run_oracle)
 
 pytestmark = pytest.mark.gpu
@@ -288,6 +288,39 @@ def test_march_matches_column(shape, storage):
     announce("  traces %.2e, worst field %.2e" % (e, max(fe.values())))
     assert e <= tol, e
     assert max(fe.values()) <= tol, fe
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_graph_replay_matches_ordinary_launches(storage):
+    """Steps replayed from a captured graph give bitwise the results of
+    ordinary launches: several replays with ordinary steps, reads of the
+    state and synchronizations between them, starts on odd steps, a reset
+    (the graph stays valid), and float16 scale tracking through replays."""
+    sc = parity_scenario()
+    sc.steps = 100
+    sc.storage = storage
+    announce("graph replay, parity case, %s storage" % storage)
+    eager, graph = make_sim(sc), make_sim(sc)
+    graph.set_graph(8)
+    chunks = [3, 17, 16, 8, 1, 24, 21]                # 90 steps: replays, odd starts, remainders
+    for rnd in range(2):
+        done = 0
+        for c in chunks if rnd == 0 else [10]:
+            eager.step(c)
+            graph.step(c)
+            done += c
+            eager.sync()
+            graph.sync()
+            assert eager.steps_done == graph.steps_done == done
+            ta, tb = eager.traces(), graph.traces()
+            assert np.array_equal(ta, tb), (rnd, done)
+            for name in FIELDS:
+                assert np.array_equal(eager.field(name), graph.field(name)), (rnd, done, name)
+        assert np.abs(eager.traces()).max() > 0
+        eager.reset()
+        graph.reset()
+    eager.close()
+    graph.close()
 
 
 def test_many_sources_fall_back_to_two_pass():
