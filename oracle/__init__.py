@@ -52,6 +52,10 @@ ORACLE_PINS = {
         "tests/test_oracle_pins.py::test_cfl_margin",
     "Ricker pulse of Sec. 2: zeros, extrema, zero mean, spectral peak":
         "tests/test_oracle_pins.py::test_ricker_properties",
+    "adjoint step (orc_adjoint_step): exact transpose of the step, layer included":
+        "tests/test_oracle_adjoint.py::test_adjoint_step_is_the_transpose",
+    "gradient of the receiver loss in the cement moduli (orc_gradient)":
+        "tests/test_oracle_adjoint.py::test_gradient_matches_finite_differences",
 }
 
 
@@ -104,6 +108,11 @@ def _load():
         lib.orc_get_dt.argtypes = [P]
         lib.orc_apply_div.argtypes = [P, ctypes.POINTER(D), ctypes.POINTER(D)]
         lib.orc_apply_strain.argtypes = [P, ctypes.POINTER(D), ctypes.POINTER(D)]
+        lib.orc_step_linear.argtypes = [P]
+        lib.orc_adjoint_step.argtypes = [P, ctypes.POINTER(D), ctypes.POINTER(D)]
+        lib.orc_get_psi.argtypes = [P, I, D]
+        lib.orc_set_psi.argtypes = [P, I, D]
+        lib.orc_gradient.argtypes = [P, L, L, L, I, I, I, I, I, D, D, D]
         _lib = lib
     return _lib
 
@@ -222,6 +231,55 @@ class OracleSim:
         O = (ctypes.POINTER(ctypes.c_double) * 3)(*[_dp(a) for a in out])
         self.lib.orc_apply_div(self.h, S, O)
         return out
+
+    NPSI = 18
+
+    def psi(self, q: int) -> np.ndarray:
+        """Layer memory variable q (0..17; requires the layer on)."""
+        out = np.empty(self.shape)
+        if self.lib.orc_get_psi(self.h, q, _dp(out)):
+            raise ValueError("no layer memory")
+        return out
+
+    def set_psi(self, q: int, a):
+        a = self._arr(a)
+        if self.lib.orc_set_psi(self.h, q, _dp(a)):
+            raise ValueError("no layer memory")
+
+    def step_linear(self):
+        """One step of the current state without sources."""
+        self.lib.orc_step_linear(self.h)
+
+    def adjoint_step(self, fb: dict, pb=None):
+        """Apply the transposed step in place: fb maps field name -> adjoint
+        array, pb lists the 18 layer-memory adjoints (layer on)."""
+        arrs = [np.ascontiguousarray(fb[n], dtype=np.float64) for n in FIELDS]
+        for n, a in zip(FIELDS, arrs):
+            fb[n] = a
+        F = (ctypes.POINTER(ctypes.c_double) * 9)(*[_dp(a) for a in arrs])
+        if pb is not None:
+            for q in range(self.NPSI):
+                pb[q] = np.ascontiguousarray(pb[q], dtype=np.float64)
+            Pp = (ctypes.POINTER(ctypes.c_double) * self.NPSI)(*[_dp(a) for a in pb])
+        else:
+            dummy = np.zeros(1)
+            Pp = (ctypes.POINTER(ctypes.c_double) * self.NPSI)(*[_dp(dummy)] * self.NPSI)
+        self.lib.orc_adjoint_step(self.h, F, Pp)
+        return fb, pb
+
+    def gradient(self, nsteps: int, window, region):
+        """Loss sum over steps n in window [n0, n1) and pressure receivers of
+        p(t_{n+1})^2, and its gradient with respect to (mu, K) of the bins of
+        region = (i0, i1, k0, nbins, bin_rows); runs the forward from the
+        zero state and the adjoint back.  Returns (loss, dL/dmu, dL/dK)."""
+        i0, i1, k0, nb, br = region
+        gm, gk = np.zeros(nb), np.zeros(nb)
+        loss = ctypes.c_double()
+        rc = self.lib.orc_gradient(self.h, nsteps, window[0], window[1], i0, i1, k0, nb, br,
+                                   ctypes.byref(loss), _dp(gm), _dp(gk))
+        if rc:
+            raise ValueError("gradient rejected (%d)" % rc)
+        return loss.value, gm, gk
 
     def apply_strain(self, vel):
         """Strain rates (e_rr, e_tt, e_zz, g_rt, g_rz, g_tz) of vel = (vr, vt, vz)."""

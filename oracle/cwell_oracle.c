@@ -43,6 +43,14 @@
  *   volume; the wavelet samples are an input array (the Ricker pulse of
  *   Sec. 2 is provided separately by orc_ricker).
  *
+ *   Adjoint: the transpose of the step, obtained by reversing each of its
+ *   statements (every read becomes a scattered add), and from it the
+ *   gradient of a receiver loss with respect to the moduli of a region
+ *   (orc_gradient): forward run storing the region's strains, then the
+ *   adjoint steps back from the last one, each adding the derivative of the
+ *   stress update with respect to lambda and mu (through the harmonic means
+ *   at the shear nodes) times the stress adjoints.
+ *
  * Memory variables are stored on the full grid here (zero outside the layer),
  * which is wasteful but plainly correct.
  *
@@ -708,3 +716,345 @@ int orc_threads(void) { return omp_get_max_threads(); }
 int orc_threads(void) { return 1; }
 #endif
 double orc_get_dt(const orc *s) { return s->dt; }
+
+/* ============================== adjoint ============================= */
+/* Discrete adjoint of the time step (the exact transpose of the linear map
+   (v^{n-1/2}, sigma^n, psi^n) -> (v^{n+1/2}, sigma^{n+1}, psi^{n+1}); the
+   sources do not depend on the state and drop out), written as the
+   reverse of each statement of step_velocity and step_stress: every read
+   X = c * f[q](i, j, k) of the forward code becomes fb[q](i, j, k) += c * Xb,
+   every read outside the grid (a zero ghost) contributes nothing. */
+
+/* transpose of at(): scatter into a(i, j, k), nothing outside the grid */
+static void addv(const orc *s, double *a, int i, int j, int k, double v)
+{
+  if (i < 0 || i >= s->nr || k < 0 || k >= s->nz) return;
+  j = ((j % s->nt) + s->nt) % s->nt;
+  a[IDX(s, i, j, k)] += v;
+}
+
+/* transpose of stretch(): forward psi' = b psi + a X, out = X + psi';
+   given out_b and pb[q][p] = adjoint of psi', returns X_b and leaves the
+   adjoint of psi in pb[q][p]. */
+static double stretch_adj(orc *s, double **pb, int q, size_t p, double a, double b, double outb)
+{
+  if (!s->psi[0]) return outb;
+  double t = pb[q][p] + outb;
+  pb[q][p] = b * t;
+  return outb + a * t;
+}
+
+/* transposes of the strain parts: scatter the adjoints of the parts into the velocity adjoints */
+static void n_parts_adj(const orc *s, double **fb, int i, int j, int k, double err, double ett, double ezz)
+{
+  double *vr = fb[VR], *vt = fb[VT], *vz = fb[VZ];
+  addv(s, vr, i, j, k, err / s->dr);
+  addv(s, vr, i - 1, j, k, -err / s->dr);
+  double c = 1.0 / rc_(s, i);
+  addv(s, vt, i, j, k, c * ett / s->dth);
+  addv(s, vt, i, j - 1, k, -c * ett / s->dth);
+  addv(s, vr, i, j, k, 0.5 * c * ett);
+  addv(s, vr, i - 1, j, k, 0.5 * c * ett);
+  addv(s, vz, i, j, k, ezz / s->dz);
+  addv(s, vz, i, j, k - 1, -ezz / s->dz);
+}
+
+static void rt_parts_adj(const orc *s, double **fb, int i, int j, int k, double Dr, double B)
+{
+  double *vr = fb[VR], *vt = fb[VT];
+  addv(s, vt, i + 1, j, k, Dr / s->dr);
+  addv(s, vt, i, j, k, -Dr / s->dr);
+  double c = 1.0 / rf_(s, i);
+  addv(s, vr, i, j + 1, k, c * B / s->dth);
+  addv(s, vr, i, j, k, -c * B / s->dth);
+  addv(s, vt, i + 1, j, k, -0.5 * c * B);
+  addv(s, vt, i, j, k, -0.5 * c * B);
+}
+
+static void rz_parts_adj(const orc *s, double **fb, int i, int j, int k, double Dr, double Dz)
+{
+  addv(s, fb[VZ], i + 1, j, k, Dr / s->dr);
+  addv(s, fb[VZ], i, j, k, -Dr / s->dr);
+  addv(s, fb[VR], i, j, k + 1, Dz / s->dz);
+  addv(s, fb[VR], i, j, k, -Dz / s->dz);
+}
+
+static void tz_parts_adj(const orc *s, double **fb, int i, int j, int k, double B, double Dz)
+{
+  double c = 1.0 / rc_(s, i);
+  addv(s, fb[VZ], i, j + 1, k, c * B / s->dth);
+  addv(s, fb[VZ], i, j, k, -c * B / s->dth);
+  addv(s, fb[VT], i, j, k + 1, Dz / s->dz);
+  addv(s, fb[VT], i, j, k, -Dz / s->dz);
+}
+
+/* transposes of the velocity parts: scatter into the stress adjoints */
+static void vr_parts_adj(const orc *s, double **fb, int i, int j, int k, double Dr, double B, double Dz)
+{
+  double *srr = fb[SRR], *stt = fb[STT], *srt = fb[SRT], *srz = fb[SRZ];
+  addv(s, srr, i + 1, j, k, Dr / s->dr);
+  addv(s, srr, i, j, k, -Dr / s->dr);
+  double c = 1.0 / rf_(s, i);
+  addv(s, srt, i, j, k, c * B / s->dth);
+  addv(s, srt, i, j - 1, k, -c * B / s->dth);
+  addv(s, srr, i + 1, j, k, 0.5 * c * B);
+  addv(s, srr, i, j, k, 0.5 * c * B);
+  addv(s, stt, i + 1, j, k, -0.5 * c * B);
+  addv(s, stt, i, j, k, -0.5 * c * B);
+  addv(s, srz, i, j, k, Dz / s->dz);
+  addv(s, srz, i, j, k - 1, -Dz / s->dz);
+}
+
+static void vt_parts_adj(const orc *s, double **fb, int i, int j, int k, double Dr, double B, double Dz)
+{
+  double *stt = fb[STT], *srt = fb[SRT], *stz = fb[STZ];
+  addv(s, srt, i, j, k, Dr / s->dr);
+  addv(s, srt, i - 1, j, k, -Dr / s->dr);
+  double c = 1.0 / rc_(s, i);
+  addv(s, stt, i, j + 1, k, c * B / s->dth);
+  addv(s, stt, i, j, k, -c * B / s->dth);
+  addv(s, srt, i, j, k, c * B);
+  addv(s, srt, i - 1, j, k, c * B);
+  addv(s, stz, i, j, k, Dz / s->dz);
+  addv(s, stz, i, j, k - 1, -Dz / s->dz);
+}
+
+static void vz_parts_adj(const orc *s, double **fb, int i, int j, int k, double Dr, double B, double Dz)
+{
+  double *szz = fb[SZZ], *srz = fb[SRZ], *stz = fb[STZ];
+  addv(s, srz, i, j, k, Dr / s->dr);
+  addv(s, srz, i - 1, j, k, -Dr / s->dr);
+  double c = 1.0 / rc_(s, i);
+  addv(s, stz, i, j, k, c * B / s->dth);
+  addv(s, stz, i, j - 1, k, -c * B / s->dth);
+  addv(s, srz, i, j, k, 0.5 * c * B);
+  addv(s, srz, i - 1, j, k, 0.5 * c * B);
+  addv(s, szz, i, j, k + 1, Dz / s->dz);
+  addv(s, szz, i, j, k, -Dz / s->dz);
+}
+
+/* Reverse of step_stress.  On entry fb[S*] hold the adjoints of sigma^{n+1},
+   fb[V*] of v^{n+1/2}, pb of psi^{n+1} (stress terms); on return fb[V*]
+   hold the adjoints of v^{n+1/2} as an input of the stress update added
+   in, pb the adjoints of psi^n.  The stress adjoints are unchanged: sigma^n
+   enters sigma^{n+1} with coefficient 1. */
+static void adj_stress(orc *s, double **fb, double **pb)
+{
+  const double dt = s->dt;
+  for (int i = 0; i < s->nr; i++)
+    for (int j = 0; j < s->nt; j++)
+      for (int k = 0; k < s->nz; k++) {
+        size_t p = IDX(s, i, j, k);
+        double g_rr = fb[SRR][p], g_tt = fb[STT][p], g_zz = fb[SZZ][p];
+        double lam = s->lam[p], mu = s->mu[p];
+        double gs = g_rr + g_tt + g_zz;
+        double err = dt * (lam * gs + 2.0 * mu * g_rr);
+        double ett = dt * (lam * gs + 2.0 * mu * g_tt);
+        double ezz = dt * (lam * gs + 2.0 * mu * g_zz);
+        err = stretch_adj(s, pb, P_N_DR, p, s->ar_c[i], s->br_c[i], err);
+        ett = stretch_adj(s, pb, P_N_B, p, s->at_c[i], s->bt_c[i], ett);
+        ezz = stretch_adj(s, pb, P_N_DZ, p, s->az_c[k], s->bz_c[k], ezz);
+        n_parts_adj(s, fb, i, j, k, err, ett, ezz);
+        double g = dt * s->mu_rt[p] * fb[SRT][p];
+        double Dr = stretch_adj(s, pb, P_RT_DR, p, s->ar_f[i], s->br_f[i], g);
+        double B = stretch_adj(s, pb, P_RT_B, p, s->at_f[i], s->bt_f[i], g);
+        rt_parts_adj(s, fb, i, j, k, Dr, B);
+        g = dt * s->mu_rz[p] * fb[SRZ][p];
+        Dr = stretch_adj(s, pb, P_RZ_DR, p, s->ar_f[i], s->br_f[i], g);
+        double Dz = stretch_adj(s, pb, P_RZ_DZ, p, s->az_h[k], s->bz_h[k], g);
+        rz_parts_adj(s, fb, i, j, k, Dr, Dz);
+        g = dt * s->mu_tz[p] * fb[STZ][p];
+        B = stretch_adj(s, pb, P_TZ_B, p, s->at_c[i], s->bt_c[i], g);
+        Dz = stretch_adj(s, pb, P_TZ_DZ, p, s->az_h[k], s->bz_h[k], g);
+        tz_parts_adj(s, fb, i, j, k, B, Dz);
+      }
+}
+
+/* Reverse of step_velocity: fb[V*] hold the adjoints of v^{n+1/2}; the
+   stress adjoints receive the transposed divergence, pb the adjoints of
+   the velocity terms' psi^n; fb[V*] are unchanged (v^{n-1/2} enters with
+   coefficient 1). */
+static void adj_velocity(orc *s, double **fb, double **pb)
+{
+  const double dt = s->dt;
+  for (int i = 0; i < s->nr; i++)
+    for (int j = 0; j < s->nt; j++)
+      for (int k = 0; k < s->nz; k++) {
+        size_t p = IDX(s, i, j, k);
+        double g = dt * s->b_r[p] * fb[VR][p];
+        double Dr = stretch_adj(s, pb, P_VR_DR, p, s->ar_f[i], s->br_f[i], g);
+        double B = stretch_adj(s, pb, P_VR_B, p, s->at_f[i], s->bt_f[i], g);
+        double Dz = stretch_adj(s, pb, P_VR_DZ, p, s->az_c[k], s->bz_c[k], g);
+        vr_parts_adj(s, fb, i, j, k, Dr, B, Dz);
+        g = dt * s->b_t[p] * fb[VT][p];
+        Dr = stretch_adj(s, pb, P_VT_DR, p, s->ar_c[i], s->br_c[i], g);
+        B = stretch_adj(s, pb, P_VT_B, p, s->at_c[i], s->bt_c[i], g);
+        Dz = stretch_adj(s, pb, P_VT_DZ, p, s->az_c[k], s->bz_c[k], g);
+        vt_parts_adj(s, fb, i, j, k, Dr, B, Dz);
+        g = dt * s->b_z[p] * fb[VZ][p];
+        Dr = stretch_adj(s, pb, P_VZ_DR, p, s->ar_c[i], s->br_c[i], g);
+        B = stretch_adj(s, pb, P_VZ_B, p, s->at_c[i], s->bt_c[i], g);
+        Dz = stretch_adj(s, pb, P_VZ_DZ, p, s->az_h[k], s->bz_h[k], g);
+        vz_parts_adj(s, fb, i, j, k, Dr, B, Dz);
+      }
+}
+
+/* One source-free step of the current state (for the adjoint checks). */
+void orc_step_linear(orc *s)
+{
+  step_velocity(s);
+  step_stress(s);
+}
+
+/* One adjoint step in place: fb[NFIELD] (n arrays each) and pb[NPSI] (n
+   arrays each, ignored with the layer off) hold the adjoint of the state
+   after a step and receive the adjoint of the state before it. */
+void orc_adjoint_step(orc *s, double *const fb_in[NFIELD], double *const pb_in[NPSI])
+{
+  double *fb[NFIELD], *pb[NPSI];
+  for (int q = 0; q < NFIELD; q++) fb[q] = fb_in[q];
+  for (int q = 0; q < NPSI; q++) pb[q] = s->psi[0] ? pb_in[q] : NULL;
+  adj_stress(s, fb, pb);
+  adj_velocity(s, fb, pb);
+}
+
+int orc_get_psi(const orc *s, int q, double *out)
+{
+  if (q < 0 || q >= NPSI || !s->psi[0]) return -1;
+  memcpy(out, s->psi[q], s->n * sizeof(double));
+  return 0;
+}
+
+int orc_set_psi(orc *s, int q, const double *in)
+{
+  if (q < 0 || q >= NPSI || !s->psi[0]) return -1;
+  memcpy(s->psi[q], in, s->n * sizeof(double));
+  return 0;
+}
+
+/* d HM4 / d a at (a, b, c, d); the one-sided limit 4 when a alone is zero */
+static double dhm4(double a, double b, double c, double d)
+{
+  if (b == 0.0 || c == 0.0 || d == 0.0) return 0.0;
+  if (a == 0.0) return 4.0;
+  double h = hm4(a, b, c, d);
+  return h * h / (4.0 * a * a);
+}
+
+/* Gradient of L = sum over steps n in [n0, n1) and pressure receivers m of
+   p_m(t_{n+1})^2 with respect to the moduli of the parameter region:
+   rings [i0, i1), every theta, depth rows [k0, k0 + nbins*bin_rows) in bins
+   of bin_rows rows.  Bin b's parameters shift mu and the bulk modulus
+   K = lambda + 2 mu / 3 of all its cells together, so
+     dL/dmu_b = sum over its cells of (dL/dmu|lambda - (2/3) dL/dlambda),
+     dL/dK_b  = sum over its cells of dL/dlambda.
+   Runs the forward steps 0..nsteps-1 from the zero state (with the
+   sources), storing the strains of the region's nodes, then the adjoint
+   steps back from the last one.  The region must lie outside the absorbing
+   layer (its strains are then the plain ones).  Returns 0, or <0 for a bad
+   argument / state. */
+int orc_gradient(orc *s, long nsteps, long n0, long n1, int i0, int i1, int k0, int nbins, int bin_rows,
+                 double *loss, double *g_mu, double *g_K)
+{
+  if (!(s->dt > 0) || s->nstep != 0) return -5;
+  int k1 = k0 + nbins * bin_rows;
+  if (i0 < 0 || i1 > s->nr || i0 >= i1 || k0 < 0 || k1 > s->nz || nbins < 1 || bin_rows < 1) return -2;
+  if (s->psi[0] && (i1 > s->nr - s->npr || k0 < s->npz + 1 || k1 > s->nz - 1 - s->npz - 1)) return -2;
+  /* nodes whose strains the gradient needs: rings i0-1..i1-1, depths k0-1..k1-1 */
+  int ea = i0 > 0 ? i0 - 1 : 0, eb = i1, za = k0 > 0 ? k0 - 1 : 0, zb = k1;
+  size_t nreg = (size_t)(eb - ea) * s->nt * (zb - za);
+  double *Z = (double *)malloc((size_t)nsteps * nreg * 6 * sizeof(double));
+  double *tr = (double *)malloc((size_t)(s->nrec > 0 ? s->nrec : 1) * nsteps * sizeof(double));
+  if (!Z || !tr) { free(Z); free(tr); return -8; }
+#define ZI(t, i, j, k) ((((size_t)(t) * (eb - ea) + ((i) - ea)) * s->nt + (j)) * (zb - za) + ((k) - za))
+  /* forward */
+  for (long t = 0; t < nsteps; t++) {
+    step_velocity(s);
+    apply_sources(s, t, 0);
+    for (int i = ea; i < eb; i++)
+      for (int j = 0; j < s->nt; j++)
+        for (int k = za; k < zb; k++) {
+          double *z = Z + ZI(t, i, j, k) * 6;
+          double a, b;
+          n_parts(s, i, j, k, &z[0], &z[1], &z[2]);
+          rt_parts(s, i, j, k, &a, &b); z[3] = a + b;
+          rz_parts(s, i, j, k, &a, &b); z[4] = a + b;
+          tz_parts(s, i, j, k, &a, &b); z[5] = a + b;
+        }
+    step_stress(s);
+    apply_sources(s, t, 1);
+    for (int m = 0; m < s->nrec; m++) tr[(size_t)m * nsteps + t] = sample(s, &s->rec[m]);
+    s->nstep++;
+  }
+  double L = 0.0;
+  for (int m = 0; m < s->nrec; m++)
+    if (s->rec[m].kind == REC_PRESSURE)
+      for (long t = n0; t < n1 && t < nsteps; t++) L += tr[(size_t)m * nsteps + t] * tr[(size_t)m * nsteps + t];
+  *loss = L;
+  /* adjoint */
+  double *fb[NFIELD], *pb[NPSI] = {0};
+  for (int q = 0; q < NFIELD; q++) fb[q] = (double *)calloc(s->n, sizeof(double));
+  if (s->psi[0])
+    for (int q = 0; q < NPSI; q++) pb[q] = (double *)calloc(s->n, sizeof(double));
+  double *glam = (double *)calloc(s->n, sizeof(double)), *gmu = (double *)calloc(s->n, sizeof(double));
+  const double dt = s->dt;
+  for (long t = nsteps - 1; t >= 0; t--) {
+    /* receivers: dL/dsigma^{t+1} */
+    if (t >= n0 && t < n1)
+      for (int m = 0; m < s->nrec; m++) {
+        const orc_rec *q = &s->rec[m];
+        if (q->kind != REC_PRESSURE) continue;
+        int j0 = q->j < 0 ? 0 : q->j, j1 = q->j < 0 ? s->nt : q->j + 1;
+        double g = 2.0 * tr[(size_t)m * nsteps + t] * (-1.0 / (3.0 * (j1 - j0)));
+        for (int j = j0; j < j1; j++) {
+          size_t p = IDX(s, q->i, j, q->k);
+          fb[SRR][p] += g; fb[STT][p] += g; fb[SZZ][p] += g;
+        }
+      }
+    /* moduli: sigma^{t+1} = sigma^t + dt C(lambda, mu) Z^{t+1/2} */
+    for (int i = ea; i < eb; i++)
+      for (int j = 0; j < s->nt; j++)
+        for (int k = za; k < zb; k++) {
+          size_t p = IDX(s, i, j, k);
+          const double *z = Z + ZI(t, i, j, k) * 6;
+          if (i >= i0 && k >= k0) {
+            double gs = fb[SRR][p] + fb[STT][p] + fb[SZZ][p];
+            glam[p] += dt * (z[0] + z[1] + z[2]) * gs;
+            gmu[p] += 2.0 * dt * (z[0] * fb[SRR][p] + z[1] * fb[STT][p] + z[2] * fb[SZZ][p]);
+          }
+          /* shear nodes of this index: their effective modulus is HM4 of four cells */
+          int i1c = i + 1 < s->nr ? i + 1 : s->nr - 1, j1c = (j + 1) % s->nt;
+          int k1c = k + 1 < s->nz ? k + 1 : s->nz - 1;
+          const double *mu = s->mu;
+          double grt = dt * z[3] * fb[SRT][p], grz = dt * z[4] * fb[SRZ][p], gtz = dt * z[5] * fb[STZ][p];
+          size_t c00 = p, ci = IDX(s, i1c, j, k), cj = IDX(s, i, j1c, k), cij = IDX(s, i1c, j1c, k);
+          size_t ck = IDX(s, i, j, k1c), cik = IDX(s, i1c, j, k1c), cjk = IDX(s, i, j1c, k1c);
+          /* rt: (i, j), (i+1, j), (i, j+1), (i+1, j+1) */
+          size_t rt[4] = {c00, ci, cj, cij};
+          size_t rz[4] = {c00, ci, ck, cik};
+          size_t tz[4] = {c00, cj, ck, cjk};
+          for (int w = 0; w < 4; w++) {
+            int o1 = (w + 1) % 4, o2 = (w + 2) % 4, o3 = (w + 3) % 4;
+            gmu[rt[w]] += grt * dhm4(mu[rt[w]], mu[rt[o1]], mu[rt[o2]], mu[rt[o3]]);
+            gmu[rz[w]] += grz * dhm4(mu[rz[w]], mu[rz[o1]], mu[rz[o2]], mu[rz[o3]]);
+            gmu[tz[w]] += gtz * dhm4(mu[tz[w]], mu[tz[o1]], mu[tz[o2]], mu[tz[o3]]);
+          }
+        }
+    adj_stress(s, fb, pb);
+    adj_velocity(s, fb, pb);
+  }
+  for (int b = 0; b < nbins; b++) { g_mu[b] = 0.0; g_K[b] = 0.0; }
+  for (int i = i0; i < i1; i++)
+    for (int j = 0; j < s->nt; j++)
+      for (int k = k0; k < k1; k++) {
+        size_t p = IDX(s, i, j, k);
+        int b = (k - k0) / bin_rows;
+        g_mu[b] += gmu[p] - (2.0 / 3.0) * glam[p];
+        g_K[b] += glam[p];
+      }
+#undef ZI
+  for (int q = 0; q < NFIELD; q++) free(fb[q]);
+  for (int q = 0; q < NPSI; q++) free(pb[q]);
+  free(glam); free(gmu); free(Z); free(tr);
+  return 0;
+}

@@ -1,0 +1,112 @@
+"""Pins of the oracle's adjoint (test infrastructure for the gradient path).
+
+1. Dot-product test: for random states U, W (fields and absorbing-layer
+   memory) and a random heterogeneous medium with a fluid core, the
+   transposed step satisfies <step(U), W> = <U, step^T(W)> to rounding.
+   This pins every transposed stencil index, coefficient, zero ghost and
+   layer-memory recursion against the forward step.
+2. Gradient: the adjoint gradient of the receiver loss with respect to the
+   cement moduli of z-bins agrees with central finite differences of the
+   FP64 forward run (relative step 1e-4), bin by bin."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2302_13907_amd import inputs
+
+
+@pytest.mark.parametrize("layer", [False, True])
+def test_adjoint_step_is_the_transpose(layer):
+    shape = (9, 5, 11)
+    o = oracle.OracleSim(*shape, 5e-3, 5e-3)
+    o.set_material(*inputs.random_medium(*shape, seed=4))
+    if layer:
+        o.set_pml(3, 2, 1e-3, 3e4)
+    o.set_dt(0.5 * o.cfl_dt())
+    rng = np.random.default_rng(0)
+    U = {n: rng.standard_normal(shape) for n in oracle.FIELDS}
+    P = [rng.standard_normal(shape) for _ in range(18)] if layer else []
+    for n, a in U.items():
+        o.set_field(n, a)
+    for q, a in enumerate(P):
+        o.set_psi(q, a)
+    o.step_linear()
+    FU = {n: o.field(n) for n in oracle.FIELDS}
+    FP = [o.psi(q) for q in range(len(P))]
+    W = {n: rng.standard_normal(shape) for n in oracle.FIELDS}
+    WP = [rng.standard_normal(shape) for _ in range(len(P))]
+    lhs = sum((FU[n] * W[n]).sum() for n in oracle.FIELDS) + sum((a * b).sum() for a, b in zip(FP, WP))
+    fb, pb = o.adjoint_step({n: W[n].copy() for n in W}, [a.copy() for a in WP] if layer else None)
+    rhs = sum((U[n] * fb[n]).sum() for n in oracle.FIELDS)
+    if layer:
+        rhs += sum((a * b).sum() for a, b in zip(P, pb))
+    assert abs(lhs - rhs) <= 1e-13 * abs(lhs), (lhs, rhs)
+
+
+# a thin well (hole 20 mm, casing to 30 mm, cement annulus to 50 mm) so that
+# the wave reaches the cement within a short run
+H = 5e-3
+SHAPE = (20, 8, 96)
+RADII = (0.02, 0.03, 0.05)
+KTOP = 48
+STEPS = 400
+WINDOW = (150, 400)
+REGION = (6, 10, KTOP + 1, 8, 2)      # annulus rings 6..9, 8 bins of 2 rows below the cement top
+
+
+def _medium(dmu=None, dK=None):
+    rho, lam, mu = inputs.cased_well(*SHAPE, H, H, z_top=KTOP * H, ramp=0.1, radii=RADII)
+    if dmu is not None:
+        i0, i1, k0, nb, br = REGION
+        K = lam + 2.0 * mu / 3.0
+        for b in range(nb):
+            sl = (slice(i0, i1), slice(None), slice(k0 + b * br, k0 + (b + 1) * br))
+            mu[sl] += dmu[b]
+            K[sl] += dK[b]
+        lam = K - 2.0 * mu / 3.0
+    return rho, lam, mu
+
+
+def _sim(med, dt=None):
+    o = oracle.OracleSim(*SHAPE, H, H)
+    o.set_material(*med)
+    o.set_pml(6, 6, 1e-3, math.pi * 40e3)
+    dt = dt or 0.5 * o.cfl_dt()
+    o.set_dt(dt)
+    o.add_source("volume", 0, -1, 40, oracle.ricker(40e3, (np.arange(STEPS) + 0.5) * dt))
+    for k in range(20, 44, 2):
+        o.add_receiver("pressure", 0, -1, k)
+    return o, dt
+
+
+def adjoint_reference():
+    """Loss and FP64 adjoint gradient of the thin-well case (also the
+    reference of the GPU gradient)."""
+    o, dt = _sim(_medium())
+    return o.gradient(STEPS, WINDOW, REGION), dt
+
+
+def test_gradient_matches_finite_differences():
+    (L, gm, gk), dt = adjoint_reference()
+    assert L > 0
+
+    def loss(dmu, dK):
+        o, _ = _sim(_medium(dmu, dK), dt)
+        tr = o.run(STEPS)
+        return float((tr[:, WINDOW[0]:WINDOW[1]] ** 2).sum())
+
+    nb = REGION[3]
+    assert math.isclose(loss(np.zeros(nb), np.zeros(nb)), L, rel_tol=1e-12)
+    _, lam_c, mu_c = inputs.moduli(*inputs.CEMENT)
+    K_c = lam_c + 2.0 * mu_c / 3.0
+    z = np.zeros(nb)
+    for b in (0, 3):
+        e = np.zeros(nb)
+        e[b] = 1e-4 * mu_c
+        fd = (loss(e, z) - loss(-e, z)) / (2 * e[b])
+        assert abs(gm[b] - fd) <= 1e-5 * abs(fd), (b, "mu", gm[b], fd)
+        e[b] = 1e-4 * K_c
+        fd = (loss(z, e) - loss(z, -e)) / (2 * e[b])
+        assert abs(gk[b] - fd) <= 1e-5 * abs(fd), (b, "K", gk[b], fd)
