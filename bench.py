@@ -92,7 +92,7 @@ PROFILE_VARIANTS = {
     "march_f32": "--path march --storage f32",
 }
 PROFILE_RUN = ("python3 -u bench.py --steps 20 --warmup 5 --no-cpu-baseline --no-storage-forms --no-stream-ceiling "
-               "--no-graph-replay --copy-gib 1")
+               "--no-graph-replay --no-adjoint --copy-gib 1")
 PROFILE_PASSES = (
     ("stats", "--kernel-trace --stats"),
     ("fetch", "--pmc FETCH_SIZE"),
@@ -348,6 +348,49 @@ def graph_replay(path: str, graph: int = 20, steps: int = 300):
     return res
 
 
+def adjoint_gradient():
+    """Seconds per adjoint gradient on the adjoint workload (forward with
+    checkpoints, segment recomputation, adjoint steps), next to one plain
+    forward run of the same steps."""
+    import numpy as np
+    import torch
+    from paper_2302_13907_amd import cwell, inputs
+    w = inputs.adjoint_case()
+    x = w.extra
+    log("adjoint gradient on %s" % w.name)
+    s = cwell.Sim(w.nr, w.nt, w.nz, w.dr, w.dz)
+    s.set_material(*w.medium_rz())
+    s.set_pml(w.npml, w.npml, w.pml_rc, math.pi * w.f0)
+    dt = w.cfl_fraction * s.cfl_dt()
+    s.set_dt(dt)
+    s.add_source("volume", 0, -1, w.src_k, cwell.ricker(w.f0, (np.arange(w.steps) + 0.5) * dt))
+    for k in w.rec_k:
+        s.add_receiver("pressure", 0, -1, k)
+    s.set_adjoint(w.steps, x["checkpoint_every"], x["region"])
+    s.bind("cuda:0")
+    s.step(10)                                    # warm-up of the forward kernels
+    s.sync()
+    s.reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(w.steps)
+    s.sync()
+    fwd = time.perf_counter() - t0
+    s.reset()
+    t0 = time.perf_counter()
+    loss, gm, gk = s.gradient(x["window"])
+    grad = time.perf_counter() - t0
+    ws = s.workspace_bytes()
+    s.close()
+    del s
+    torch.cuda.empty_cache()
+    if not (np.all(np.isfinite(gm)) and np.all(np.isfinite(gk))):
+        raise RuntimeError("non-finite gradient")
+    return {"workload": w.name, "parameters": 2 * x["region"][3], "checkpoint_every": x["checkpoint_every"],
+            "s_per_gradient": round(grad, 3), "forward_s": round(fwd, 3), "ratio_to_forward": round(grad / fwd, 2),
+            "workspace_GB": round(ws / 1e9, 2), "loss": loss}
+
+
 def storage_forms(path: str, warmup: int = 10, steps: int = 100):
     """Gcell-updates/s of the mixed-precision workload with float32, float16
     and bfloat16 field storage (float32 arithmetic in every case)."""
@@ -382,6 +425,8 @@ def main():
     ap.add_argument("--no-storage-forms", action="store_true",
                     help="skip the float32 / float16 / bfloat16 storage comparison on the "
                          "192 x 96 x 4096 mixed-precision workload")
+    ap.add_argument("--no-adjoint", action="store_true",
+                    help="skip the seconds-per-adjoint-gradient measurement")
     ap.add_argument("--no-graph-replay", action="store_true",
                     help="skip the ordinary-launch / graph-replay comparison on the parity-size workload")
     ap.add_argument("--no-stream-ceiling", action="store_true",
@@ -476,6 +521,8 @@ def main():
         out["storage_forms"] = storage_forms(args.path)
     if not args.no_graph_replay:
         out["graph_replay"] = graph_replay(args.path)
+    if not args.no_adjoint:
+        out["adjoint"] = adjoint_gradient()
     if not args.no_cpu_baseline:
         log("CPU baseline: FP64 oracle for about %.0f s" % args.cpu_seconds)
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)

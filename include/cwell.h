@@ -235,6 +235,41 @@ cw_status cw_profile_read(cw_sim *s, int32_t kernel, double *total_ms, int64_t *
    out[m] = f(t[m]). */
 cw_status cw_ricker(double f0, const double *t, int64_t n, double *out);
 
+/* Adjoint gradient.  The loss is the sum, over steps n in [n0, n1) and
+   pressure receivers m, of p_m(t_{n+1})^2.  Its parameters are the moduli
+   of a region: rings [i0, i1), every theta, depth rows [k0, k0 + nbins *
+   bin_rows) in bins of bin_rows rows; bin b's parameters shift the shear
+   modulus mu and the bulk modulus K = lambda + 2 mu / 3 of all its cells.
+   cw_gradient runs nsteps forward steps from rest (sources included),
+   keeping a checkpoint of the whole state every checkpoint_every steps,
+   then the discrete adjoint of the step backwards: segment by segment it
+   recomputes the forward steps from the segment's checkpoint (storing the
+   region's strain rates) and then takes their adjoint steps, adding each
+   step's contribution to the gradient (Eq. (1): the stress update is linear
+   in lambda, mu and, through the harmonic means of the shear nodes, in the
+   cells' mu).  Outputs: *loss, grad_mu[nbins] = dL/dmu_b (K fixed),
+   grad_K[nbins] = dL/dK_b (mu fixed), all float64; the state afterwards is
+   unspecified (call cw_reset before stepping again).  Float32 storage and
+   the two-pass kernels only.
+
+   cw_set_adjoint: before cw_bind, after cw_set_pml (its buffers -- the
+   adjoint state, nsteps / checkpoint_every checkpoints, one segment of
+   strain rates -- become part of the workspace; the trace capacity is
+   raised to nsteps).  The region must lie clear of the absorbing layer and
+   the grid's edges: 1 <= i0 < i1 <= nr - max(npml_r, 2), max(npml_z + 1, 1)
+   <= k0, k0 + nbins * bin_rows <= nz - 1 - max(npml_z, 1); CW_ERR_RANGE
+   otherwise.  nsteps = 0 switches the adjoint off. */
+cw_status cw_set_adjoint(cw_sim *s, int64_t nsteps, int32_t checkpoint_every, int32_t i0, int32_t i1, int32_t k0,
+                         int32_t nbins, int32_t bin_rows);
+/* Sets the region's moduli to those given by cw_set_material plus the
+   per-bin shifts dmu[nbins], dK[nbins] (Pa), on the host copy and, once
+   bound, on the device.  CW_ERR_MATERIAL if a shifted cell would have
+   mu < 0 or lambda + 2 mu <= 0, CW_ERR_UNSTABLE if dt would exceed the
+   Courant limit of a shifted cell; nothing changes then.  The absorbing
+   layer's profile keeps the largest P speed of the original medium. */
+cw_status cw_set_region_moduli(cw_sim *s, const double *dmu, const double *dK);
+cw_status cw_gradient(cw_sim *s, int64_t n0, int64_t n1, double *loss, double *grad_mu, double *grad_K);
+
 /* Bandwidth reference (measurement only, not part of the scheme): stream
    nread + nwrite arrays of bytes_per_array bytes each, laid out back to
    back in the caller's device buffer `dev` (16-byte aligned, at least

@@ -101,6 +101,20 @@ struct cw_sim {
   double *d_traces = nullptr;
   double *d_energy = nullptr;   // kEnergyBlocks partials + 1 result
   int64_t *d_step = nullptr;    // steps done, as the injection and receiver kernels read it
+  // adjoint gradient (cw_set_adjoint): configuration and buffers in the workspace
+  bool adj = false;
+  int64_t adj_steps = 0;
+  int adj_every = 0;
+  int adj_i0 = 0, adj_i1 = 0, adj_k0 = 0, adj_nb = 0, adj_br = 0;
+  float *adj_fb[NF] = {};
+  float *adj_pr[NPSI_R] = {};
+  float *adj_pz[NPSI_Z] = {};
+  float *adj_T[9] = {};
+  float *adj_ckpt = nullptr;    // checkpoints [ncp][9 n + 12 slab_r + 6 slab_z]
+  float *adj_Z = nullptr;       // strain rates of one segment [every][6][region nodes]
+  double *adj_glam = nullptr, *adj_gmu = nullptr;   // per region cell
+  float *adj_w = nullptr;       // receiver adjoint weights [steps][receivers]
+  std::vector<double> adj_mu0, adj_K0;   // the region's moduli as set by cw_set_material
   // graph replay of the two-pass step (cw_set_graph)
   int graph_steps = 0;
   hipGraph_t graph = nullptr;
@@ -155,8 +169,43 @@ int inject_count(const cw_sim *s)
 }
 
 struct Layout {
-  size_t fields, material, metric, tabr, tabz, psir, psiz, inject, amp, rec, traces, energy, scales, step, total;
+  size_t fields, material, metric, tabr, tabz, psir, psiz, inject, amp, rec, traces, energy, scales, step, adj,
+      total;
 };
+
+// the adjoint's region and its sizes
+AdjRegion adj_region(const cw_sim *s)
+{
+  AdjRegion g{};
+  g.i0 = s->adj_i0; g.i1 = s->adj_i1; g.k0 = s->adj_k0; g.k1 = s->adj_k0 + s->adj_nb * s->adj_br;
+  g.ea = g.i0 - 1; g.eb = g.i1; g.za = g.k0 - 1; g.zb = g.k1;
+  return g;
+}
+size_t adj_region_nodes(const cw_sim *s)
+{
+  const AdjRegion g = adj_region(s);
+  return (size_t)(g.eb - g.ea) * s->nt * (g.zb - g.za);
+}
+size_t adj_region_cells(const cw_sim *s)
+{
+  const AdjRegion g = adj_region(s);
+  return (size_t)(g.i1 - g.i0) * s->nt * (g.k1 - g.k0);
+}
+size_t adj_state_floats(const cw_sim *s)
+{
+  return NF * s->n + (size_t)NPSI_R * s->npr * s->nt * s->nz + (size_t)NPSI_Z * s->nr * s->nt * nzs_of(s);
+}
+size_t adj_bytes(const cw_sim *s)
+{
+  if (!s->adj) return 0;
+  const size_t ncp = (size_t)((s->adj_steps + s->adj_every - 1) / s->adj_every);
+  size_t f = adj_state_floats(s)               // adjoint fields and layer memory
+             + 9 * s->n                        // term adjoints
+             + ncp * adj_state_floats(s)       // checkpoints
+             + (size_t)s->adj_every * 6 * adj_region_nodes(s)
+             + (size_t)s->adj_steps * s->receivers.size();
+  return f * sizeof(float) + 2 * adj_region_cells(s) * sizeof(double) + 1024;
+}
 
 Layout layout(const cw_sim *s)
 {
@@ -177,6 +226,7 @@ Layout layout(const cw_sim *s)
   L.energy = take((kEnergyBlocks + 1) * sizeof(double));
   L.scales = take(3 * NF * sizeof(float) + NF * kMaxSlots * sizeof(unsigned));
   L.step = take(sizeof(int64_t));
+  L.adj = take(adj_bytes(s));
   L.total = off;
   return L;
 }
@@ -560,6 +610,21 @@ cw_status cw_bind(cw_sim *s, void *workspace, uint64_t bytes, void *stream)
   s->d_traces = (double *)(w + L.traces);
   s->d_energy = (double *)(w + L.energy);
   s->d_step = (int64_t *)(w + L.step);
+  if (s->adj) {
+    float *p = (float *)(w + L.adj);
+    for (int q = 0; q < NF; q++) { s->adj_fb[q] = p; p += s->n; }
+    for (int q = 0; q < NPSI_R; q++) { s->adj_pr[q] = slab_r ? p : nullptr; p += slab_r; }
+    for (int q = 0; q < NPSI_Z; q++) { s->adj_pz[q] = slab_z ? p : nullptr; p += slab_z; }
+    for (int q = 0; q < 9; q++) { s->adj_T[q] = p; p += s->n; }
+    const size_t ncp = (size_t)((s->adj_steps + s->adj_every - 1) / s->adj_every);
+    s->adj_ckpt = p; p += ncp * adj_state_floats(s);
+    s->adj_Z = p; p += (size_t)s->adj_every * 6 * adj_region_nodes(s);
+    s->adj_w = p; p += (size_t)s->adj_steps * s->receivers.size();
+    char *c = (char *)p;
+    c += (256 - ((uintptr_t)c & 255)) & 255;
+    s->adj_glam = (double *)c;
+    s->adj_gmu = s->adj_glam + adj_region_cells(s);
+  }
 
   // injections: dt * w[n] / V per target node, V the node (or ring) volume
   std::vector<float> amps(amp_floats(s));
@@ -1000,6 +1065,204 @@ cw_status cw_stream_probe(void *dev, uint64_t bytes_per_array, int32_t nread, in
   (void)hipEventDestroy(e1);
   if (res == CW_OK) *ms_per_pass = (double)ms / reps;
   return res;
+}
+
+static cw_status check_adjoint_region(const cw_sim *s)
+{
+  const int k1 = s->adj_k0 + s->adj_nb * s->adj_br;
+  const int rmax = s->nr - std::max(s->npr, 2), zmax = s->nz - 1 - std::max(s->npz, 1);
+  if (s->adj_i0 < 1 || s->adj_i1 <= s->adj_i0 || s->adj_i1 > rmax || s->adj_k0 < std::max(s->npz + 1, 1) ||
+      k1 > zmax)
+    return fail(CW_ERR_RANGE, "the parameter region (rings [%d, %d), depths [%d, %d)) must lie inside rings "
+                "[1, %d) and depths [%d, %d), clear of the absorbing layer and the grid's edges",
+                s->adj_i0, s->adj_i1, s->adj_k0, k1, rmax, std::max(s->npz + 1, 1), zmax);
+  return CW_OK;
+}
+
+cw_status cw_set_adjoint(cw_sim *s, int64_t nsteps, int32_t checkpoint_every, int32_t i0, int32_t i1, int32_t k0,
+                         int32_t nbins, int32_t bin_rows)
+{
+  cw_status st;
+  if (!configurable(s, &st)) return st;
+  if (nsteps < 0 || checkpoint_every < 1 || nbins < 1 || bin_rows < 1)
+    return fail(CW_ERR_RANGE, "need nsteps >= 0, checkpoint_every >= 1, nbins >= 1, bin_rows >= 1");
+  if (nsteps == 0) {
+    s->adj = false;
+    return CW_OK;
+  }
+  cw_sim t = {};
+  t.nr = s->nr; t.nz = s->nz; t.npr = s->npr; t.npz = s->npz;
+  t.adj_i0 = i0; t.adj_i1 = i1; t.adj_k0 = k0; t.adj_nb = nbins; t.adj_br = bin_rows;
+  if ((st = check_adjoint_region(&t)) != CW_OK) return st;
+  s->adj = true;
+  s->adj_steps = nsteps;
+  s->adj_every = checkpoint_every;
+  s->adj_i0 = i0; s->adj_i1 = i1; s->adj_k0 = k0; s->adj_nb = nbins; s->adj_br = bin_rows;
+  if (s->trace_cap < nsteps) s->trace_cap = nsteps;
+  s->adj_mu0.clear();
+  s->adj_K0.clear();
+  return CW_OK;
+}
+
+// cells of the region as stored in the medium arrays (every theta row of a
+// 3-D medium, one of an axisymmetric one), in the order the shifts walk them
+extern "C++" template <class F>
+static void for_region_medium(const cw_sim *s, F &&f)
+{
+  const int rows = s->med_rz ? 1 : s->nt;
+  const int k1 = s->adj_k0 + s->adj_nb * s->adj_br;
+  for (int i = s->adj_i0; i < s->adj_i1; i++)
+    for (int j = 0; j < rows; j++)
+      for (int k = s->adj_k0; k < k1; k++) f(i, j, k, (k - s->adj_k0) / s->adj_br, mat_index(s, i, j, k));
+}
+
+cw_status cw_set_region_moduli(cw_sim *s, const double *dmu, const double *dK)
+{
+  if (!s || !dmu || !dK) return fail(CW_ERR_ARG, "null argument");
+  if (!s->adj) return fail(CW_ERR_STATE, "no parameter region: cw_set_adjoint first");
+  if (!s->have_material) return fail(CW_ERR_STATE, "medium not set");
+  if (s->adj_mu0.empty())
+    for_region_medium(s, [&](int, int, int, int, size_t p) {
+      s->adj_mu0.push_back(s->mu[p]);
+      s->adj_K0.push_back((double)s->lam[p] + 2.0 * s->mu[p] / 3.0);
+    });
+  std::vector<float> mu_new, lam_new;
+  size_t c = 0;
+  bool ok = true;
+  double worst = INFINITY;
+  for_region_medium(s, [&](int i, int, int, int b, size_t p) {
+    const double mu = s->adj_mu0[c] + dmu[b], K = s->adj_K0[c] + dK[b];
+    const double lam = K - 2.0 * mu / 3.0;
+    c++;
+    if (!(mu >= 0) || !(lam + 2 * mu > 0) || !std::isfinite(mu) || !std::isfinite(K)) ok = false;
+    const double vp = std::sqrt(std::max(lam + 2 * mu, 0.0) / s->rho[p]);
+    const double ra = (i + 0.5) * s->dr * s->dth;
+    const double g = std::sqrt(1.0 / (s->dr * s->dr) + 1.0 / (ra * ra) + 1.0 / (s->dz * s->dz));
+    worst = std::min(worst, 1.0 / (vp * g));
+    mu_new.push_back((float)mu);
+    lam_new.push_back((float)lam);
+  });
+  if (!ok) return fail(CW_ERR_MATERIAL, "shifted moduli out of range (need mu >= 0, lambda + 2 mu > 0)");
+  if (s->dt > worst) return fail(CW_ERR_UNSTABLE, "dt %.6g exceeds the Courant limit %.6g of the shifted region",
+                                 s->dt, worst);
+  c = 0;
+  for_region_medium(s, [&](int, int, int, int, size_t p) {
+    s->mu[p] = mu_new[c];
+    s->lam[p] = lam_new[c];
+    c++;
+  });
+  if (s->bound) {
+    HIPCHK(hipSetDevice(s->device));
+    // the rings of the region, whole (contiguous in both medium layouts)
+    const size_t ring = s->med_rz ? (size_t)s->nz : (size_t)s->nt * s->nz;
+    const size_t off = (size_t)s->adj_i0 * ring, cnt = (size_t)(s->adj_i1 - s->adj_i0) * ring;
+    HIPCHK(hipMemcpyAsync(s->d_mu + off, s->mu.data() + off, cnt * sizeof(float), hipMemcpyHostToDevice, s->stream));
+    HIPCHK(hipMemcpyAsync(s->d_lam + off, s->lam.data() + off, cnt * sizeof(float), hipMemcpyHostToDevice,
+                          s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+  }
+  return CW_OK;
+}
+
+cw_status cw_gradient(cw_sim *s, int64_t n0, int64_t n1, double *loss, double *grad_mu, double *grad_K)
+{
+  if (!s || !loss || !grad_mu || !grad_K) return fail(CW_ERR_ARG, "null argument");
+  if (!s->bound) return fail(CW_ERR_STATE, "cw_bind first");
+  if (!s->adj) return fail(CW_ERR_STATE, "cw_set_adjoint before cw_bind");
+  if (s->storage != ST_F32) return fail(CW_ERR_STATE, "the gradient runs with float32 storage");
+  if (s->path == CW_PATH_FUSED) return fail(CW_ERR_STATE, "the gradient runs on the two-pass path");
+  cw_status st;
+  if ((st = check_adjoint_region(s)) != CW_OK) return st;
+  HIPCHK(hipSetDevice(s->device));
+  const int64_t N = s->adj_steps, C = s->adj_every, ncp = (N + C - 1) / C;
+  const size_t nst = adj_state_floats(s), n = s->n;
+  const size_t slab_r = (size_t)s->npr * s->nt * s->nz, slab_z = (size_t)s->nr * s->nt * nzs_of(s);
+  const int nrec = (int)s->receivers.size();
+  const AdjRegion g = adj_region(s);
+  const size_t nreg = adj_region_nodes(s), ncell = adj_region_cells(s);
+  std::vector<int> ck_cur(ncp);
+  auto state_copy = [&](float *ck, int buf, bool save) -> cw_status {
+    float *parts[3] = {s->fields[buf][0], slab_r ? s->psi_r[s->psi_cur][0] : nullptr,
+                       slab_z ? s->psi_z[s->psi_cur][0] : nullptr};
+    const size_t cnt[3] = {NF * n, NPSI_R * slab_r, NPSI_Z * slab_z};
+    size_t o = 0;
+    for (int q = 0; q < 3; q++) {
+      if (cnt[q])
+        HIPCHK(hipMemcpyAsync(save ? ck + o : parts[q], save ? parts[q] : ck + o, cnt[q] * sizeof(float),
+                              hipMemcpyDeviceToDevice, s->stream));
+      o += cnt[q];
+    }
+    return CW_OK;
+  };
+  // forward from rest, a checkpoint at the start of every segment
+  if ((st = zero_state(s)) != CW_OK) return st;
+  for (int64_t t = 0; t < N; t++) {
+    if (t % C == 0) {
+      ck_cur[t / C] = s->cur;
+      if ((st = state_copy(s->adj_ckpt + (size_t)(t / C) * nst, s->cur, true)) != CW_OK) return st;
+    }
+    if ((st = cw_step(s, 1)) != CW_OK) return st;
+  }
+  // loss and the receivers' adjoint weights
+  std::vector<double> tr((size_t)nrec * s->trace_cap);
+  HIPCHK(hipStreamSynchronize(s->stream));
+  if (nrec) HIPCHK(hipMemcpy(tr.data(), s->d_traces, tr.size() * sizeof(double), hipMemcpyDeviceToHost));
+  double L = 0.0;
+  std::vector<float> w((size_t)N * nrec, 0.0f);
+  for (int m = 0; m < nrec; m++) {
+    const Receiver &r = s->receivers[m];
+    if (r.kind != CW_REC_PRESSURE) continue;
+    const int cells = r.j < 0 ? s->nt : 1;
+    for (int64_t t = std::max<int64_t>(n0, 0); t < std::min(n1, N); t++) {
+      const double p = tr[(size_t)m * s->trace_cap + t];
+      L += p * p;
+      w[(size_t)t * nrec + m] = (float)(2.0 * p * (-1.0 / (3.0 * cells)));
+    }
+  }
+  *loss = L;
+  if (nrec) HIPCHK(hipMemcpy(s->adj_w, w.data(), w.size() * sizeof(float), hipMemcpyHostToDevice));
+  // adjoint state and accumulators from zero
+  HIPCHK(hipMemsetAsync(s->adj_fb[0], 0, nst * sizeof(float), s->stream));
+  HIPCHK(hipMemsetAsync(s->adj_glam, 0, 2 * ncell * sizeof(double), s->stream));
+  const StepArgs sa = step_args(s, 0, 1);
+  AdjArgs a{};
+  a.nr = s->nr; a.nt = s->nt; a.nz = s->nz; a.npr = s->npr; a.npz = s->npz; a.nzs = nzs_of(s);
+  a.dt = sa.dt; a.inv_dr = sa.inv_dr; a.inv_dz = sa.inv_dz; a.inv_dth = sa.inv_dth;
+  a.inv_rc = sa.inv_rc; a.inv_rf = sa.inv_rf;
+  a.rho = sa.rho; a.lam = sa.lam; a.mu = sa.mu; a.m_ring = sa.m_ring; a.m_row = sa.m_row;
+  for (int q = 0; q < NF; q++) a.fb[q] = s->adj_fb[q];
+  for (int q = 0; q < NPSI_R; q++) a.pr[q] = s->adj_pr[q];
+  for (int q = 0; q < NPSI_Z; q++) a.pz[q] = s->adj_pz[q];
+  for (int q = 0; q < 9; q++) a.T[q] = s->adj_T[q];
+  a.tab_r = sa.tab_r; a.tab_z = sa.tab_z;
+  // segments backwards: recompute the segment's strain rates, then its adjoint steps
+  for (int64_t seg = ncp - 1; seg >= 0; seg--) {
+    const int64_t t0 = seg * C, t1 = std::min(t0 + C, N);
+    if ((st = state_copy(s->adj_ckpt + (size_t)seg * nst, ck_cur[seg], false)) != CW_OK) return st;
+    s->cur = ck_cur[seg];
+    s->nstep = t0;
+    HIPCHK(launch_set_step(s->d_step, t0, s->stream));
+    for (int64_t t = t0; t < t1; t++) {
+      if ((st = cw_step(s, 1)) != CW_OK) return st;
+      HIPCHK(launch_adjoint_capture(a, g, s->fields[s->cur][VR], s->fields[s->cur][VT], s->fields[s->cur][VZ],
+                                    s->adj_Z + (size_t)(t - t0) * 6 * nreg, s->stream));
+    }
+    for (int64_t t = t1 - 1; t >= t0; t--)
+      HIPCHK(launch_adjoint_step(a, s->d_rec, nrec, s->adj_w + (size_t)t * nrec, g,
+                                 s->adj_Z + (size_t)(t - t0) * 6 * nreg, s->adj_glam, s->adj_gmu, s->stream));
+  }
+  std::vector<double> glam(ncell), gmu(ncell);
+  HIPCHK(hipStreamSynchronize(s->stream));
+  HIPCHK(hipMemcpy(glam.data(), s->adj_glam, ncell * sizeof(double), hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(gmu.data(), s->adj_gmu, ncell * sizeof(double), hipMemcpyDeviceToHost));
+  for (int b = 0; b < s->adj_nb; b++) { grad_mu[b] = 0.0; grad_K[b] = 0.0; }
+  const int nk = g.k1 - g.k0;
+  for (size_t c = 0; c < ncell; c++) {
+    const int b = (int)(c % nk) / s->adj_br;
+    grad_mu[b] += gmu[c] - (2.0 / 3.0) * glam[c];
+    grad_K[b] += glam[c];
+  }
+  return CW_OK;
 }
 
 }  // extern "C"

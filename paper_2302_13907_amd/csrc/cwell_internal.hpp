@@ -167,6 +167,35 @@ hipError_t launch_rescale(float *scl_written, float *scl_next, unsigned *maxabs,
 constexpr int kF16TargetExp = 11;   // scaled float16 maxima land in [2^10, 2^11)
 // depth-vectorized two-pass kernels (4 cells per thread), when nz % 4 == 0
 bool vec_applies(int nz);
+// Adjoint of the two-pass step (adjoint.hip).  fb: adjoints of the 9
+// fields (updated in place, one step back per launch_adjoint_step); pr, pz:
+// adjoints of the layer memory (same layout as psi_r, psi_z); T: nine
+// scratch arrays of n values for the adjoints of the update terms.
+struct AdjArgs {
+  int nr, nt, nz, npr, npz, nzs;
+  float dt, inv_dr, inv_dz, inv_dth;
+  const float *inv_rc, *inv_rf;
+  const float *rho, *lam, *mu;
+  size_t m_ring;
+  int m_row;
+  float *fb[NF];
+  float *pr[NPSI_R];
+  float *pz[NPSI_Z];
+  float *T[9];
+  const float *tab_r, *tab_z;
+};
+// Parameter region: cells [i0, i1) x all theta x [k0, k1); the gradient
+// reads the strain rates of the nodes [ea, eb) x all theta x [za, zb)
+// (one ring and one depth more on the inner / upper side).
+struct AdjRegion {
+  int i0, i1, k0, k1;
+  int ea, eb, za, zb;
+};
+hipError_t launch_adjoint_step(const AdjArgs &a, const Receiver *rec, int nrec, const float *w, const AdjRegion &g,
+                               const float *Z, double *glam, double *gmu, hipStream_t stream);
+hipError_t launch_adjoint_capture(const AdjArgs &a, const AdjRegion &g, const float *vr, const float *vt,
+                                  const float *vz, float *Z, hipStream_t stream);
+hipError_t launch_set_step(int64_t *step, int64_t value, hipStream_t stream);
 bool march_applies(int nt, int nz);
 bool stream_mix_supported(int r, int w);
 hipError_t launch_stream(const void *base, size_t n4, int r, int w, hipStream_t stream);

@@ -31,7 +31,8 @@ EXPORTS = ("cw_create", "cw_set_material", "cw_set_material_rz", "cw_set_pml", "
            "cw_workspace_bytes", "cw_bind", "cw_step", "cw_sync", "cw_get_traces",
            "cw_get_field", "cw_set_field", "cw_energy", "cw_reset", "cw_steps_done",
            "cw_ricker", "cw_destroy", "cw_last_error", "cw_profile", "cw_profile_read",
-           "cw_set_path", "cw_set_storage", "cw_stream_probe", "cw_set_graph")
+           "cw_set_path", "cw_set_storage", "cw_stream_probe", "cw_set_graph", "cw_set_adjoint",
+           "cw_set_region_moduli", "cw_gradient")
 
 STORAGE = {"f32": 0, "f16": 1, "bf16": 2}
 
@@ -93,6 +94,9 @@ def load():
         "cw_profile_read": [P, I32, DP, ctypes.POINTER(I64)],
         "cw_stream_probe": [P, ctypes.c_uint64, I32, I32, I32, P, DP],
         "cw_set_graph": [P, I32],
+        "cw_set_adjoint": [P, I64, I32, I32, I32, I32, I32, I32],
+        "cw_set_region_moduli": [P, DP, DP],
+        "cw_gradient": [P, I64, I64, DP, DP, DP],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -154,6 +158,7 @@ class Sim:
         self.lib = load()
         self.shape = (int(nr), int(ntheta), int(nz))
         self.dr, self.dz = float(dr), float(dz)
+        self._nbins = 0
         g = _Grid(int(nr), int(ntheta), int(nz), float(dr), float(dz))
         h = ctypes.c_void_p()
         _check(self.lib.cw_create(ctypes.byref(g), ctypes.byref(h)))
@@ -275,6 +280,31 @@ class Sim:
         """Kernel path of step(): "auto", "two-pass", "fused" or "march"."""
         _check(self.lib.cw_set_path(self.h, PATHS[path]))
 
+    def set_adjoint(self, nsteps: int, checkpoint_every: int, region):
+        """Configure the adjoint gradient (before bind): region = (i0, i1, k0,
+        nbins, bin_rows); nsteps forward steps, a checkpoint every
+        checkpoint_every steps."""
+        i0, i1, k0, nb, br = region
+        _check(self.lib.cw_set_adjoint(self.h, int(nsteps), int(checkpoint_every), int(i0), int(i1), int(k0),
+                                       int(nb), int(br)))
+        self._nbins = int(nb)
+
+    def set_region_moduli(self, dmu, dK):
+        """Shift the region's bins' mu and K (Pa) from the medium given at set_material."""
+        dmu = np.ascontiguousarray(dmu, dtype=np.float64)
+        dK = np.ascontiguousarray(dK, dtype=np.float64)
+        if dmu.shape != (self._nbins,) or dK.shape != (self._nbins,):
+            raise ValueError("one shift per bin")
+        _check(self.lib.cw_set_region_moduli(self.h, _dp(dmu), _dp(dK)))
+
+    def gradient(self, window):
+        """(loss, dL/dmu per bin, dL/dK per bin) of the loss over steps
+        [window[0], window[1]); runs the configured forward and adjoint."""
+        gm, gk = np.zeros(self._nbins), np.zeros(self._nbins)
+        loss = ctypes.c_double()
+        _check(self.lib.cw_gradient(self.h, int(window[0]), int(window[1]), ctypes.byref(loss), _dp(gm), _dp(gk)))
+        return loss.value, gm, gk
+
     def set_graph(self, steps: int):
         """Replay the two-pass step's launches as a HIP graph of `steps`
         (even) steps; 0 switches graph replay off."""
@@ -290,3 +320,26 @@ class Sim:
         n = ctypes.c_int64()
         _check(self.lib.cw_profile_read(self.h, KERNELS[kernel], ctypes.byref(ms), ctypes.byref(n)))
         return ms.value, n.value
+
+
+def cement_loss(sim: "Sim", window, dmu, dK):
+    """The receiver loss of `sim` over `window` as a differentiable function
+    of the per-bin shifts dmu, dK (float64 torch tensors of nbins values):
+    the forward sets the region's moduli and runs cw_gradient, whose
+    gradient the backward returns."""
+    import torch
+
+    class _CementLoss(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, mu_shift, k_shift):
+            sim.set_region_moduli(mu_shift.detach().cpu().numpy(), k_shift.detach().cpu().numpy())
+            loss, gm, gk = sim.gradient(window)
+            ctx.save_for_backward(torch.from_numpy(gm), torch.from_numpy(gk))
+            return torch.tensor(loss, dtype=torch.float64)
+
+        @staticmethod
+        def backward(ctx, g):
+            gm, gk = ctx.saved_tensors
+            return g * gm, g * gk
+
+    return _CementLoss.apply(dmu, dK)

@@ -190,6 +190,19 @@ def mixed_precision_case() -> Workload:
                     z_top=2048 * 5e-3, ramp=ramp)
 
 
+def adjoint_case() -> Workload:
+    """128 x 64 x 2048 cells of 5 mm, 1500 steps, 20-cell layer, 15 kHz axis
+    source at k = 512, 32 axis receivers every 20 mm below it, cement top at
+    k = 1024 with a 0.32 m (64-row) shear ramp.  Gradient parameters: the
+    cement annulus (rings 22..29) in 64 bins of one row below the top;
+    checkpoints every 100 steps; loss over steps [750, 1500)."""
+    w = Workload("cased-well 128x64x2048 (5 mm), 1500 steps, adjoint", 128, 64, 2048, 5e-3, 5e-3,
+                 steps=1500, npml=20, f0=15e3, src_k=512,
+                 rec_k=[516 + 4 * m for m in range(32)], z_top=1024 * 5e-3, ramp=0.32)
+    w.extra.update(region=(22, 30, 1025, 64, 1), checkpoint_every=100, window=(750, 1500))
+    return w
+
+
 def scaled_case(nr: int, nt: int, nz: int, steps: int = 50) -> Workload:
     """The production medium on a smaller grid (same 2 mm cells and layout
     fractions); used for parity at sizes the oracle finishes quickly."""

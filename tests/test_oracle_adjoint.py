@@ -45,40 +45,7 @@ def test_adjoint_step_is_the_transpose(layer):
     assert abs(lhs - rhs) <= 1e-13 * abs(lhs), (lhs, rhs)
 
 
-# a thin well (hole 20 mm, casing to 30 mm, cement annulus to 50 mm) so that
-# the wave reaches the cement within a short run
-H = 5e-3
-SHAPE = (20, 8, 96)
-RADII = (0.02, 0.03, 0.05)
-KTOP = 48
-STEPS = 400
-WINDOW = (150, 400)
-REGION = (6, 10, KTOP + 1, 8, 2)      # annulus rings 6..9, 8 bins of 2 rows below the cement top
-
-
-def _medium(dmu=None, dK=None):
-    rho, lam, mu = inputs.cased_well(*SHAPE, H, H, z_top=KTOP * H, ramp=0.1, radii=RADII)
-    if dmu is not None:
-        i0, i1, k0, nb, br = REGION
-        K = lam + 2.0 * mu / 3.0
-        for b in range(nb):
-            sl = (slice(i0, i1), slice(None), slice(k0 + b * br, k0 + (b + 1) * br))
-            mu[sl] += dmu[b]
-            K[sl] += dK[b]
-        lam = K - 2.0 * mu / 3.0
-    return rho, lam, mu
-
-
-def _sim(med, dt=None):
-    o = oracle.OracleSim(*SHAPE, H, H)
-    o.set_material(*med)
-    o.set_pml(6, 6, 1e-3, math.pi * 40e3)
-    dt = dt or 0.5 * o.cfl_dt()
-    o.set_dt(dt)
-    o.add_source("volume", 0, -1, 40, oracle.ricker(40e3, (np.arange(STEPS) + 0.5) * dt))
-    for k in range(20, 44, 2):
-        o.add_receiver("pressure", 0, -1, k)
-    return o, dt
+from adjoint_case import REGION, STEPS, WINDOW, medium as _medium, oracle_sim as _sim
 
 
 def adjoint_reference():
