@@ -92,7 +92,7 @@ PROFILE_VARIANTS = {
     "march_f32": "--path march --storage f32",
 }
 PROFILE_RUN = ("python3 -u bench.py --steps 20 --warmup 5 --no-cpu-baseline --no-storage-forms --no-stream-ceiling "
-               "--no-graph-replay --no-adjoint --copy-gib 1")
+               "--no-graph-replay --no-adjoint --no-batched --copy-gib 1")
 PROFILE_PASSES = (
     ("stats", "--kernel-trace --stats"),
     ("fetch", "--pmc FETCH_SIZE"),
@@ -391,6 +391,66 @@ def adjoint_gradient():
             "workspace_GB": round(ws / 1e9, 2), "loss": loss}
 
 
+def batched_form(small: bool = False, steps: int = 40, graph: int = 20):
+    """A batched workload (48 uneven 128 x 64 x Nz instances, or with `small`
+    256 uneven 48 x 16 x Nz ones): aggregate Gcell-updates/s of the
+    instances stepped one after another, of one batch (autotuned tile
+    shapes), and of the batch under graph replay."""
+    import numpy as np
+    import torch
+    from paper_2302_13907_amd import autotune, cwell, inputs
+    ws = inputs.small_batched_case() if small else inputs.batched_case()
+    log("batched form: %d instances" % len(ws))
+    sims = []
+    for w in ws:
+        s = cwell.Sim(w.nr, w.nt, w.nz, w.dr, w.dz)
+        s.set_material(*w.medium_rz())
+        s.set_pml(w.npml, w.npml, w.pml_rc, math.pi * w.f0)
+        dt = w.cfl_fraction * s.cfl_dt()
+        s.set_dt(dt)
+        total = 4 * steps + 8 + 2 * graph
+        s.add_source("volume", 0, -1, w.src_k, cwell.ricker(w.f0, (np.arange(total) + 0.5) * dt))
+        for k in w.rec_k:
+            s.add_receiver("pressure", 0, -1, k)
+        s.set_trace_capacity(total)
+        s.set_path("two-pass")
+        s.bind("cuda:0")
+        sims.append(s)
+    cells = sum(w.cells for w in ws)
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    for s in sims:
+        s.step(2)
+    t_seq = timed(lambda: [s.step(steps) for s in sims])
+    b = cwell.Batch(sims)
+    tiles = autotune.tune_batch(b, sims)
+    b.bind()
+    b.step(2)
+    t_bat = timed(lambda: b.step(steps))
+    b.set_graph(graph)
+    b.step(2 * graph)                             # capture and warm up
+    t_gr = timed(lambda: b.step(steps))
+    b.close()
+    for s in sims:
+        s.close()
+    del sims
+    torch.cuda.empty_cache()
+    gc = lambda t: round(cells * steps / t / 1e9, 3)
+    depths = sorted({w.nz for w in ws})
+    return {"workload": "%d instances of %dx%dxNz, Nz in {%d..%d} (5 mm)" % (len(ws), ws[0].nr, ws[0].nt,
+                                                                           depths[0], depths[-1]),
+            "cells_per_step": cells, "steps": steps, "unit": "Gcell-updates/s",
+            "sequential": gc(t_seq), "batched": gc(t_bat), "batched_graph": gc(t_gr),
+            "speedup_batched": round(t_seq / t_bat, 3), "speedup_batched_graph": round(t_seq / t_gr, 3),
+            "tiles": {str(ws[q].nz): tz for q, tz in sorted(tiles.items())}}
+
+
 def storage_forms(path: str, warmup: int = 10, steps: int = 100):
     """Gcell-updates/s of the mixed-precision workload with float32, float16
     and bfloat16 field storage (float32 arithmetic in every case)."""
@@ -425,6 +485,8 @@ def main():
     ap.add_argument("--no-storage-forms", action="store_true",
                     help="skip the float32 / float16 / bfloat16 storage comparison on the "
                          "192 x 96 x 4096 mixed-precision workload")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the batched-form measurements (48 uneven large and 256 uneven small instances)")
     ap.add_argument("--no-adjoint", action="store_true",
                     help="skip the seconds-per-adjoint-gradient measurement")
     ap.add_argument("--no-graph-replay", action="store_true",
@@ -523,6 +585,8 @@ def main():
         out["graph_replay"] = graph_replay(args.path)
     if not args.no_adjoint:
         out["adjoint"] = adjoint_gradient()
+    if not args.no_batched:
+        out["batched"] = [batched_form(), batched_form(small=True)]
     if not args.no_cpu_baseline:
         log("CPU baseline: FP64 oracle for about %.0f s" % args.cpu_seconds)
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)

@@ -270,6 +270,30 @@ cw_status cw_set_adjoint(cw_sim *s, int64_t nsteps, int32_t checkpoint_every, in
 cw_status cw_set_region_moduli(cw_sim *s, const double *dmu, const double *dK);
 cw_status cw_gradient(cw_sim *s, int64_t n0, int64_t n1, double *loss, double *grad_mu, double *grad_K);
 
+/* Batches: many simulations (of any sizes) advanced together, each step
+   one velocity launch and one stress launch over the tiles of all of them
+   (plus batched source, receiver and step-counter launches), so small and
+   uneven instances share the device.  Every simulation must be bound on
+   one device and one stream, use float32 storage, have nz a multiple of 4
+   and have done steps of one parity; each keeps its own state, sources,
+   receivers and traces (cw_get_traces, cw_get_field etc. work as usual) and
+   gives bitwise the results of stepping it alone with CW_PATH_TWO_PASS.
+   The batch descriptor lives in a small caller-owned device workspace
+   (cw_batch_workspace_bytes, 256-byte aligned).  Tile shape per instance
+   (cw_batch_set_tile, before cw_batch_bind): a workgroup covers tz_waves x
+   256 depth cells of 4 / tz_waves theta rows, tz_waves in {1, 2, 4}
+   (default 4); shallow or ragged columns waste fewer lanes with shorter
+   tiles.  cw_batch_set_graph: as cw_set_graph, for the batch.  The batch
+   must be destroyed before its simulations. */
+typedef struct cw_batch cw_batch;
+cw_status cw_batch_create(cw_sim *const *sims, int32_t count, cw_batch **out);
+cw_status cw_batch_set_tile(cw_batch *b, int32_t index, int32_t tz_waves);
+cw_status cw_batch_workspace_bytes(const cw_batch *b, uint64_t *bytes);
+cw_status cw_batch_bind(cw_batch *b, void *workspace, uint64_t bytes);
+cw_status cw_batch_set_graph(cw_batch *b, int32_t steps);
+cw_status cw_batch_step(cw_batch *b, int64_t nsteps);
+void cw_batch_destroy(cw_batch *b);
+
 /* Bandwidth reference (measurement only, not part of the scheme): stream
    nread + nwrite arrays of bytes_per_array bytes each, laid out back to
    back in the caller's device buffer `dev` (16-byte aligned, at least

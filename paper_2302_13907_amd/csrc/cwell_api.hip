@@ -1265,4 +1265,213 @@ cw_status cw_gradient(cw_sim *s, int64_t n0, int64_t n1, double *loss, double *g
   return CW_OK;
 }
 
+/* ------------------------------ batches ------------------------------ */
+struct cw_batch {
+  std::vector<cw_sim *> sims;
+  std::vector<int> tz;                 // tile shape per instance (wavefronts along depth)
+  bool bound = false;
+  int device = 0;
+  hipStream_t stream = nullptr;
+  BatchInst *d_inst = nullptr;
+  long *d_tile0 = nullptr;
+  long tiles = 0;
+  int max_rec = 0;
+  bool any_inject = false;
+  int graph_steps = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  hipStream_t capture_stream = nullptr;
+  void drop_graph()
+  {
+    if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    graph_exec = nullptr;
+    graph = nullptr;
+  }
+  ~cw_batch()
+  {
+    drop_graph();
+    if (capture_stream) (void)hipStreamDestroy(capture_stream);
+  }
+};
+
+static cw_status check_batch_member(const cw_batch *b, const cw_sim *s)
+{
+  if (!s) return fail(CW_ERR_ARG, "null simulation in the batch");
+  if (!s->bound) return fail(CW_ERR_STATE, "every simulation of a batch must be bound");
+  if (s->storage != ST_F32) return fail(CW_ERR_STATE, "batches take float32 storage");
+  if (!vec_applies(s->nz)) return fail(CW_ERR_RANGE, "batches need nz a multiple of 4 (have %d)", s->nz);
+  if (!b->sims.empty()) {
+    const cw_sim *f = b->sims[0];
+    if (s->device != f->device || s->stream != f->stream)
+      return fail(CW_ERR_ARG, "the simulations of a batch must share one device and one stream");
+    if (s->cur != f->cur) return fail(CW_ERR_STATE, "the simulations of a batch must have done steps of one parity");
+  }
+  return CW_OK;
+}
+
+cw_status cw_batch_create(cw_sim *const *sims, int32_t count, cw_batch **out)
+{
+  if (!sims || !out || count < 1 || count > 65535) return fail(CW_ERR_ARG, "need 1..65535 simulations");
+  cw_batch *b = new (std::nothrow) cw_batch;
+  if (!b) return fail(CW_ERR_NOMEM, "out of host memory");
+  for (int q = 0; q < count; q++) {
+    const cw_status st = check_batch_member(b, sims[q]);
+    if (st != CW_OK) {
+      delete b;
+      return st;
+    }
+    b->sims.push_back(sims[q]);
+    b->tz.push_back(4);
+  }
+  b->device = sims[0]->device;
+  b->stream = sims[0]->stream;
+  *out = b;
+  return CW_OK;
+}
+
+void cw_batch_destroy(cw_batch *b) { delete b; }
+
+cw_status cw_batch_set_tile(cw_batch *b, int32_t index, int32_t tz_waves)
+{
+  if (!b) return fail(CW_ERR_ARG, "null batch");
+  if (b->bound) return fail(CW_ERR_STATE, "tile shapes are set before cw_batch_bind");
+  if (index < 0 || index >= (int)b->sims.size()) return fail(CW_ERR_RANGE, "no instance %d", index);
+  if (tz_waves != 1 && tz_waves != 2 && tz_waves != 4) return fail(CW_ERR_RANGE, "tile depth must be 1, 2 or 4 wavefronts");
+  b->tz[index] = tz_waves;
+  return CW_OK;
+}
+
+static size_t batch_bytes(const cw_batch *b)
+{
+  return align256(b->sims.size() * sizeof(BatchInst)) + align256(b->sims.size() * sizeof(long));
+}
+
+cw_status cw_batch_workspace_bytes(const cw_batch *b, uint64_t *bytes)
+{
+  if (!b || !bytes) return fail(CW_ERR_ARG, "null argument");
+  *bytes = batch_bytes(b);
+  return CW_OK;
+}
+
+cw_status cw_batch_bind(cw_batch *b, void *workspace, uint64_t bytes)
+{
+  if (!b || !workspace) return fail(CW_ERR_ARG, "null argument");
+  if (b->bound) return fail(CW_ERR_STATE, "already bound");
+  if ((uintptr_t)workspace & 255) return fail(CW_ERR_ARG, "workspace must be 256-byte aligned");
+  if (bytes < batch_bytes(b)) return fail(CW_ERR_RANGE, "workspace of %llu bytes, need %llu", (unsigned long long)bytes,
+                                          (unsigned long long)batch_bytes(b));
+  const int n = (int)b->sims.size();
+  std::vector<BatchInst> h(n);
+  std::vector<long> t0(n);
+  long tiles = 0;
+  for (int q = 0; q < n; q++) {
+    const cw_sim *s = b->sims[q];
+    BatchInst &I = h[q];
+    I.a[0] = step_args(s, 0, 1);
+    I.a[1] = step_args(s, 1, 0);
+    const int w = b->tz[q], rows = 4 / w;
+    I.tz_waves = w;
+    I.nseg = (s->nz + 256 * w - 1) / (256 * w);
+    I.tiles = (long)s->nr * ((s->nt + rows - 1) / rows) * I.nseg;
+    I.tile0 = tiles;
+    t0[q] = tiles;
+    tiles += I.tiles;
+    I.inject = s->d_inject; I.ninj = s->ninject;
+    I.rec = s->d_rec; I.nrec = (int)s->receivers.size();
+    I.cap = s->trace_cap; I.traces = s->d_traces; I.step = s->d_step;
+    b->max_rec = std::max(b->max_rec, I.nrec);
+    b->any_inject = b->any_inject || s->ninject > 0;
+  }
+  if (tiles > 0x7fffffff) return fail(CW_ERR_RANGE, "%ld workgroups exceed one launch", tiles);
+  b->tiles = tiles;
+  char *w = (char *)workspace;
+  b->d_inst = (BatchInst *)w;
+  b->d_tile0 = (long *)(w + align256(n * sizeof(BatchInst)));
+  HIPCHK(hipSetDevice(b->device));
+  HIPCHK(hipMemcpy(b->d_inst, h.data(), n * sizeof(BatchInst), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(b->d_tile0, t0.data(), n * sizeof(long), hipMemcpyHostToDevice));
+  b->bound = true;
+  return CW_OK;
+}
+
+cw_status cw_batch_set_graph(cw_batch *b, int32_t steps)
+{
+  if (!b) return fail(CW_ERR_ARG, "null batch");
+  if (steps < 0 || steps % 2 || steps > kMaxGraphSteps)
+    return fail(CW_ERR_RANGE, "graph steps must be even and in [0, %d] (have %d)", kMaxGraphSteps, steps);
+  b->drop_graph();
+  b->graph_steps = steps;
+  return CW_OK;
+}
+
+// one batched step's launches on `stream` (parity = the instances' common buffer parity)
+static cw_status batch_launches(cw_batch *b, int parity, hipStream_t stream)
+{
+  const int n = (int)b->sims.size();
+  HIPCHK(launch_velocity_batch(b->d_inst, b->d_tile0, n, b->tiles, parity, stream));
+  if (b->any_inject) HIPCHK(launch_inject_batch(b->d_inst, n, 0, parity, stream));
+  HIPCHK(launch_stress_batch(b->d_inst, b->d_tile0, n, b->tiles, parity, stream));
+  if (b->any_inject) HIPCHK(launch_inject_batch(b->d_inst, n, 1, parity, stream));
+  HIPCHK(launch_record_batch(b->d_inst, n, b->max_rec, parity, stream));
+  HIPCHK(launch_step_done_batch(b->d_inst, n, stream));
+  return CW_OK;
+}
+
+cw_status cw_batch_step(cw_batch *b, int64_t nsteps)
+{
+  if (!b) return fail(CW_ERR_ARG, "null batch");
+  if (!b->bound) return fail(CW_ERR_STATE, "cw_batch_bind first");
+  if (nsteps < 0) return fail(CW_ERR_RANGE, "negative step count");
+  cw_batch probe;
+  for (cw_sim *s : b->sims) {
+    cw_status st = check_batch_member(&probe, s);
+    if (st != CW_OK) return st;
+    if (s->cur != b->sims[0]->cur) return fail(CW_ERR_STATE, "the instances' buffer parities differ");
+    if (!s->receivers.empty() && s->nstep + nsteps > s->trace_cap)
+      return fail(CW_ERR_RANGE, "trace capacity %lld exceeded", (long long)s->trace_cap);
+    probe.sims.push_back(s);
+  }
+  HIPCHK(hipSetDevice(b->device));
+  cw_status st;
+  auto advance = [&](int64_t k) {
+    for (cw_sim *s : b->sims) {
+      s->nstep += k;
+      if (k & 1) s->cur = 1 - s->cur;
+    }
+  };
+  int64_t done = 0;
+  while (done < nsteps) {
+    const int parity = b->sims[0]->cur;
+    if (b->graph_steps > 0 && parity == 0 && nsteps - done >= b->graph_steps) {
+      if (!b->graph_exec) {
+        if (!b->capture_stream) HIPCHK(hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking));
+        const hipError_t eb = hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal);
+        cw_status cst = eb == hipSuccess ? CW_OK : fail(CW_ERR_HIP, "graph capture: %s", hipGetErrorString(eb));
+        for (int g = 0; g < b->graph_steps && cst == CW_OK; g++) cst = batch_launches(b, g & 1, b->capture_stream);
+        hipGraph_t gr = nullptr;
+        const hipError_t ee = eb == hipSuccess ? hipStreamEndCapture(b->capture_stream, &gr) : hipSuccess;
+        if (cst != CW_OK || ee != hipSuccess) {
+          if (gr) (void)hipGraphDestroy(gr);
+          return cst != CW_OK ? cst : fail(CW_ERR_HIP, "graph capture failed: %s", hipGetErrorString(ee));
+        }
+        b->graph = gr;
+        const hipError_t ei = hipGraphInstantiate(&b->graph_exec, gr, nullptr, nullptr, 0);
+        if (ei != hipSuccess) {
+          b->drop_graph();
+          return fail(CW_ERR_HIP, "graph instantiation failed: %s", hipGetErrorString(ei));
+        }
+      }
+      HIPCHK(hipGraphLaunch(b->graph_exec, b->stream));
+      done += b->graph_steps;
+      advance(b->graph_steps);
+      continue;
+    }
+    if ((st = batch_launches(b, parity, b->stream)) != CW_OK) return st;
+    done++;
+    advance(1);
+  }
+  return CW_OK;
+}
+
 }  // extern "C"

@@ -167,6 +167,33 @@ hipError_t launch_rescale(float *scl_written, float *scl_next, unsigned *maxabs,
 constexpr int kF16TargetExp = 11;   // scaled float16 maxima land in [2^10, 2^11)
 // depth-vectorized two-pass kernels (4 cells per thread), when nz % 4 == 0
 bool vec_applies(int nz);
+// One instance of a batched two-pass step (float32 storage): its step
+// arguments for both buffer parities (parity p reads fields[p] and writes
+// fields[1 - p]), its tile shape and share of the batched grid, and its
+// sources, receivers and step counter.  Tile shape: a workgroup's four
+// wavefronts cover tz_waves x 256 depth cells of 4 / tz_waves theta rows.
+struct BatchInst {
+  StepArgs a[2];
+  long tile0;               // first workgroup of this instance
+  long tiles;               // workgroups of this instance
+  int tz_waves;             // 1, 2 or 4
+  int nseg;                 // depth segments per column, ceil(nz / (256 tz_waves))
+  const Inject *inject;
+  int ninj;
+  const Receiver *rec;
+  int nrec;
+  int64_t cap;
+  double *traces;
+  int64_t *step;
+};
+hipError_t launch_velocity_batch(const BatchInst *dev, const long *tile0, int count, long tiles, int parity,
+                                 hipStream_t stream);
+hipError_t launch_stress_batch(const BatchInst *dev, const long *tile0, int count, long tiles, int parity,
+                               hipStream_t stream);
+hipError_t launch_inject_batch(const BatchInst *dev, int count, int phase, int parity, hipStream_t stream);
+hipError_t launch_record_batch(const BatchInst *dev, int count, int max_rec, int parity, hipStream_t stream);
+hipError_t launch_step_done_batch(const BatchInst *dev, int count, hipStream_t stream);
+
 // Adjoint of the two-pass step (adjoint.hip).  fb: adjoints of the 9
 // fields (updated in place, one step back per launch_adjoint_step); pr, pz:
 // adjoints of the layer memory (same layout as psi_r, psi_z); T: nine

@@ -262,10 +262,8 @@ __global__ void __launch_bounds__(256) k_stress_basic(StepArgs a, int nbx)
 // One block applies every injection of the phase in list order, so two
 // sources hitting the same node add in a fixed order.
 template <class S>
-__global__ void __launch_bounds__(256) k_inject(const Inject *list, int ninj, int phase,
-                                                const int64_t *stepp, StepArgs a)
+__device__ void inject_all(const Inject *list, int ninj, int phase, int64_t step, const StepArgs &a)
 {
-  const int64_t step = *stepp;                     // steps done (device counter)
   for (int m = 0; m < ninj; m++) {
     const Inject e = list[m];
     if (e.phase == phase && step < e.nsamp) {
@@ -284,13 +282,23 @@ __global__ void __launch_bounds__(256) k_inject(const Inject *list, int ninj, in
   }
 }
 
+template <class S>
+__global__ void __launch_bounds__(256) k_inject(const Inject *list, int ninj, int phase,
+                                                const int64_t *stepp, StepArgs a)
+{
+  inject_all<S>(list, ninj, phase, *stepp, a);      // step: steps done (device counter)
+}
+
+__global__ void __launch_bounds__(256) k_inject_batch(const BatchInst *B, int phase, int parity)
+{
+  const BatchInst &I = B[blockIdx.x];
+  inject_all<StF32>(I.inject, I.ninj, phase, *I.step, I.a[parity]);
+}
+
 // One wavefront per receiver; float64 sum over the ring in a fixed order.
 template <class S>
-__global__ void __launch_bounds__(64) k_record(const Receiver *rec, const int64_t *stepp, int64_t cap,
-                                               StepArgs a, double *traces)
+__device__ void record_one(const Receiver &r, int m, int64_t step, int64_t cap, const StepArgs &a, double *traces)
 {
-  const int64_t step = *stepp;
-  const Receiver r = rec[blockIdx.x];
   const int j0 = r.j < 0 ? 0 : r.j, j1 = r.j < 0 ? a.nt : r.j + 1;
   const float *o = a.scl_out;
   double acc = 0.0;
@@ -305,8 +313,29 @@ __global__ void __launch_bounds__(64) k_record(const Receiver *rec, const int64_
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
   if (threadIdx.x == 0) {
     const double cnt = (double)(j1 - j0);
-    traces[(size_t)blockIdx.x * cap + step] = r.kind == 0 ? -acc / (3.0 * cnt) : acc / cnt;
+    traces[(size_t)m * cap + step] = r.kind == 0 ? -acc / (3.0 * cnt) : acc / cnt;
   }
+}
+
+template <class S>
+__global__ void __launch_bounds__(64) k_record(const Receiver *rec, const int64_t *stepp, int64_t cap,
+                                               StepArgs a, double *traces)
+{
+  record_one<S>(rec[blockIdx.x], blockIdx.x, *stepp, cap, a, traces);
+}
+
+// grid (receivers of the largest instance, instances)
+__global__ void __launch_bounds__(64) k_record_batch(const BatchInst *B, int parity)
+{
+  const BatchInst &I = B[blockIdx.y];
+  if ((int)blockIdx.x >= I.nrec) return;
+  record_one<StF32>(I.rec[blockIdx.x], blockIdx.x, *I.step, I.cap, I.a[parity], I.traces);
+}
+
+__global__ void k_step_done_batch(const BatchInst *B, int count)
+{
+  const int q = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (q < count) *B[q].step += 1;
 }
 
 // Energy density of one cell in float64; a.in = level n, a.out = level n+1.
@@ -471,6 +500,25 @@ hipError_t launch_energy(const StepArgs &a, int storage, double *partials, int n
   });
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(256), 0, stream, partials, nblocks, scale, result);
+  return hipGetLastError();
+}
+
+hipError_t launch_inject_batch(const BatchInst *dev, int count, int phase, int parity, hipStream_t stream)
+{
+  hipLaunchKernelGGL(k_inject_batch, dim3(count), dim3(256), 0, stream, dev, phase, parity);
+  return hipGetLastError();
+}
+
+hipError_t launch_record_batch(const BatchInst *dev, int count, int max_rec, int parity, hipStream_t stream)
+{
+  if (max_rec == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_record_batch, dim3(max_rec, count), dim3(64), 0, stream, dev, parity);
+  return hipGetLastError();
+}
+
+hipError_t launch_step_done_batch(const BatchInst *dev, int count, hipStream_t stream)
+{
+  hipLaunchKernelGGL(k_step_done_batch, dim3((count + 63) / 64), dim3(64), 0, stream, dev, count);
   return hipGetLastError();
 }
 

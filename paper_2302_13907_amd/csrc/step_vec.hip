@@ -298,6 +298,63 @@ k_stress_vec(StepArgs a, int nbx)
   }
 }
 
+// Batched form: one workgroup grid over the tiles of every instance; the
+// instance is found by a binary search of the tiles' first indices (a small
+// array the scalar cache keeps), then the column code runs as above.
+__device__ __forceinline__ int batch_instance(const long *tile0, int count, long t)
+{
+  int lo = 0, hi = count - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (tile0[mid] <= t) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// this wavefront's (ring, theta row, depth group) in tile t of instance I; false if the row is past nt
+// (32-bit index arithmetic: a batched grid has fewer than 2^31 workgroups)
+__device__ __forceinline__ bool batch_cell(const BatchInst &I, const StepArgs &a, long t, int &i, int &j, int &kb,
+                                           bool &live)
+{
+  const int w = I.tz_waves, rows = 4 / w;
+  const int wv = threadIdx.x >> 6, dz = wv % w, dr = wv / w;
+  const unsigned local = (unsigned)(t - I.tile0), nseg = (unsigned)I.nseg;
+  const unsigned seg = local % nseg, rest = local / nseg;
+  const unsigned njt = (unsigned)((a.nt + rows - 1) / rows);
+  j = (int)(rest % njt) * rows + dr;
+  i = (int)(rest / njt);
+  if (j >= a.nt) return false;
+  const int k0 = (int)seg * w * 256 + dz * 256 + (int)(threadIdx.x & 63) * 4;
+  live = k0 < a.nz;
+  kb = live ? k0 : a.nz - VW;
+  return true;
+}
+
+__global__ void __launch_bounds__(256) k_velocity_batch(const BatchInst *__restrict__ B,
+                                                        const long *__restrict__ tile0, int count, int parity)
+{
+  const BatchInst &I = B[batch_instance(tile0, count, blockIdx.x)];
+  const StepArgs a = I.a[parity];     // a private copy: the field stores cannot alias it
+  int i, j, kb;
+  bool live;
+  if (!batch_cell(I, a, blockIdx.x, i, j, kb, live)) return;   // whole wavefront; no barriers here
+  float mr = 0.0f, mt = 0.0f, mz = 0.0f;
+  velocity_column<StF32>(a, i, j, kb, live, mr, mt, mz);
+}
+
+__global__ void __launch_bounds__(256) k_stress_batch(const BatchInst *__restrict__ B,
+                                                      const long *__restrict__ tile0, int count, int parity)
+{
+  const BatchInst &I = B[batch_instance(tile0, count, blockIdx.x)];
+  const StepArgs a = I.a[parity];
+  int i, j, kb;
+  bool live;
+  if (!batch_cell(I, a, blockIdx.x, i, j, kb, live)) return;
+  float mx[6] = {0, 0, 0, 0, 0, 0};
+  stress_column<StF32>(a, i, j, kb, live, mx);
+}
+
 template <class F>
 hipError_t dispatch(int storage, F &&f)
 {
@@ -333,6 +390,22 @@ hipError_t launch_stress_vec(const StepArgs &a, int storage, hipStream_t stream)
     hipLaunchKernelGGL(k_stress_vec<decltype(s)>, dim3((unsigned)g), dim3(256), 0, stream, a, nbx);
     return hipGetLastError();
   });
+}
+
+hipError_t launch_velocity_batch(const BatchInst *dev, const long *tile0, int count, long tiles, int parity,
+                                 hipStream_t stream)
+{
+  if (tiles < 1 || tiles > 0x7fffffff) return hipErrorInvalidConfiguration;
+  hipLaunchKernelGGL(k_velocity_batch, dim3((unsigned)tiles), dim3(256), 0, stream, dev, tile0, count, parity);
+  return hipGetLastError();
+}
+
+hipError_t launch_stress_batch(const BatchInst *dev, const long *tile0, int count, long tiles, int parity,
+                               hipStream_t stream)
+{
+  if (tiles < 1 || tiles > 0x7fffffff) return hipErrorInvalidConfiguration;
+  hipLaunchKernelGGL(k_stress_batch, dim3((unsigned)tiles), dim3(256), 0, stream, dev, tile0, count, parity);
+  return hipGetLastError();
 }
 
 }  // namespace cw

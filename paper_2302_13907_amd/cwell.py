@@ -32,7 +32,8 @@ EXPORTS = ("cw_create", "cw_set_material", "cw_set_material_rz", "cw_set_pml", "
            "cw_get_field", "cw_set_field", "cw_energy", "cw_reset", "cw_steps_done",
            "cw_ricker", "cw_destroy", "cw_last_error", "cw_profile", "cw_profile_read",
            "cw_set_path", "cw_set_storage", "cw_stream_probe", "cw_set_graph", "cw_set_adjoint",
-           "cw_set_region_moduli", "cw_gradient")
+           "cw_set_region_moduli", "cw_gradient", "cw_batch_create", "cw_batch_set_tile",
+           "cw_batch_workspace_bytes", "cw_batch_bind", "cw_batch_set_graph", "cw_batch_step", "cw_batch_destroy")
 
 STORAGE = {"f32": 0, "f16": 1, "bf16": 2}
 
@@ -97,6 +98,12 @@ def load():
         "cw_set_adjoint": [P, I64, I32, I32, I32, I32, I32, I32],
         "cw_set_region_moduli": [P, DP, DP],
         "cw_gradient": [P, I64, I64, DP, DP, DP],
+        "cw_batch_create": [ctypes.POINTER(P), I32, ctypes.POINTER(P)],
+        "cw_batch_set_tile": [P, I32, I32],
+        "cw_batch_workspace_bytes": [P, ctypes.POINTER(ctypes.c_uint64)],
+        "cw_batch_bind": [P, P, ctypes.c_uint64],
+        "cw_batch_set_graph": [P, I32],
+        "cw_batch_step": [P, I64],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -104,6 +111,8 @@ def load():
         fn.restype = ctypes.c_int32
     lib.cw_destroy.argtypes = [P]
     lib.cw_destroy.restype = None
+    lib.cw_batch_destroy.argtypes = [P]
+    lib.cw_batch_destroy.restype = None
     lib.cw_last_error.argtypes = []
     lib.cw_last_error.restype = ctypes.c_char_p
     _lib = lib
@@ -320,6 +329,51 @@ class Sim:
         n = ctypes.c_int64()
         _check(self.lib.cw_profile_read(self.h, KERNELS[kernel], ctypes.byref(ms), ctypes.byref(n)))
         return ms.value, n.value
+
+
+class Batch:
+    """Simulations advanced together by batched launches (see cw_batch_* in
+    include/cwell.h).  The simulations must be bound (on one stream) first."""
+
+    def __init__(self, sims):
+        self.lib = load()
+        self.sims = list(sims)
+        arr = (ctypes.c_void_p * len(self.sims))(*[s.h for s in self.sims])
+        h = ctypes.c_void_p()
+        _check(self.lib.cw_batch_create(arr, len(self.sims), ctypes.byref(h)))
+        self.h = h
+        self._ws = None
+
+    def set_tile(self, index: int, tz_waves: int):
+        _check(self.lib.cw_batch_set_tile(self.h, int(index), int(tz_waves)))
+
+    def bind(self):
+        import torch
+        b = ctypes.c_uint64()
+        _check(self.lib.cw_batch_workspace_bytes(self.h, ctypes.byref(b)))
+        ws = torch.empty(b.value + 256, dtype=torch.uint8, device=self.sims[0].workspace.device)
+        ptr = ws.data_ptr()
+        ptr += (-ptr) % 256
+        _check(self.lib.cw_batch_bind(self.h, ctypes.c_void_p(ptr), b.value))
+        self._ws = ws
+
+    def set_graph(self, steps: int):
+        _check(self.lib.cw_batch_set_graph(self.h, int(steps)))
+
+    def step(self, n: int = 1):
+        _check(self.lib.cw_batch_step(self.h, int(n)))
+
+    def close(self):
+        if self.h:
+            self.lib.cw_batch_destroy(self.h)
+            self.h = None
+            self._ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def cement_loss(sim: "Sim", window, dmu, dK):

@@ -13,7 +13,7 @@ values are not given in the text; the values below are typical ones.
 from __future__ import annotations
 
 from dataclasses import dataclass, field
-from typing import List, Optional, Tuple
+from typing import List, Optional, Tuple, Sequence
 
 import numpy as np
 
@@ -201,6 +201,35 @@ def adjoint_case() -> Workload:
                  rec_k=[516 + 4 * m for m in range(32)], z_top=1024 * 5e-3, ramp=0.32)
     w.extra.update(region=(22, 30, 1025, 64, 1), checkpoint_every=100, window=(750, 1500))
     return w
+
+
+def batched_case(count: int = 48, seed: int = 4, nr: int = 128, nt: int = 64,
+                 depths: Sequence[int] = (1024, 1536, 2048, 3072, 4096), npml: int = 20) -> List[Workload]:
+    """Instances of nr x nt x Nz cells of 5 mm (default 128 x 64), Nz drawn
+    uniformly from `depths`, 1500 steps, an npml-cell layer, 15 kHz axis
+    source at a depth uniform over the top 30 % of the column (below the
+    layer), cement top uniform in [0.5, 0.8] Nz, shear ramp length uniform
+    in [0.05, 0.5] m, 32 axis receivers every 20 mm below the source.  The
+    draws are made in instance order from numpy's default_rng(seed)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for q in range(count):
+        nz = int(rng.choice(list(depths)))
+        src_k = int(rng.integers(npml + 1, int(0.3 * nz)))
+        top = int(rng.uniform(0.5, 0.8) * nz)
+        ramp = float(rng.uniform(0.05, 0.5))
+        rec = [min(nz - npml - 2, src_k + 4 * (m + 1)) for m in range(32)]
+        out.append(Workload("batch instance %d: cased-well %dx%dx%d (5 mm), 1500 steps" % (q, nr, nt, nz),
+                            nr, nt, nz, 5e-3, 5e-3, steps=1500, npml=npml, f0=15e3, src_k=src_k, rec_k=rec,
+                            z_top=top * 5e-3, ramp=ramp))
+    return out
+
+
+def small_batched_case(count: int = 256, seed: int = 5) -> List[Workload]:
+    """Many small instances, where one launch per instance and step would
+    cost more than the work: 48 x 16 x Nz cells of 5 mm, Nz from
+    {256, 384, 512}, 8-cell layer; otherwise as batched_case."""
+    return batched_case(count, seed, nr=48, nt=16, depths=(256, 384, 512), npml=8)
 
 
 def scaled_case(nr: int, nt: int, nz: int, steps: int = 50) -> Workload:
