@@ -323,15 +323,17 @@ STREAM_MIX = {"velocity": ((10, 3), (9, 3)), "stress": ((11, 6), (9, 6)), "fused
 
 def stream_ceiling(kernel: str, axisym: bool, roofline: dict):
     """What HBM delivers to a kernel that only streams the dominant kernel's
-    read/write mix (1 GiB per array), and a plain 1 + 1 copy; the dominant
-    kernel's algorithmic rate as a fraction of the former."""
+    read/write mix (1 GiB per array; 16 bytes per thread and array as the
+    step kernels read, and 4), and a plain 1 + 1 copy; the dominant kernel's
+    algorithmic rate as a fraction of the 16-byte figure."""
     from paper_2302_13907_amd import cwell
     r, w = STREAM_MIX[kernel][1 if axisym else 0]
     log("stream ceiling: %d reads + %d writes" % (r, w))
     mix = cwell.stream_probe(r, w) / 1e9
+    mix4 = cwell.stream_probe(r, w, lane_bytes=4) / 1e9
     copy = cwell.stream_probe(1, 1) / 1e9
-    return {"kernel": kernel, "reads": r, "writes": w, "GBps": round(mix, 1), "copy_GBps": round(copy, 1),
-            "frac_of_ceiling": round(roofline["achieved"] / mix, 4)}
+    return {"kernel": kernel, "reads": r, "writes": w, "GBps": round(mix, 1), "GBps_4B_lanes": round(mix4, 1),
+            "copy_GBps": round(copy, 1), "frac_of_ceiling": round(roofline["achieved"] / mix, 4)}
 
 
 def graph_replay(path: str, graph: int = 20, steps: int = 300):

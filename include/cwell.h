@@ -298,14 +298,16 @@ void cw_batch_destroy(cw_batch *b);
    nread + nwrite arrays of bytes_per_array bytes each, laid out back to
    back in the caller's device buffer `dev` (16-byte aligned, at least
    (nread + nwrite) * bytes_per_array bytes; its contents are overwritten):
-   every 16-byte group of the write arrays receives the sum of the same
-   group of the read arrays.  Runs 2 untimed passes and `reps` timed ones
+   every group of the write arrays receives the sum of the same group of
+   the read arrays, one group per thread, a group being lane_bytes = 16
+   (four floats) or 4 (one float) bytes; CW_ERR_ARG for other widths.
+   Runs 2 untimed passes and `reps` timed ones
    on `stream` (a hipStream_t, NULL for the default stream), waits, and
    returns the average milliseconds per pass.  Supported (nread, nwrite):
    (1, 1), (9, 3), (10, 3), (9, 6), (11, 6), (9, 9), (12, 9) -- the stream
    mixes of the step kernels; others give CW_ERR_RANGE. */
-cw_status cw_stream_probe(void *dev, uint64_t bytes_per_array, int32_t nread, int32_t nwrite, int32_t reps,
-                          void *stream, double *ms_per_pass);
+cw_status cw_stream_probe(void *dev, uint64_t bytes_per_array, int32_t nread, int32_t nwrite, int32_t lane_bytes,
+                          int32_t reps, void *stream, double *ms_per_pass);
 
 void cw_destroy(cw_sim *s);
 const char *cw_last_error(void);

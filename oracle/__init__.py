@@ -56,6 +56,18 @@ ORACLE_PINS = {
         "tests/test_oracle_adjoint.py::test_adjoint_step_is_the_transpose",
     "gradient of the receiver loss in the cement moduli (orc_gradient)":
         "tests/test_oracle_adjoint.py::test_gradient_matches_finite_differences",
+    "refined grid (refined.py): Fourier interpolation exact on band-limited functions":
+        "tests/test_oracle_refined.py::test_interpolation_exact_on_band_limited_functions",
+    "refined grid: fine-to-coarse map is the weighted transpose of the interpolation":
+        "tests/test_oracle_refined.py::test_restriction_is_half_the_transpose",
+    "refined grid: one zone equals the uniform C oracle (independent implementation)":
+        "tests/test_oracle_refined.py::test_single_zone_matches_uniform_oracle",
+    "refined grid: energy conservation across zone interfaces":
+        "tests/test_oracle_refined.py::test_energy_conserved_across_zones",
+    "refined grid: axisymmetric solution equals the one-cell uniform grid":
+        "tests/test_oracle_refined.py::test_axisymmetric_solution_is_that_of_the_uniform_grid",
+    "refined grid: order-one wave follows the fine uniform grid":
+        "tests/test_oracle_refined.py::test_order_one_wave_close_to_the_fine_uniform_grid",
 }
 
 

@@ -1035,16 +1035,16 @@ cw_status cw_ricker(double f0, const double *t, int64_t n, double *out)
   return CW_OK;
 }
 
-cw_status cw_stream_probe(void *dev, uint64_t bytes_per_array, int32_t nread, int32_t nwrite, int32_t reps,
-                          void *stream, double *ms_per_pass)
+cw_status cw_stream_probe(void *dev, uint64_t bytes_per_array, int32_t nread, int32_t nwrite, int32_t lane_bytes,
+                          int32_t reps, void *stream, double *ms_per_pass)
 {
   if (!dev || !ms_per_pass || reps < 1) return fail(CW_ERR_ARG, "null buffer or result, or reps < 1");
+  if (lane_bytes != 4 && lane_bytes != 16) return fail(CW_ERR_ARG, "lane_bytes must be 4 or 16");
   if (((uintptr_t)dev & 15) || bytes_per_array < 16 || (bytes_per_array & 15))
     return fail(CW_ERR_ARG, "the buffer must be 16-byte aligned and each array a positive multiple of 16 bytes");
   if (!stream_mix_supported(nread, nwrite))
     return fail(CW_ERR_RANGE, "unsupported stream mix %d reads / %d writes", nread, nwrite);
   hipStream_t st = static_cast<hipStream_t>(stream);
-  const size_t n4 = bytes_per_array / 16;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   HIPCHK(hipEventCreate(&e0));
   if (hipEventCreate(&e1) != hipSuccess) {
@@ -1055,7 +1055,7 @@ cw_status cw_stream_probe(void *dev, uint64_t bytes_per_array, int32_t nread, in
   float ms = 0.0f;
   auto run = [&](int n) {
     for (int q = 0; q < n; q++)
-      if (launch_stream(dev, n4, nread, nwrite, st) != hipSuccess) return false;
+      if (launch_stream(dev, bytes_per_array, lane_bytes, nread, nwrite, st) != hipSuccess) return false;
     return true;
   };
   if (!run(2) || hipEventRecord(e0, st) != hipSuccess || !run(reps) || hipEventRecord(e1, st) != hipSuccess ||

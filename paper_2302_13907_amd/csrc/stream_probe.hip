@@ -1,37 +1,55 @@
 // Bandwidth reference for the roofline: a kernel that only streams.  Each
-// thread reads one 16-byte group from each of R arrays and writes one to
-// each of W arrays (their sum, so no read can be dropped), which is the
-// access pattern of the step kernels with the stencil taken out.  The rate
-// it reaches for a kernel's mix of read and write streams is what HBM
-// delivers for that pattern on the device at hand.
+// thread reads one group (16 bytes, or 4) from each of R arrays and writes
+// one to each of W arrays (their sum, so no read can be dropped), which is
+// the access pattern of the step kernels with the stencil taken out.  The
+// rate it reaches for a kernel's mix of read and write streams is what HBM
+// delivers for that pattern on the device at hand; the 4-byte form has four
+// times as many threads resident for the same bytes.
 #include "cwell_internal.hpp"
 
 namespace cw {
 
 namespace {
 
-template <int R, int W>
-__global__ void __launch_bounds__(256) k_stream(const float4 *base, size_t n4)
+__device__ __forceinline__ void acc(float4 &s, const float4 &v) { s.x += v.x; s.y += v.y; s.z += v.z; s.w += v.w; }
+__device__ __forceinline__ void acc(float &s, float v) { s += v; }
+__device__ __forceinline__ float4 bump(float4 s, int q) { s.x += (float)q; return s; }
+__device__ __forceinline__ float bump(float s, int q) { return s + (float)q; }
+
+template <class T, int R, int W>
+__global__ void __launch_bounds__(256) k_stream(const T *base, size_t ng)
 {
   const size_t t = (size_t)blockIdx.x * 256 + threadIdx.x;
-  if (t >= n4) return;
-  float4 s = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  if (t >= ng) return;
+  T s{};
 #pragma unroll
-  for (int q = 0; q < R; q++) {
-    const float4 v = base[(size_t)q * n4 + t];
-    s.x += v.x; s.y += v.y; s.z += v.z; s.w += v.w;
-  }
-  float4 *out = const_cast<float4 *>(base) + (size_t)R * n4;
+  for (int q = 0; q < R; q++) acc(s, base[(size_t)q * ng + t]);
+  T *out = const_cast<T *>(base) + (size_t)R * ng;
 #pragma unroll
-  for (int q = 0; q < W; q++) out[(size_t)q * n4 + t] = make_float4(s.x + q, s.y, s.z, s.w);
+  for (int q = 0; q < W; q++) out[(size_t)q * ng + t] = bump(s, q);
 }
 
-template <int R, int W>
-hipError_t launch(const float4 *base, size_t n4, hipStream_t stream)
+template <class T, int R, int W>
+hipError_t launch(const void *base, size_t bytes_per_array, hipStream_t stream)
 {
-  const size_t g = (n4 + 255) / 256;
-  hipLaunchKernelGGL((k_stream<R, W>), dim3((unsigned)g), dim3(256), 0, stream, base, n4);
+  const size_t ng = bytes_per_array / sizeof(T);
+  const size_t g = (ng + 255) / 256;
+  if (g > 0x7fffffffu) return hipErrorInvalidConfiguration;
+  hipLaunchKernelGGL((k_stream<T, R, W>), dim3((unsigned)g), dim3(256), 0, stream, static_cast<const T *>(base), ng);
   return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_mix(const void *b, size_t bytes, int r, int w, hipStream_t stream)
+{
+  if (r == 1 && w == 1) return launch<T, 1, 1>(b, bytes, stream);
+  if (r == 9 && w == 3) return launch<T, 9, 3>(b, bytes, stream);
+  if (r == 10 && w == 3) return launch<T, 10, 3>(b, bytes, stream);
+  if (r == 9 && w == 6) return launch<T, 9, 6>(b, bytes, stream);
+  if (r == 11 && w == 6) return launch<T, 11, 6>(b, bytes, stream);
+  if (r == 9 && w == 9) return launch<T, 9, 9>(b, bytes, stream);
+  if (r == 12 && w == 9) return launch<T, 12, 9>(b, bytes, stream);
+  return hipErrorInvalidValue;
 }
 
 }  // namespace
@@ -46,17 +64,10 @@ bool stream_mix_supported(int r, int w)
   return false;
 }
 
-hipError_t launch_stream(const void *base, size_t n4, int r, int w, hipStream_t stream)
+hipError_t launch_stream(const void *base, size_t bytes_per_array, int lane_bytes, int r, int w, hipStream_t stream)
 {
-  const float4 *b = static_cast<const float4 *>(base);
-  if ((size_t)((n4 + 255) / 256) > 0x7fffffffu) return hipErrorInvalidConfiguration;
-  if (r == 1 && w == 1) return launch<1, 1>(b, n4, stream);
-  if (r == 9 && w == 3) return launch<9, 3>(b, n4, stream);
-  if (r == 10 && w == 3) return launch<10, 3>(b, n4, stream);
-  if (r == 9 && w == 6) return launch<9, 6>(b, n4, stream);
-  if (r == 11 && w == 6) return launch<11, 6>(b, n4, stream);
-  if (r == 9 && w == 9) return launch<9, 9>(b, n4, stream);
-  if (r == 12 && w == 9) return launch<12, 9>(b, n4, stream);
+  if (lane_bytes == 16) return launch_mix<float4>(base, bytes_per_array, r, w, stream);
+  if (lane_bytes == 4) return launch_mix<float>(base, bytes_per_array, r, w, stream);
   return hipErrorInvalidValue;
 }
 

@@ -93,7 +93,7 @@ def load():
         "cw_set_path": [P, I32],
         "cw_set_storage": [P, I32],
         "cw_profile_read": [P, I32, DP, ctypes.POINTER(I64)],
-        "cw_stream_probe": [P, ctypes.c_uint64, I32, I32, I32, P, DP],
+        "cw_stream_probe": [P, ctypes.c_uint64, I32, I32, I32, I32, P, DP],
         "cw_set_graph": [P, I32],
         "cw_set_adjoint": [P, I64, I32, I32, I32, I32, I32, I32],
         "cw_set_region_moduli": [P, DP, DP],
@@ -141,10 +141,11 @@ def ricker(f0: float, t) -> np.ndarray:
 
 
 def stream_probe(nread: int, nwrite: int, bytes_per_array: int = 1 << 30, reps: int = 10,
-                 device: str = "cuda") -> float:
+                 device: str = "cuda", lane_bytes: int = 16) -> float:
     """Achieved bytes per second of a kernel that only streams nread arrays
     in and nwrite arrays out (the access pattern of a step kernel without
-    its stencil), on a torch-allocated buffer on the current stream."""
+    its stencil), lane_bytes (16 or 4) per thread and array, on a
+    torch-allocated buffer on the current stream."""
     import torch
     lib = load()
     n = nread + nwrite
@@ -155,7 +156,7 @@ def stream_probe(nread: int, nwrite: int, bytes_per_array: int = 1 << 30, reps: 
     stream = torch.cuda.current_stream(buf.device).cuda_stream
     ms = ctypes.c_double()
     _check(lib.cw_stream_probe(ctypes.c_void_p(ptr), int(bytes_per_array), int(nread), int(nwrite),
-                               int(reps), ctypes.c_void_p(stream), ctypes.byref(ms)))
+                               int(lane_bytes), int(reps), ctypes.c_void_p(stream), ctypes.byref(ms)))
     del buf
     return n * bytes_per_array / (ms.value * 1e-3)
 

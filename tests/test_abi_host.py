@@ -118,11 +118,13 @@ def test_stream_probe_validation():
     """The bandwidth reference rejects bad arguments before touching the device."""
     lib = cwell.load()
     ms = ctypes.c_double()
-    assert lib.cw_stream_probe(None, 1 << 20, 9, 3, 1, None, ctypes.byref(ms)) == -1
-    assert lib.cw_stream_probe(ctypes.c_void_p(4096 + 8), 1 << 20, 9, 3, 1, None, ctypes.byref(ms)) == -1
-    assert lib.cw_stream_probe(ctypes.c_void_p(4096), 1000, 9, 3, 1, None, ctypes.byref(ms)) == -1
-    assert lib.cw_stream_probe(ctypes.c_void_p(4096), 1 << 20, 9, 3, 0, None, ctypes.byref(ms)) == -1
-    assert lib.cw_stream_probe(ctypes.c_void_p(4096), 1 << 20, 7, 2, 1, None, ctypes.byref(ms)) == -2
+    assert lib.cw_stream_probe(None, 1 << 20, 9, 3, 16, 1, None, ctypes.byref(ms)) == -1
+    assert lib.cw_stream_probe(ctypes.c_void_p(4096 + 8), 1 << 20, 9, 3, 16, 1, None, ctypes.byref(ms)) == -1
+    assert lib.cw_stream_probe(ctypes.c_void_p(4096), 1000, 9, 3, 16, 1, None, ctypes.byref(ms)) == -1
+    assert lib.cw_stream_probe(ctypes.c_void_p(4096), 1 << 20, 9, 3, 16, 0, None, ctypes.byref(ms)) == -1
+    assert lib.cw_stream_probe(ctypes.c_void_p(4096), 1 << 20, 9, 3, 8, 1, None, ctypes.byref(ms)) == -1
+    assert b"lane_bytes" in lib.cw_last_error()
+    assert lib.cw_stream_probe(ctypes.c_void_p(4096), 1 << 20, 7, 2, 4, 1, None, ctypes.byref(ms)) == -2
     assert b"7 reads" in lib.cw_last_error()
 
 

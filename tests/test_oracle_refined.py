@@ -1,0 +1,222 @@
+"""Pins of the refined-grid oracle (Sec. 3: azimuthal refinement with Fourier
+interpolation between the zones), against what mathematics fixes and against
+the independent uniform-grid C oracle."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import refined as R
+from paper_2302_13907_amd import inputs
+
+
+def _trig(rng, nc):
+    """A random real trigonometric polynomial of degree < nc / 2."""
+    M = (nc - 1) // 2
+    a, b = rng.standard_normal(M + 1), rng.standard_normal(M + 1)
+
+    def f(th):
+        s = a[0] * np.ones_like(th)
+        for m in range(1, M + 1):
+            s = s + a[m] * np.cos(m * th) + b[m] * np.sin(m * th)
+        return s
+    return f
+
+
+@pytest.mark.parametrize("nc", [1, 2, 3, 4, 8, 16, 64])
+@pytest.mark.parametrize("half", [False, True])
+def test_interpolation_exact_on_band_limited_functions(nc, half):
+    """Both directions reproduce every trigonometric polynomial the coarse
+    grid resolves, on integer and on half-integer nodes."""
+    rng = np.random.default_rng(nc + 100 * half)
+    f = _trig(rng, nc)
+    s = 0.5 if half else 0.0
+    nf = 2 * nc
+    x = f((np.arange(nc) + s) * 2 * math.pi / nc)[:, None] * np.ones((1, 3))
+    y = f((np.arange(nf) + s) * 2 * math.pi / nf)[:, None] * np.ones((1, 3))
+    scale = np.abs(y).max()
+    assert np.abs(R.prolong(x, nf, half) - y).max() <= 1e-13 * scale
+    assert np.abs(R.restrict(y, nc, half) - x).max() <= 1e-13 * scale
+
+
+def test_coarse_nyquist_mode_is_kept_on_integer_nodes():
+    """cos(N theta / 2) alternates sign on the coarse integer nodes; the fine
+    samples of its split interpolant are the same cosine."""
+    nc = 8
+    th_c = np.arange(nc) * 2 * math.pi / nc
+    th_f = np.arange(2 * nc) * math.pi / nc
+    x = np.cos(nc / 2 * th_c)[:, None]
+    assert np.allclose(R.prolong(x, 2 * nc, False)[:, 0], np.cos(nc / 2 * th_f), atol=1e-14)
+
+
+@pytest.mark.parametrize("nc", [1, 2, 3, 6, 8])
+@pytest.mark.parametrize("half", [False, True])
+def test_restriction_is_half_the_transpose(nc, half):
+    """R = (1/2) P^T: the fine-to-coarse map is the transpose of the paper's
+    coarse-to-fine interpolation weighted by dtheta_fine / dtheta_coarse."""
+    nf = 2 * nc
+    P = np.stack([R.prolong(np.eye(nc)[:, [j]], nf, half)[:, 0] for j in range(nc)], axis=1)
+    Rm = np.stack([R.restrict(np.eye(nf)[:, [j]], nc, half)[:, 0] for j in range(nf)], axis=1)
+    assert np.abs(Rm - 0.5 * P.T).max() <= 1e-15
+
+
+def _well_rz(nr, nz, h):
+    rho, lam, mu = inputs.cased_well(nr, 1, nz, h, h, z_top=nz * h / 2, ramp=0.02, radii=(0.02, 0.03, 0.045))
+    return [a[:, 0, :] for a in (rho, lam, mu)]
+
+
+def test_single_zone_matches_uniform_oracle():
+    """One zone is the uniform scheme: the numpy oracle and the C oracle (two
+    independent implementations) agree to rounding, with the layer and every
+    source kind."""
+    nr, nt, nz, h = 12, 8, 40, 5e-3
+    rz = _well_rz(nr, nz, h)
+    o = oracle.OracleSim(nr, nt, nz, h, h)
+    o.set_material(*[np.repeat(a[:, None, :], nt, axis=1) for a in rz])
+    o.set_pml(3, 4, 1e-3, math.pi * 40e3)
+    dt = 0.5 * o.cfl_dt()
+    o.set_dt(dt)
+    r = R.RefinedOracle(nr, nz, h, h, [(0, nt)])
+    r.set_material_rz(*rz)
+    r.set_pml(3, 4, 1e-3, math.pi * 40e3)
+    r.set_dt(dt)
+    assert r.cfl_dt() == pytest.approx(o.cfl_dt(), rel=1e-14)
+    w = oracle.ricker(40e3, (np.arange(80) + 0.5) * dt)
+    for sim in (o, r):
+        sim.add_source("volume", 0, -1, 10, w)
+        sim.add_source("force_r", 3, 2, 20, w)
+        sim.add_source("force_z", 2, 5, 15, w)
+        sim.add_source("torsion", 4, -1, 25, w)
+        sim.add_receiver("pressure", 0, -1, 12)
+        sim.add_receiver("field", 5, 3, 18, "vt")
+    to, tr = o.run(80), r.run(80)
+    assert np.abs(to - tr).max() <= 1e-12 * np.abs(to).max()
+    for name in R.FIELDS:
+        a, b = o.field(name).reshape(-1), r.field(name)
+        assert np.abs(a - b).max() <= 1e-12 * np.abs(a).max(), name
+
+
+def _isotropic_state(r, seed):
+    """Random state whose fluid cells hold isotropic stress and no shear
+    stress where the shear modulus is zero (the energy counts only these)."""
+    rng = np.random.default_rng(seed)
+    for i in range(r.nr):
+        sh = (r.nt[i], r.nz)
+        fluid = (r.mu[i] == 0)[None, :]
+        p = rng.standard_normal(sh)
+        for name in ("srr", "stt", "szz"):
+            r.f[name][i] = np.where(fluid, p, rng.standard_normal(sh))
+        for name, c in (("srt", r.mu_rt), ("srz", r.mu_rz), ("stz", r.mu_tz)):
+            r.f[name][i] = np.where((c[i] > 0)[None, :], rng.standard_normal(sh), 0.0)
+        for name in ("vr", "vt", "vz"):
+            r.f[name][i] = 1e-6 * rng.standard_normal(sh)
+
+
+@pytest.mark.parametrize("zones", [[(0, 4), (3, 8)], [(0, 2), (2, 4), (5, 8)], [(0, 3), (4, 6)], [(0, 1), (1, 2), (3, 4)]])
+def test_energy_conserved_across_zones(zones):
+    """Layer off, no source, random heterogeneous medium with a fluid core:
+    the leapfrog energy stays constant to rounding across the zone
+    interfaces (the interpolation pair is the weighted transpose pair)."""
+    nr, nz = 10, 12
+    rng = np.random.default_rng(3)
+    rho = rng.uniform(1000, 8000, (nr, nz))
+    mu = rng.uniform(5e9, 8e10, (nr, nz))
+    lam = rng.uniform(1e9, 1e11, (nr, nz))
+    mu[:2], lam[:2], rho[:2] = 0.0, 2.25e9, 1000.0
+    r = R.RefinedOracle(nr, nz, 0.01, 0.01, zones)
+    r.set_material_rz(rho, lam, mu)
+    r.set_dt(0.5 * r.cfl_dt())
+    _isotropic_state(r, 4)
+    before = r.field("vt")
+    _, E = r.run(400, energy=True)
+    assert np.abs(E / E[0] - 1).max() <= 1e-12
+    # the state really moved
+    assert np.abs(r.field("vt") - before).max() > 0.5 * np.abs(before).max()
+
+
+def test_axisymmetric_solution_is_that_of_the_uniform_grid():
+    """A ring source in an axisymmetric medium: every zone's fields stay
+    theta-invariant and equal those of the uniform C oracle with one
+    azimuthal cell (interpolation of a constant is the constant)."""
+    nr, nz, h = 16, 48, 5e-3
+    rz = _well_rz(nr, nz, h)
+    zones = [(0, 2), (3, 4), (7, 8)]
+    r = R.RefinedOracle(nr, nz, h, h, zones)
+    r.set_material_rz(*rz)
+    r.set_pml(4, 5, 1e-3, math.pi * 40e3)
+    o = oracle.OracleSim(nr, 1, nz, h, h)
+    o.set_material(*[a[:, None, :] for a in rz])
+    o.set_pml(4, 5, 1e-3, math.pi * 40e3)
+    dt = 0.5 * r.cfl_dt()
+    r.set_dt(dt)
+    o.set_dt(dt)
+    w = oracle.ricker(40e3, (np.arange(120) + 0.5) * dt)
+    for sim in (o, r):
+        sim.add_source("volume", 0, -1, 20, 1e6 * w)
+        sim.add_receiver("pressure", 0, -1, 24)
+        sim.add_receiver("pressure", 9, -1, 30)
+    to, tr = o.run(120), r.run(120)
+    assert np.abs(to - tr).max() <= 1e-11 * np.abs(to).max()
+    u = o.field("vz").reshape(nr, nz)
+    for i in range(nr):
+        ring = r.ring("vz", i)
+        assert np.abs(ring - u[i][None, :]).max() <= 1e-11 * np.abs(u).max()
+    assert max(np.abs(a).max() for a in r.f["vt"]) == 0.0
+
+
+def test_order_one_wave_close_to_the_fine_uniform_grid():
+    """A smooth initial radial velocity of azimuthal order 1 near the axis
+    (g(r, z) cos theta): the refined grid, twice coarser in theta next to
+    the axis, follows the uniform grid with the finest resolution everywhere
+    to a few percent (the coarse zone's theta difference is less accurate);
+    a wrong interface phase or weight would not."""
+    nr, nz, h = 16, 48, 5e-3
+    rz = _well_rz(nr, nz, h)
+    nt = 16
+    r = R.RefinedOracle(nr, nz, h, h, [(0, 8), (6, 16)])
+    o = oracle.OracleSim(nr, nt, nz, h, h)
+    r.set_material_rz(*rz)
+    o.set_material(*[np.repeat(a[:, None, :], nt, axis=1) for a in rz])
+    dt = 0.5 * o.cfl_dt()
+    r.set_dt(dt)
+    o.set_dt(dt)
+    Rf = (np.arange(nr) + 1.0) * h                  # v_r sits at R_i, theta_j, z_k
+    z = np.arange(nz) * h
+    g = np.exp(-(((Rf[:, None] - 0.015) ** 2 + (z[None, :] - 0.12) ** 2) / 0.008 ** 2))
+    o.set_field("vr", g[:, None, :] * np.cos(np.arange(nt) * 2 * math.pi / nt)[None, :, None])
+    r.set_field("vr", np.concatenate([(g[i][None, :] * np.cos(np.arange(r.nt[i]) * 2 * math.pi / r.nt[i])[:, None]).reshape(-1)
+                                      for i in range(nr)]))
+    for i, k in ((10, 24), (12, 30), (4, 22), (7, 26)):
+        r.add_receiver("field", i, 0, k, "vr")
+        o.add_receiver("field", i, 0, k, "vr")
+    to, tr = o.run(150), r.run(150)
+    rel = np.linalg.norm(to - tr) / np.linalg.norm(to)
+    assert rel < 0.05, rel
+
+
+def test_zone_plan_doubles_with_radius():
+    """Zones halve the azimuthal step each time the radius doubles, keeping
+    the outer resolution: at 256 rings of 2 mm, 4 cells below 16 mm, 8 up to
+    32 mm, ..., 128 from 256 mm."""
+    zones = R.zone_plan(256, 128, 4, 2e-3)
+    assert zones == [(0, 4), (8, 8), (16, 16), (32, 32), (64, 64), (128, 128)]
+    for nr in (20, 37, 100):
+        z = R.zone_plan(nr, 64, 8, 5e-3)
+        assert z[0][0] == 0 and z[-1][1] == 64
+        for (a0, n0), (a1, n1) in zip(z, z[1:]):
+            assert n1 == 2 * n0 and a1 > a0
+            assert (a1 + 0.5) * 5e-3 >= nr * 5e-3 / 2 ** (len(z) - z.index((a1, n1)))
+
+
+def test_refinement_relaxes_the_courant_limit():
+    """Coarser azimuthal steps near the axis lift the axis-limited time step
+    (the production medium at 2 mm: uniform 128 vs zones from 4 to 128)."""
+    nr, nz, h = 256, 8, 2e-3
+    rz = [a[:, 0, :] for a in inputs.cased_well(nr, 1, nz, h, h, z_top=0.0)]
+    uni = R.RefinedOracle(nr, nz, h, h, [(0, 128)])
+    ref = R.RefinedOracle(nr, nz, h, h, R.zone_plan(nr, 128, 4, h))
+    for s in (uni, ref):
+        s.set_material_rz(*rz)
+    assert ref.cfl_dt() / uni.cfl_dt() > 5.0
+    assert ref.cells < 0.7 * uni.cells
