@@ -92,7 +92,7 @@ PROFILE_VARIANTS = {
     "march_f32": "--path march --storage f32",
 }
 PROFILE_RUN = ("python3 -u bench.py --steps 20 --warmup 5 --no-cpu-baseline --no-storage-forms --no-stream-ceiling "
-               "--no-graph-replay --no-adjoint --no-batched --copy-gib 1")
+               "--no-graph-replay --no-adjoint --no-batched --no-refined --copy-gib 1")
 PROFILE_PASSES = (
     ("stats", "--kernel-trace --stats"),
     ("fetch", "--pmc FETCH_SIZE"),
@@ -453,6 +453,57 @@ def batched_form(small: bool = False, steps: int = 40, graph: int = 20):
             "tiles": {str(ws[q].nz): tz for q, tz in sorted(tiles.items())}}
 
 
+def refined_form(uniform_ms: float, warmup: int = 10, steps: int = 100):
+    """The production workload on the azimuthally refined grid (4 azimuthal
+    cells next to the axis doubling with the radius up to 128): Gcell-
+    updates/s of its own cells, its time step against the uniform grid's,
+    and the physical time simulated per second of wall time, against the
+    uniform grid's (uniform_ms: its measured milliseconds per step)."""
+    import numpy as np
+    import torch
+    from paper_2302_13907_amd import cwell, inputs
+    w = inputs.refined_production_case()
+    zones = w.extra["zones"]
+    log("refined form: %d zones %s" % (len(zones), zones))
+    u = cwell.Sim(w.nr, w.nt, w.nz, w.dr, w.dz)          # host-side only: the uniform Courant limit
+    u.set_material(*w.medium_rz())
+    dt_uni = w.cfl_fraction * u.cfl_dt()
+    u.close()
+    r = cwell.Refined(w.nr, w.nz, w.dr, w.dz, zones)
+    r.set_material_rz(*w.medium_rz())
+    r.set_pml(w.npml, w.npml, w.pml_rc, math.pi * w.f0)
+    dt = w.cfl_fraction * r.cfl_dt()
+    r.set_dt(dt)
+    total = warmup + steps
+    r.add_source("volume", 0, -1, w.src_k, cwell.ricker(w.f0, (np.arange(total) + 0.5) * dt))
+    for k in w.rec_k:
+        r.add_receiver("pressure", 0, -1, k)
+    r.set_trace_capacity(total)
+    r.bind("cuda:0")
+    r.step(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r.step(steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    tr = r.traces(total)
+    r.close()
+    del r
+    torch.cuda.empty_cache()
+    if not np.all(np.isfinite(tr)):
+        raise RuntimeError("non-finite traces on the refined grid")
+    ms = el / steps * 1e3
+    cells = sum((b - a) * n for (a, n), (b, _) in zip(zones, zones[1:] + [(w.nr, 0)])) * w.nz
+    us_per_s = lambda d, m: d * 1e6 / (m * 1e-3)          # simulated microseconds per wall second
+    return {"workload": w.name, "zones": [list(z) for z in zones], "cells": cells,
+            "cells_uniform": w.cells, "steps": steps, "ms_per_step": round(ms, 4),
+            "value": round(cells * steps / el / 1e9, 3), "unit": "Gcell-updates/s",
+            "dt": dt, "dt_uniform": dt_uni, "dt_ratio": round(dt / dt_uni, 3),
+            "sim_us_per_s": round(us_per_s(dt, ms), 2),
+            "sim_us_per_s_uniform": round(us_per_s(dt_uni, uniform_ms), 2),
+            "time_to_solution_speedup": round(us_per_s(dt, ms) / us_per_s(dt_uni, uniform_ms), 3)}
+
+
 def storage_forms(path: str, warmup: int = 10, steps: int = 100):
     """Gcell-updates/s of the mixed-precision workload with float32, float16
     and bfloat16 field storage (float32 arithmetic in every case)."""
@@ -489,6 +540,8 @@ def main():
                          "192 x 96 x 4096 mixed-precision workload")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched-form measurements (48 uneven large and 256 uneven small instances)")
+    ap.add_argument("--no-refined", action="store_true",
+                    help="skip the azimuthally refined grid (production workload, zones of 4..128 cells)")
     ap.add_argument("--no-adjoint", action="store_true",
                     help="skip the seconds-per-adjoint-gradient measurement")
     ap.add_argument("--no-graph-replay", action="store_true",
@@ -589,6 +642,8 @@ def main():
         out["adjoint"] = adjoint_gradient()
     if not args.no_batched:
         out["batched"] = [batched_form(), batched_form(small=True)]
+    if not args.no_refined:
+        out["refined"] = refined_form(out["ms_per_step"] if args.workload == "production" else float("nan"))
     if not args.no_cpu_baseline:
         log("CPU baseline: FP64 oracle for about %.0f s" % args.cpu_seconds)
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)

@@ -294,6 +294,54 @@ cw_status cw_batch_set_graph(cw_batch *b, int32_t steps);
 cw_status cw_batch_step(cw_batch *b, int64_t nsteps);
 void cw_batch_destroy(cw_batch *b);
 
+/* Azimuthally refined grid (Sec. 3).  The rings are split into zones;
+   zone q holds rings [first_ring[q], first_ring[q + 1]) (the last zone up
+   to nr) with ntheta[q] azimuthal cells, ntheta doubling from one zone to
+   the next (the paper halves the azimuthal step each time the radius
+   doubles, which keeps r dtheta bounded and lifts the axis-limited Courant
+   step).  Within a zone the scheme is the uniform one.  Across the circle
+   between two zones each side's stencils read the other side's edge ring
+   on their own azimuthal grid: coarse -> fine by trigonometric
+   interpolation (the Fourier transform of the coarse ring, padded with
+   zeros, transformed back; the coarse Nyquist mode split evenly between
+   +n/2 and -n/2; half-integer nodes shifted in phase), fine -> coarse by
+   the transpose of that map times dtheta_fine / dtheta_coarse (which keeps
+   the scheme's energy conserved).
+   cw_refined_create: grid->ntheta must equal the outermost zone's ntheta
+   (at most 640), nz a multiple of 4, first_ring[0] = 0, first rings
+   increasing and below nr; CW_ERR_RANGE otherwise.  The medium must not
+   vary along theta (cw_refined_set_material_rz, [nr][nz] float64).  The
+   radial absorbing layer must lie inside the outermost zone.  Sources and
+   receivers take a global ring i and an azimuthal index j of that ring's
+   own grid (-1: the whole ring).  Fields are exchanged as the rings
+   concatenated, ring 0 first, ring i holding ntheta_i x nz float32 values
+   (cw_refined_cells of them).  Traces are [receiver][cap] as cw_get_traces.
+   Float32 storage; the zones are stepped as one batch (one velocity and one
+   stress launch per step) with one interpolation launch before each of
+   them.  One workspace, one stream, as cw_bind. */
+typedef struct cw_refined cw_refined;
+cw_status cw_refined_create(const cw_grid *g, int32_t nzones, const int32_t *first_ring, const int32_t *ntheta,
+                            cw_refined **out);
+cw_status cw_refined_cells(const cw_refined *r, uint64_t *cells);
+cw_status cw_refined_set_material_rz(cw_refined *r, const double *rho, const double *lam, const double *mu);
+cw_status cw_refined_set_pml(cw_refined *r, int32_t npml_r, int32_t npml_z, double rc, double alpha);
+cw_status cw_refined_cfl_dt(const cw_refined *r, double *dt_cfl);
+cw_status cw_refined_set_dt(cw_refined *r, double dt);
+cw_status cw_refined_add_source(cw_refined *r, int32_t kind, int32_t i, int32_t j, int32_t k, const double *w,
+                                int64_t n);
+cw_status cw_refined_add_receiver(cw_refined *r, int32_t kind, int32_t field, int32_t i, int32_t j, int32_t k,
+                                  int32_t *id);
+cw_status cw_refined_set_trace_capacity(cw_refined *r, int64_t nsteps);
+cw_status cw_refined_workspace_bytes(const cw_refined *r, uint64_t *bytes);
+cw_status cw_refined_bind(cw_refined *r, void *workspace, uint64_t bytes, void *stream);
+cw_status cw_refined_step(cw_refined *r, int64_t nsteps);
+cw_status cw_refined_get_field(cw_refined *r, int32_t field, float *host_out);
+cw_status cw_refined_set_field(cw_refined *r, int32_t field, const float *host_in);
+cw_status cw_refined_get_traces(cw_refined *r, double *out, int64_t cap, int64_t *nsteps_done);
+cw_status cw_refined_energy(cw_refined *r, double *E);
+cw_status cw_refined_reset(cw_refined *r);
+void cw_refined_destroy(cw_refined *r);
+
 /* Bandwidth reference (measurement only, not part of the scheme): stream
    nread + nwrite arrays of bytes_per_array bytes each, laid out back to
    back in the caller's device buffer `dev` (16-byte aligned, at least

@@ -123,27 +123,21 @@ def zone_plan(nr: int, ntheta_outer: int, ntheta_inner: int, dr: float):
     (ntheta_inner doubling up to ntheta_outer), zone Q-1 holds the rings
     whose centre radius lies in [r_max / 2, r_max), zone Q-2 those in
     [r_max / 4, r_max / 2), ..., zone 0 every ring below r_max / 2^(Q-1).
-    Zones that would hold no ring are dropped (the next one inwards keeps
-    its doubling).  Returns [(first_ring, ntheta), ...]."""
+    A zone that would hold no ring is left out; the cell counts then halve
+    inwards from the outermost zone, one halving per zone kept.  Returns
+    [(first_ring, ntheta), ...]."""
     q_count = int(round(math.log2(ntheta_outer / ntheta_inner))) + 1
     if ntheta_inner < 1 or ntheta_inner * 2 ** (q_count - 1) != ntheta_outer:
         raise ValueError("ntheta_outer / ntheta_inner must be a power of two")
     r_max = nr * dr
-    rc = (np.arange(nr) + 0.5) * dr
-    out = []
-    for q in range(q_count):
-        lo = 0.0 if q == 0 else r_max / 2 ** (q_count - q)
-        first = int(np.searchsorted(rc, lo, side="left"))
-        if first >= nr or (out and first <= out[-1][0]):
-            continue
-        out.append((first, ntheta_outer // 2 ** (q_count - 1 - q)))
-    if out[0][0] != 0:
-        out[0] = (0, out[0][1])
-    # consecutive zones must double: drop inner zones that lost their neighbour
-    while len(out) > 1 and any(b[1] != 2 * a[1] for a, b in zip(out, out[1:])):
-        k = next(i for i, (a, b) in enumerate(zip(out, out[1:])) if b[1] != 2 * a[1])
-        out = [(0, out[k + 1][1] // 2)] + out[k + 1:] if k == 0 else out[:k] + out[k + 1:]
-    return out
+    starts = [0]
+    for q in range(1, q_count):
+        edge = r_max / 2 ** (q_count - q)
+        first = next((i for i in range(nr) if (i + 0.5) * dr >= edge), nr)
+        if first < nr and first > starts[-1]:
+            starts.append(first)
+    n = len(starts)
+    return [(starts[q], ntheta_outer // 2 ** (n - 1 - q)) for q in range(n)]
 
 
 class RefinedOracle:

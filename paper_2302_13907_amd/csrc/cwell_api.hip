@@ -61,6 +61,15 @@ struct cw_sim {
   int nr = 0, nt = 0, nz = 0;
   double dr = 0, dz = 0, dth = 0;
   size_t n = 0;
+  // a zone of an azimuthally refined grid (cw_refined_*): global index of
+  // ring 0, ghost rings around the field arrays, medium rings stored beyond
+  // the last one (the next zone's first), and the speed that sets the
+  // absorbing profile (that of the whole grid; 0: this medium's own)
+  int ring0 = 0;
+  bool ghost_in = false, ghost_out = false;
+  int med_extra = 0;
+  double vp_ref = 0;
+  size_t n_alloc() const { return (size_t)(nr + ghost_in + ghost_out) * nt * nz; }
   // medium (float32 copies, uploaded at bind) and what the setup derives from it
   std::vector<float> rho, lam, mu;
   bool have_material = false;
@@ -212,7 +221,7 @@ Layout layout(const cw_sim *s)
   Layout L{};
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off += align256(bytes); return o; };
-  L.fields = take(2 * NF * s->n * field_bytes(s));
+  L.fields = take(2 * NF * s->n_alloc() * field_bytes(s));
   L.material = take(3 * s->nm * sizeof(float));
   L.metric = take(2 * (size_t)s->nr * sizeof(float));
   L.tabr = take(NTAB_R * (size_t)s->nr * sizeof(float));
@@ -238,7 +247,7 @@ double courant(const cw_sim *s, const double *rho, const double *lam, const doub
   double best = INFINITY;
   const size_t per_ring = rz_only ? (size_t)s->nz : (size_t)s->nt * s->nz;
   for (int i = 0; i < s->nr; i++) {
-    const double ra = (i + 0.5) * s->dr * s->dth;
+    const double ra = (s->ring0 + i + 0.5) * s->dr * s->dth;
     const double g = std::sqrt(1.0 / (s->dr * s->dr) + 1.0 / (ra * ra) + 1.0 / (s->dz * s->dz));
     double vmax = 0;
     for (size_t c = 0; c < per_ring; c++) {
@@ -274,18 +283,19 @@ void build_tables(cw_sim *s)
   s->inv_rc.resize(s->nr);
   s->inv_rf.resize(s->nr);
   for (int i = 0; i < s->nr; i++) {
-    s->inv_rc[i] = (float)(1.0 / ((i + 0.5) * s->dr));
-    s->inv_rf[i] = (float)(1.0 / ((i + 1.0) * s->dr));
+    s->inv_rc[i] = (float)(1.0 / ((s->ring0 + i + 0.5) * s->dr));
+    s->inv_rf[i] = (float)(1.0 / ((s->ring0 + i + 1.0) * s->dr));
   }
   s->tab_r.assign(NTAB_R * (size_t)s->nr, 0.0f);
   s->tab_z.assign(NTAB_Z * (size_t)s->nz, 0.0f);
   const double Lr = s->npr * s->dr, Lz = s->npz * s->dz;
-  const double d0r = s->npr > 0 ? -3.0 * s->vp_max * std::log(s->rc) / (2.0 * Lr) : 0.0;
-  const double d0z = s->npz > 0 ? -3.0 * s->vp_max * std::log(s->rc) / (2.0 * Lz) : 0.0;
-  const double r0 = (s->nr - s->npr) * s->dr;   // inner edge of the radial layer
+  const double vp = s->vp_ref > 0 ? s->vp_ref : s->vp_max;
+  const double d0r = s->npr > 0 ? -3.0 * vp * std::log(s->rc) / (2.0 * Lr) : 0.0;
+  const double d0z = s->npz > 0 ? -3.0 * vp * std::log(s->rc) / (2.0 * Lz) : 0.0;
+  const double r0 = (s->ring0 + s->nr - s->npr) * s->dr;   // inner edge of the radial layer
   for (int i = 0; i < s->nr; i++) {
     for (int face = 0; face < 2; face++) {
-      const double r = (i + (face ? 1.0 : 0.5)) * s->dr;
+      const double r = (s->ring0 + i + (face ? 1.0 : 0.5)) * s->dr;
       const double x = (s->npr > 0 && r > r0) ? (r - r0) / Lr : 0.0;
       const double d = d0r * x * x;                       // radial profile
       const double dint = s->npr > 0 ? d0r * Lr * x * x * x / (3.0 * r) : 0.0;  // (1/r) * integral of d
@@ -319,6 +329,10 @@ StepArgs step_args(const cw_sim *s, int in, int out)
 {
   StepArgs a{};
   a.nr = s->nr; a.nt = s->nt; a.nz = s->nz;
+  a.ring0 = s->ring0;
+  a.m_last = s->nr - 1 + s->med_extra;
+  a.ghost_in = s->ghost_in;
+  a.ghost_out = s->ghost_out;
   a.npr = s->npr; a.npz = s->npz; a.nzs = nzs_of(s);
   a.dt = (float)s->dt;
   a.inv_dr = (float)(1.0 / s->dr);
@@ -369,7 +383,7 @@ cw_status timed(cw_sim *s, int kernel, F &&fn)
 cw_status zero_state(cw_sim *s)
 {
   const Layout L = layout(s);
-  HIPCHK(hipMemsetAsync(s->ws + L.fields, 0, 2 * NF * s->n * field_bytes(s), s->stream));
+  HIPCHK(hipMemsetAsync(s->ws + L.fields, 0, 2 * NF * s->n_alloc() * field_bytes(s), s->stream));
   // every scale 1, no maxima yet (pageable source: the caller synchronizes)
   static const float ones[3 * NF] = {1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1,
                                      1, 1, 1, 1, 1, 1, 1, 1, 1};
@@ -423,7 +437,9 @@ static cw_status set_medium(cw_sim *s, const double *rho, const double *lam, con
   cw_status st;
   if (!configurable(s, &st)) return st;
   if (!rho || !lam || !mu) return fail(CW_ERR_ARG, "null medium array");
-  const size_t nin = rz ? (size_t)s->nr * s->nz : s->n;
+  if (s->med_extra && !rz) return fail(CW_ERR_ARG, "a zone takes an axisymmetric medium");
+  const int mrings = s->nr + s->med_extra;
+  const size_t nin = rz ? (size_t)mrings * s->nz : s->n;
   if ((st = check_medium(nin, rho, lam, mu)) != CW_OK) return st;
   // a 3-D medium identical along theta (bitwise) is stored like an axisymmetric one:
   // the kernels then read [nr][nz] tables, which stay in cache, instead of full arrays
@@ -440,7 +456,7 @@ static cw_status set_medium(cw_sim *s, const double *rho, const double *lam, con
           }
       }
   }
-  const size_t nm = axisym ? (size_t)s->nr * s->nz : s->n;
+  const size_t nm = axisym ? (size_t)mrings * s->nz : s->n;
   try {
     s->rho.assign(nm, 0.0f); s->lam.assign(nm, 0.0f); s->mu.assign(nm, 0.0f);
   } catch (...) {
@@ -451,7 +467,7 @@ static cw_status set_medium(cw_sim *s, const double *rho, const double *lam, con
   // source row: the input's (i, 0, k) for an axisymmetric store (rz input: (i, k))
   const int nrow = axisym ? 1 : s->nt;
   const size_t in_ring = rz ? (size_t)s->nz : (size_t)s->nt * s->nz;
-  for (int i = 0; i < s->nr; i++)
+  for (int i = 0; i < mrings; i++)
     for (int j = 0; j < nrow; j++) {
       const size_t dst = ((size_t)i * nrow + j) * s->nz;
       const size_t src = (size_t)i * in_ring + (size_t)j * s->nz;
@@ -588,7 +604,8 @@ cw_status cw_bind(cw_sim *s, void *workspace, uint64_t bytes, void *stream)
   char *w = s->ws;
   for (int b = 0; b < 2; b++)
     for (int q = 0; q < NF; q++)
-      s->fields[b][q] = (float *)(w + L.fields + ((size_t)b * NF + q) * s->n * field_bytes(s));
+      s->fields[b][q] = (float *)(w + L.fields + (((size_t)b * NF + q) * s->n_alloc() +
+                                                  (s->ghost_in ? (size_t)s->nt * s->nz : 0)) * field_bytes(s));
   s->d_scl = (float *)(w + L.scales);
   s->d_maxabs = (unsigned *)(s->d_scl + 3 * NF);
   s->d_rho = (float *)(w + L.material);
@@ -643,7 +660,7 @@ cw_status cw_bind(cw_sim *s, void *workspace, uint64_t bytes, void *stream)
     case CW_SRC_FORCE_Z: targets = {{VZ, false}}; phase = 0; break;
     }
     for (const T &t : targets) {
-      const double rad = (src.i + (t.face ? 1.0 : 0.5)) * s->dr;
+      const double rad = (s->ring0 + src.i + (t.face ? 1.0 : 0.5)) * s->dr;
       const double vol = src.j < 0 ? 2.0 * kPi * rad * s->dr * s->dz : rad * s->dr * s->dth * s->dz;
       double scale = 1.0;
       if (t.field == VR || t.field == VZ) {
@@ -651,7 +668,7 @@ cw_status cw_bind(cw_sim *s, void *workspace, uint64_t bytes, void *stream)
         // a ring source takes the ring's first cell, the medium being that of the caller
         const int jj = src.j < 0 ? 0 : src.j;
         const size_t p = mat_index(s, src.i, jj, src.k);
-        const int i1 = std::min(src.i + 1, s->nr - 1), k1 = std::min(src.k + 1, s->nz - 1);
+        const int i1 = std::min(src.i + 1, s->nr - 1 + s->med_extra), k1 = std::min(src.k + 1, s->nz - 1);
         const size_t p1 = t.field == VR ? mat_index(s, i1, jj, src.k) : mat_index(s, src.i, jj, k1);
         scale = 2.0 / ((double)s->rho[p] + (double)s->rho[p1]);
       }
@@ -1470,6 +1487,426 @@ cw_status cw_batch_step(cw_batch *b, int64_t nsteps)
     if ((st = batch_launches(b, parity, b->stream)) != CW_OK) return st;
     done++;
     advance(1);
+  }
+  return CW_OK;
+}
+
+
+// ---------------------------------------------------------------------------
+// Azimuthally refined grid (Sec. 3): zones of rings whose azimuthal cell
+// count doubles from one zone to the next.  Each zone is a simulation of its
+// own (ring offset, ghost rings, the next zone's first medium ring); one
+// batch steps them together, and before each half step a transfer launch
+// fills every ghost ring with the neighbouring zone's edge ring on the
+// zone's own azimuthal grid.
+
+struct cw_refined {
+  int nr = 0, nz = 0;
+  double dr = 0, dz = 0;
+  std::vector<int> first, nth;               // zone q: rings [first[q], first[q + 1]), nth[q] cells
+  std::vector<cw_sim *> zones;
+  cw_batch *batch = nullptr;
+  std::vector<std::pair<int, int>> rec;      // receiver id -> (zone, id in the zone)
+  bool bound = false;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  Transfer *d_tr[2][2] = {};                 // [parity][0: before the velocity, 1: before the stress update]
+  int ntr[2][2] = {};
+  float *d_mat = nullptr;
+  int max_ns = 1;
+  ~cw_refined()
+  {
+    delete batch;
+    for (cw_sim *z : zones) delete z;
+  }
+  int zone_of(int i) const
+  {
+    int q = 0;
+    while (q + 1 < (int)first.size() && first[q + 1] <= i) q++;
+    return q;
+  }
+  int rings(int q) const { return (q + 1 < (int)first.size() ? first[q + 1] : nr) - first[q]; }
+};
+
+namespace {
+
+// Trigonometric interpolation kernel of n equispaced samples (the even-n
+// Nyquist mode split evenly between +n/2 and -n/2): the interpolant through
+// samples x_j at t_j is sum_j x_j D_n(t - t_j).
+double dirichlet(int n, double t)
+{
+  double v = 1.0;
+  for (int m = 1; 2 * m < n; m++) v += 2.0 * std::cos(m * t);
+  if (n % 2 == 0) v += std::cos(0.5 * n * t);
+  return v / n;
+}
+
+// Coarse (nc) -> fine (2 nc) interpolation matrix P [2 nc][nc] on integer
+// (half = 0) or half-integer (half = 1) azimuthal nodes, float64.
+std::vector<double> prolong_matrix(int nc, int half)
+{
+  const int nf = 2 * nc;
+  const double s = half ? 0.5 : 0.0;
+  std::vector<double> P((size_t)nf * nc);
+  for (int jf = 0; jf < nf; jf++)
+    for (int jc = 0; jc < nc; jc++)
+      P[(size_t)jf * nc + jc] = dirichlet(nc, (jf + s) * 2.0 * kPi / nf - (jc + s) * 2.0 * kPi / nc);
+  return P;
+}
+
+size_t refined_aux_floats(const cw_refined *r)
+{
+  size_t f = 0;
+  for (size_t q = 1; q < r->nth.size(); q++) f += 4 * (size_t)r->nth[q - 1] * r->nth[q];
+  return f;
+}
+
+size_t refined_bytes(const cw_refined *r, size_t *zone_bytes, size_t *batch_off, size_t *tr_off, size_t *mat_off)
+{
+  size_t off = 0;
+  for (size_t q = 0; q < r->zones.size(); q++) {
+    zone_bytes[q] = align256(layout(r->zones[q]).total);
+    off += zone_bytes[q];
+  }
+  *batch_off = off;
+  off += align256(r->zones.size() * sizeof(BatchInst)) + align256(r->zones.size() * sizeof(long));
+  *tr_off = off;
+  off += align256(4 * 4 * r->zones.size() * sizeof(Transfer));
+  *mat_off = off;
+  off += align256(refined_aux_floats(r) * sizeof(float));
+  return off;
+}
+
+}  // namespace
+
+cw_status cw_refined_create(const cw_grid *g, int32_t nzones, const int32_t *first_ring, const int32_t *ntheta,
+                            cw_refined **out)
+{
+  if (!g || !first_ring || !ntheta || !out) return fail(CW_ERR_ARG, "null argument");
+  if (nzones < 1 || nzones > 32) return fail(CW_ERR_RANGE, "1..32 zones (have %d)", nzones);
+  if (g->nr < 1 || g->nz < 4 || g->nz % 4) return fail(CW_ERR_RANGE, "need nr >= 1 and nz a positive multiple of 4");
+  if (!(g->dr > 0) || !(g->dz > 0) || !std::isfinite(g->dr) || !std::isfinite(g->dz))
+    return fail(CW_ERR_ARG, "cell sizes must be finite and > 0");
+  if (first_ring[0] != 0) return fail(CW_ERR_RANGE, "the first zone starts at ring 0");
+  for (int q = 0; q < nzones; q++) {
+    if (ntheta[q] < 1) return fail(CW_ERR_RANGE, "zone %d: ntheta must be >= 1", q);
+    if (q > 0 && (first_ring[q] <= first_ring[q - 1] || ntheta[q] != 2 * ntheta[q - 1]))
+      return fail(CW_ERR_RANGE, "zone %d: zones start at increasing rings and double ntheta", q);
+  }
+  if (first_ring[nzones - 1] >= g->nr) return fail(CW_ERR_RANGE, "a zone starts beyond the last ring");
+  if (ntheta[nzones - 1] != g->ntheta)
+    return fail(CW_ERR_RANGE, "the outermost zone's ntheta (%d) must be the grid's (%d)", ntheta[nzones - 1], g->ntheta);
+  if (interp_lds_bytes(g->ntheta) > 160 * 1024) return fail(CW_ERR_RANGE, "ntheta above 640 is not supported");
+  cw_refined *r = new (std::nothrow) cw_refined();
+  if (!r) return fail(CW_ERR_NOMEM, "out of host memory");
+  r->nr = g->nr; r->nz = g->nz; r->dr = g->dr; r->dz = g->dz;
+  r->first.assign(first_ring, first_ring + nzones);
+  r->nth.assign(ntheta, ntheta + nzones);
+  for (int q = 0; q < nzones; q++) {
+    cw_grid zg{r->rings(q), ntheta[q], g->nz, g->dr, g->dz};
+    cw_sim *z = nullptr;
+    const cw_status st = cw_create(&zg, &z);
+    if (st != CW_OK) { delete r; return st; }
+    z->ring0 = first_ring[q];
+    z->ghost_in = q > 0;
+    z->ghost_out = q + 1 < nzones;
+    z->med_extra = q + 1 < nzones ? 1 : 0;
+    r->zones.push_back(z);
+  }
+  *out = r;
+  return CW_OK;
+}
+
+void cw_refined_destroy(cw_refined *r) { delete r; }
+
+cw_status cw_refined_cells(const cw_refined *r, uint64_t *cells)
+{
+  if (!r || !cells) return fail(CW_ERR_ARG, "null argument");
+  uint64_t c = 0;
+  for (const cw_sim *z : r->zones) c += z->n;
+  *cells = c;
+  return CW_OK;
+}
+
+cw_status cw_refined_set_material_rz(cw_refined *r, const double *rho, const double *lam, const double *mu)
+{
+  if (!r || !rho || !lam || !mu) return fail(CW_ERR_ARG, "null argument");
+  if (r->bound) return fail(CW_ERR_STATE, "configuration after cw_refined_bind");
+  cw_status st;
+  if ((st = check_medium((size_t)r->nr * r->nz, rho, lam, mu)) != CW_OK) return st;
+  double vmax = 0;
+  for (size_t p = 0; p < (size_t)r->nr * r->nz; p++) vmax = std::max(vmax, std::sqrt((lam[p] + 2 * mu[p]) / rho[p]));
+  for (size_t q = 0; q < r->zones.size(); q++) {
+    const size_t o = (size_t)r->first[q] * r->nz;
+    if ((st = set_medium(r->zones[q], rho + o, lam + o, mu + o, true)) != CW_OK) return st;
+    r->zones[q]->vp_ref = vmax;
+  }
+  return CW_OK;
+}
+
+cw_status cw_refined_set_pml(cw_refined *r, int32_t npml_r, int32_t npml_z, double rc, double alpha)
+{
+  if (!r) return fail(CW_ERR_ARG, "null argument");
+  if (r->bound) return fail(CW_ERR_STATE, "configuration after cw_refined_bind");
+  const int last = (int)r->zones.size() - 1;
+  if (npml_r < 0 || npml_r >= r->rings(last))
+    return fail(CW_ERR_RANGE, "the radial layer (%d rings) must lie inside the outermost zone (%d rings)", npml_r,
+                r->rings(last));
+  for (int q = 0; q <= last; q++) {
+    const cw_status st = cw_set_pml(r->zones[q], q == last ? npml_r : 0, npml_z, rc, alpha);
+    if (st != CW_OK) return st;
+  }
+  return CW_OK;
+}
+
+cw_status cw_refined_cfl_dt(const cw_refined *r, double *dt_cfl)
+{
+  if (!r || !dt_cfl) return fail(CW_ERR_ARG, "null argument");
+  double best = INFINITY;
+  for (const cw_sim *z : r->zones) {
+    if (!z->have_material) return fail(CW_ERR_STATE, "medium not set");
+    best = std::min(best, z->dt_cfl);
+  }
+  *dt_cfl = best;
+  return CW_OK;
+}
+
+cw_status cw_refined_set_dt(cw_refined *r, double dt)
+{
+  if (!r) return fail(CW_ERR_ARG, "null argument");
+  if (r->bound) return fail(CW_ERR_STATE, "configuration after cw_refined_bind");
+  for (cw_sim *z : r->zones) {
+    const cw_status st = cw_set_dt(z, dt);
+    if (st != CW_OK) return st;
+  }
+  return CW_OK;
+}
+
+cw_status cw_refined_add_source(cw_refined *r, int32_t kind, int32_t i, int32_t j, int32_t k, const double *w,
+                                int64_t n)
+{
+  if (!r) return fail(CW_ERR_ARG, "null argument");
+  if (r->bound) return fail(CW_ERR_STATE, "configuration after cw_refined_bind");
+  if (i < 0 || i >= r->nr) return fail(CW_ERR_RANGE, "source ring %d outside the grid", i);
+  const int q = r->zone_of(i);
+  return cw_add_source(r->zones[q], kind, i - r->first[q], j, k, w, n);
+}
+
+cw_status cw_refined_add_receiver(cw_refined *r, int32_t kind, int32_t field, int32_t i, int32_t j, int32_t k,
+                                  int32_t *id)
+{
+  if (!r) return fail(CW_ERR_ARG, "null argument");
+  if (r->bound) return fail(CW_ERR_STATE, "configuration after cw_refined_bind");
+  if (i < 0 || i >= r->nr) return fail(CW_ERR_RANGE, "receiver ring %d outside the grid", i);
+  const int q = r->zone_of(i);
+  int32_t lid = 0;
+  const cw_status st = cw_add_receiver(r->zones[q], kind, field, i - r->first[q], j, k, &lid);
+  if (st != CW_OK) return st;
+  r->rec.emplace_back(q, lid);
+  if (id) *id = (int32_t)r->rec.size() - 1;
+  return CW_OK;
+}
+
+cw_status cw_refined_set_trace_capacity(cw_refined *r, int64_t nsteps)
+{
+  if (!r) return fail(CW_ERR_ARG, "null argument");
+  for (cw_sim *z : r->zones) {
+    const cw_status st = cw_set_trace_capacity(z, nsteps);
+    if (st != CW_OK) return st;
+  }
+  return CW_OK;
+}
+
+cw_status cw_refined_workspace_bytes(const cw_refined *r, uint64_t *bytes)
+{
+  if (!r || !bytes) return fail(CW_ERR_ARG, "null argument");
+  std::vector<size_t> zb(r->zones.size());
+  size_t b, t, m;
+  *bytes = refined_bytes(r, zb.data(), &b, &t, &m);
+  return CW_OK;
+}
+
+cw_status cw_refined_bind(cw_refined *r, void *workspace, uint64_t bytes, void *stream)
+{
+  if (!r || !workspace) return fail(CW_ERR_ARG, "null argument");
+  if (r->bound) return fail(CW_ERR_STATE, "already bound");
+  if ((uintptr_t)workspace & 255) return fail(CW_ERR_ARG, "workspace not 256-byte aligned");
+  const int nzn = (int)r->zones.size();
+  std::vector<size_t> zb(nzn);
+  size_t boff, troff, moff;
+  const size_t need = refined_bytes(r, zb.data(), &boff, &troff, &moff);
+  if (bytes < need)
+    return fail(CW_ERR_NOMEM, "workspace of %llu bytes, need %llu", (unsigned long long)bytes, (unsigned long long)need);
+  char *w = (char *)workspace;
+  size_t off = 0;
+  cw_status st;
+  for (int q = 0; q < nzn; q++) {
+    if ((st = cw_bind(r->zones[q], w + off, zb[q], stream)) != CW_OK) return st;
+    off += zb[q];
+  }
+  r->stream = (hipStream_t)stream;
+  r->device = r->zones[0]->device;
+  if ((st = cw_batch_create(r->zones.data(), nzn, &r->batch)) != CW_OK) return st;
+  if ((st = cw_batch_bind(r->batch, w + boff, troff - boff)) != CW_OK) return st;
+
+  // interpolation matrices per interface: P_int, P_half [nf][nc], R_int, R_half [nc][nf] (R = P^T / 2)
+  std::vector<float> mats(refined_aux_floats(r));
+  std::vector<size_t> mo(nzn, 0);
+  size_t mp = 0;
+  for (int q = 1; q < nzn; q++) {
+    const int nc = r->nth[q - 1], nf = r->nth[q];
+    mo[q] = mp;
+    for (int half = 0; half < 2; half++) {
+      const std::vector<double> P = prolong_matrix(nc, half);
+      float *Pm = mats.data() + mp + (size_t)half * nf * nc;
+      float *Rm = mats.data() + mp + (size_t)(2 + half) * nf * nc;
+      for (int jf = 0; jf < nf; jf++)
+        for (int jc = 0; jc < nc; jc++) {
+          Pm[(size_t)jf * nc + jc] = (float)P[(size_t)jf * nc + jc];
+          Rm[(size_t)jc * nf + jf] = (float)(0.5 * P[(size_t)jf * nc + jc]);
+        }
+    }
+    mp += 4 * (size_t)nf * nc;
+  }
+  r->d_mat = (float *)(w + moff);
+  // transfers: for parity p, the state is in fields[p] (stresses at level n)
+  // and the velocities of level n+1/2 go to fields[1 - p]
+  Transfer *dtr = (Transfer *)(w + troff);
+  std::vector<Transfer> h[2][2];
+  r->max_ns = 1;
+  for (int p = 0; p < 2; p++)
+    for (int q = 1; q < nzn; q++) {
+      const cw_sim *C = r->zones[q - 1], *F = r->zones[q];
+      const int nc = r->nth[q - 1], nf = r->nth[q];
+      const size_t cring = (size_t)nc * r->nz, fring = (size_t)nf * r->nz;
+      const float *Pint = r->d_mat + mo[q], *Phalf = Pint + (size_t)nf * nc;
+      const float *Rint = Pint + 2 * (size_t)nf * nc, *Rhalf = Pint + 3 * (size_t)nf * nc;
+      auto c_last = [&](int b, int f) { return C->fields[b][f] + (size_t)(C->nr - 1) * cring; };
+      auto c_ghost = [&](int b, int f) { return C->fields[b][f] + (size_t)C->nr * cring; };
+      auto f_first = [&](int b, int f) { return F->fields[b][f]; };
+      auto f_ghost = [&](int b, int f) { return F->fields[b][f] - fring; };
+      // before the velocity update: sigma_rr, sigma_tt of the fine ring for the coarse
+      // zone's v_r; sigma_rt, sigma_rz of the coarse ring for the fine zone's v_t, v_z
+      h[p][0].push_back({f_first(p, SRR), c_ghost(p, SRR), Rint, nf, nc});
+      h[p][0].push_back({f_first(p, STT), c_ghost(p, STT), Rint, nf, nc});
+      h[p][0].push_back({c_last(p, SRT), f_ghost(p, SRT), Phalf, nc, nf});
+      h[p][0].push_back({c_last(p, SRZ), f_ghost(p, SRZ), Pint, nc, nf});
+      // before the stress update: v_r of the coarse ring for the fine zone's normal
+      // stresses; v_t, v_z of the fine ring for the coarse zone's sigma_rt, sigma_rz
+      h[p][1].push_back({c_last(1 - p, VR), f_ghost(1 - p, VR), Pint, nc, nf});
+      h[p][1].push_back({f_first(1 - p, VT), c_ghost(1 - p, VT), Rhalf, nf, nc});
+      h[p][1].push_back({f_first(1 - p, VZ), c_ghost(1 - p, VZ), Rint, nf, nc});
+      r->max_ns = std::max(r->max_ns, nf);
+    }
+  HIPCHK(hipSetDevice(r->device));
+  size_t to = 0;
+  for (int p = 0; p < 2; p++)
+    for (int ph = 0; ph < 2; ph++) {
+      r->d_tr[p][ph] = dtr + to;
+      r->ntr[p][ph] = (int)h[p][ph].size();
+      if (!h[p][ph].empty())
+        HIPCHK(hipMemcpy(dtr + to, h[p][ph].data(), h[p][ph].size() * sizeof(Transfer), hipMemcpyHostToDevice));
+      to += h[p][ph].size();
+    }
+  if (!mats.empty()) HIPCHK(hipMemcpy(r->d_mat, mats.data(), mats.size() * sizeof(float), hipMemcpyHostToDevice));
+  r->bound = true;
+  return CW_OK;
+}
+
+cw_status cw_refined_step(cw_refined *r, int64_t nsteps)
+{
+  if (!r) return fail(CW_ERR_ARG, "null argument");
+  if (!r->bound) return fail(CW_ERR_STATE, "cw_refined_bind first");
+  if (nsteps < 0) return fail(CW_ERR_RANGE, "negative step count");
+  for (cw_sim *z : r->zones)
+    if (!z->receivers.empty() && z->nstep + nsteps > z->trace_cap)
+      return fail(CW_ERR_RANGE, "trace capacity %lld exceeded", (long long)z->trace_cap);
+  HIPCHK(hipSetDevice(r->device));
+  cw_batch *b = r->batch;
+  const int n = (int)r->zones.size();
+  for (int64_t t = 0; t < nsteps; t++) {
+    const int p = r->zones[0]->cur;
+    HIPCHK(launch_interp(r->d_tr[p][0], r->ntr[p][0], r->nz, r->max_ns, r->stream));
+    HIPCHK(launch_velocity_batch(b->d_inst, b->d_tile0, n, b->tiles, p, r->stream));
+    if (b->any_inject) HIPCHK(launch_inject_batch(b->d_inst, n, 0, p, r->stream));
+    HIPCHK(launch_interp(r->d_tr[p][1], r->ntr[p][1], r->nz, r->max_ns, r->stream));
+    HIPCHK(launch_stress_batch(b->d_inst, b->d_tile0, n, b->tiles, p, r->stream));
+    if (b->any_inject) HIPCHK(launch_inject_batch(b->d_inst, n, 1, p, r->stream));
+    HIPCHK(launch_record_batch(b->d_inst, n, b->max_rec, p, r->stream));
+    HIPCHK(launch_step_done_batch(b->d_inst, n, r->stream));
+    for (cw_sim *z : r->zones) {
+      z->nstep++;
+      z->cur = 1 - z->cur;
+    }
+  }
+  return CW_OK;
+}
+
+cw_status cw_refined_get_field(cw_refined *r, int32_t field, float *host_out)
+{
+  if (!r || !host_out) return fail(CW_ERR_ARG, "null argument");
+  size_t off = 0;
+  for (cw_sim *z : r->zones) {
+    const cw_status st = cw_get_field(z, field, host_out + off);
+    if (st != CW_OK) return st;
+    off += z->n;
+  }
+  return CW_OK;
+}
+
+cw_status cw_refined_set_field(cw_refined *r, int32_t field, const float *host_in)
+{
+  if (!r || !host_in) return fail(CW_ERR_ARG, "null argument");
+  size_t off = 0;
+  for (cw_sim *z : r->zones) {
+    const cw_status st = cw_set_field(z, field, host_in + off);
+    if (st != CW_OK) return st;
+    off += z->n;
+  }
+  return CW_OK;
+}
+
+cw_status cw_refined_get_traces(cw_refined *r, double *out, int64_t cap, int64_t *nsteps_done)
+{
+  if (!r || (!out && !r->rec.empty())) return fail(CW_ERR_ARG, "null argument");
+  if (!r->bound) return fail(CW_ERR_STATE, "cw_refined_bind first");
+  const int64_t done = r->zones[0]->nstep;
+  if (cap < done) return fail(CW_ERR_RANGE, "cap %lld < steps done %lld", (long long)cap, (long long)done);
+  if (nsteps_done) *nsteps_done = done;
+  std::vector<double> buf;
+  for (size_t q = 0; q < r->zones.size(); q++) {
+    cw_sim *z = r->zones[q];
+    if (z->receivers.empty()) continue;
+    buf.assign(z->receivers.size() * (size_t)cap, 0.0);
+    const cw_status st = cw_get_traces(z, buf.data(), cap, nullptr);
+    if (st != CW_OK) return st;
+    for (size_t m = 0; m < r->rec.size(); m++)
+      if (r->rec[m].first == (int)q)
+        std::memcpy(out + m * (size_t)cap, buf.data() + (size_t)r->rec[m].second * cap, (size_t)done * sizeof(double));
+  }
+  return CW_OK;
+}
+
+cw_status cw_refined_energy(cw_refined *r, double *E)
+{
+  if (!r || !E) return fail(CW_ERR_ARG, "null argument");
+  double sum = 0;
+  for (cw_sim *z : r->zones) {
+    double e = 0;
+    const cw_status st = cw_energy(z, &e);
+    if (st != CW_OK) return st;
+    sum += e;
+  }
+  *E = sum;
+  return CW_OK;
+}
+
+cw_status cw_refined_reset(cw_refined *r)
+{
+  if (!r) return fail(CW_ERR_ARG, "null argument");
+  for (cw_sim *z : r->zones) {
+    const cw_status st = cw_reset(z);
+    if (st != CW_OK) return st;
   }
   return CW_OK;
 }

@@ -31,6 +31,13 @@ enum TabZ { AZ_C = 0, BZ_C, AZ_H, BZ_H, NTAB_Z };
 // Everything one time step reads and writes, by value as a kernel argument.
 struct StepArgs {
   int nr, nt, nz;
+  // Zones of an azimuthally refined grid: ring0 is the global index of ring 0
+  // (radii are (ring0 + i + 1/2) dr); m_last is the last ring the medium
+  // arrays hold (nr - 1, or nr when they include the next zone's first
+  // ring); ghost_in / ghost_out: the field arrays hold a ring at i = -1 / i =
+  // nr with the neighbouring zone's values on this zone's azimuthal grid,
+  // read instead of the zero closure.
+  int ring0, m_last, ghost_in, ghost_out;
   int npr, npz, nzs;        // layer cells in r, in z (each end), z-slab rows (2 npz + 1)
   float dt, inv_dr, inv_dz, inv_dth;
   const float *inv_rc;      // 1 / r_i  [nr]
@@ -158,6 +165,17 @@ hipError_t launch_inject(const Inject *dev_list, int ninj, int phase, const int6
                          const StepArgs &a, int storage, hipStream_t stream);
 hipError_t launch_record(const Receiver *dev_rec, int nrec, const int64_t *step, int64_t cap,
                          const StepArgs &a, int storage, double *traces, hipStream_t stream);
+// One ghost-ring fill of an azimuthally refined grid: dst[r][k] =
+// sum_j M[r][j] src[j][k], rings of nz depth cells.
+struct Transfer {
+  const float *src;         // source ring [ns][nz]
+  float *dst;               // ghost ring [nd][nz]
+  const float *M;           // [nd][ns]
+  int ns, nd;
+};
+size_t interp_lds_bytes(int max_ns);
+hipError_t launch_interp(const Transfer *dev, int count, int nz, int max_ns, hipStream_t stream);
+
 hipError_t launch_energy(const StepArgs &a, int storage, double *partials, int nblocks, double scale,
                          double *result, hipStream_t stream);
 // After a float16 step: record the scale the level-n+1 buffer was written

@@ -143,7 +143,7 @@ __global__ void __launch_bounds__(256) k_velocity_basic(StepArgs a, int nbx)
   }
 
   // buoyancies: arithmetic mean of the two adjacent densities (clamped at the edges)
-  const int i1 = i + 1 < a.nr ? i + 1 : a.nr - 1;
+  const int i1 = i + 1 <= a.m_last ? i + 1 : a.m_last;
   const int k1 = kk + 1 < a.nz ? kk + 1 : a.nz - 1;
   const size_t p = at(a, i, j, kk);
   const float rho0 = a.rho[mat(a, i, j, kk)];
@@ -221,7 +221,7 @@ __global__ void __launch_bounds__(256) k_stress_basic(StepArgs a, int nbx)
     tz_dz = cpml(a.psi_z[Z_TZ_DZ], q, T[AZ_H * a.nz + k], T[BZ_H * a.nz + k], tz_dz);
   }
 
-  const int i1 = i + 1 < a.nr ? i + 1 : a.nr - 1;
+  const int i1 = i + 1 <= a.m_last ? i + 1 : a.m_last;
   const int k1 = kk + 1 < a.nz ? kk + 1 : a.nz - 1;
   const size_t p = at(a, i, j, kk);
   const size_t pm = mat(a, i, j, kk);
@@ -343,11 +343,11 @@ template <class S>
 __device__ double cell_energy(const StepArgs &a, int i, int j, int k)
 {
   const int jp = j == a.nt - 1 ? 0 : j + 1;
-  const int i1 = i + 1 < a.nr ? i + 1 : a.nr - 1;
+  const int i1 = i + 1 <= a.m_last ? i + 1 : a.m_last;
   const int k1 = k + 1 < a.nz ? k + 1 : a.nz - 1;
   const size_t p = at(a, i, j, k);
   const float *ci = a.scl_in, *co = a.scl_out;
-  const double ri = (double)(i + 0.5), Ri = (double)(i + 1);   // radii in units of dr
+  const double ri = (double)(a.ring0 + i + 0.5), Ri = (double)(a.ring0 + i + 1);   // radii in units of dr
   const size_t pm = mat(a, i, j, k);
   const double rho0 = a.rho[pm];
   const double rr = 0.5 * (rho0 + a.rho[mat(a, i1, j, k)]);

@@ -45,7 +45,7 @@ __device__ __forceinline__ void velocity_column(const StepArgs &a, int i, int j,
   const int jp = j == a.nt - 1 ? 0 : j + 1;
   const Lanes<S> L(a, kb, j, jm, jp);
   const float *c = a.scl_in;
-  const int i1 = i + 1 < a.nr ? i + 1 : a.nr - 1;
+  const int i1 = i + 1 <= a.m_last ? i + 1 : a.m_last;   // medium ring index, clamped at the edge
   float srr0[VW], srr1[VW], stt0[VW], stt1[VW], stt_jp[VW], srt0[VW], srt_jm[VW], srt_im[VW];
   float srz0[VW], srz_im[VW], stz0[VW], stz_jm[VW], szz0[VW];
   const rsrc_t R_srr = L.field(a.in[SRR], i), R_stt = L.field(a.in[STT], i), R_srt = L.field(a.in[SRT], i);
@@ -224,7 +224,7 @@ __device__ __forceinline__ void stress_column(const StepArgs &a, int i, int j, i
     }
   }
   // moduli: reciprocals of mu at the cell and its neighbours (r, theta, depth)
-  const int i1 = i + 1 < a.nr ? i + 1 : a.nr - 1;
+  const int i1 = i + 1 <= a.m_last ? i + 1 : a.m_last;
   const rsrc_t R_mu = L.med(a.mu, i), R_mu1 = L.med(a.mu, i1);   // medium index clamped at the edge
   float lam[VW], mu[VW], m_i1[VW], m_jp[VW], m_i1jp[VW];
   ldb4(lam, L.med(a.lam, i), L.m0, L.mj);

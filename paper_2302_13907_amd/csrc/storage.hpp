@@ -44,8 +44,8 @@ struct StF32 {
   static constexpr bool scaled = false;
   static constexpr unsigned bytes = 4;   // bytes per stored value
   // f advanced by p stored values
-  __device__ static const float *adv(const float *f, size_t p) { return f + p; }
-  __device__ static float *adv(float *f, size_t p) { return f + p; }
+  __device__ static const float *adv(const float *f, ptrdiff_t p) { return f + p; }
+  __device__ static float *adv(float *f, ptrdiff_t p) { return f + p; }
   __device__ static float ld(const float *f, size_t p, float) { return f[p]; }
   __device__ static void ldb(float (&o)[4], rsrc_t r, unsigned voff, unsigned soff, float) { ldb4(o, r, voff, soff); }
   __device__ static float ldb1(rsrc_t r, unsigned voff, unsigned soff, float) { return cw::ldb1(r, voff, soff); }
@@ -70,11 +70,11 @@ struct StF32 {
 struct StF16 {
   static constexpr bool scaled = true;
   static constexpr unsigned bytes = 2;
-  __device__ static const float *adv(const float *f, size_t p)
+  __device__ static const float *adv(const float *f, ptrdiff_t p)
   {
     return reinterpret_cast<const float *>(reinterpret_cast<const unsigned short *>(f) + p);
   }
-  __device__ static float *adv(float *f, size_t p)
+  __device__ static float *adv(float *f, ptrdiff_t p)
   {
     return reinterpret_cast<float *>(reinterpret_cast<unsigned short *>(f) + p);
   }
@@ -126,11 +126,11 @@ struct StF16 {
 struct StBF16 {
   static constexpr bool scaled = false;
   static constexpr unsigned bytes = 2;
-  __device__ static const float *adv(const float *f, size_t p)
+  __device__ static const float *adv(const float *f, ptrdiff_t p)
   {
     return reinterpret_cast<const float *>(reinterpret_cast<const unsigned short *>(f) + p);
   }
-  __device__ static float *adv(float *f, size_t p)
+  __device__ static float *adv(float *f, ptrdiff_t p)
   {
     return reinterpret_cast<float *>(reinterpret_cast<unsigned short *>(f) + p);
   }

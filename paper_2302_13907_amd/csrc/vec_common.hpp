@@ -128,18 +128,20 @@ struct Lanes {
     mringb = (unsigned)(mring * 4);
   }
   // resource of ring i of a field array / a float32 array
-  __device__ rsrc_t field(const float *f, int i) const { return make_rsrc(S::adv(f, (size_t)i * ring), ringb); }
-  __device__ rsrc_t fieldw(float *f, int i) const { return make_rsrc(S::adv(f, (size_t)i * ring), ringb); }
+  // (i may be -1: a ghost ring before ring 0)
+  __device__ rsrc_t field(const float *f, int i) const { return make_rsrc(S::adv(f, (ptrdiff_t)i * (ptrdiff_t)ring), ringb); }
+  __device__ rsrc_t fieldw(float *f, int i) const { return make_rsrc(S::adv(f, (ptrdiff_t)i * (ptrdiff_t)ring), ringb); }
   __device__ rsrc_t f32(const float *f, int i) const { return make_rsrc(f + (size_t)i * ring, ringm); }
   __device__ rsrc_t med(const float *f, int i) const { return make_rsrc(f + (size_t)i * mring, mringb); }
 };
 
-// VW values of a field at ring i (zero for a ring outside [0, nr)), row offset soff
+// VW values of a field at ring i, row offset soff: zero for a ring outside
+// [0, nr) unless a ghost ring stands there
 template <class S>
 __device__ __forceinline__ void ldf(float (&o)[VW], const Lanes<S> &L, const StepArgs &a, const float *f, float s,
                                     int i, unsigned soff)
 {
-  if (i < 0 || i >= a.nr) {
+  if ((i < 0 && !a.ghost_in) || (i >= a.nr && !a.ghost_out)) {
 #pragma unroll
     for (int e = 0; e < VW; e++) o[e] = 0.0f;
     return;

@@ -33,7 +33,12 @@ EXPORTS = ("cw_create", "cw_set_material", "cw_set_material_rz", "cw_set_pml", "
            "cw_ricker", "cw_destroy", "cw_last_error", "cw_profile", "cw_profile_read",
            "cw_set_path", "cw_set_storage", "cw_stream_probe", "cw_set_graph", "cw_set_adjoint",
            "cw_set_region_moduli", "cw_gradient", "cw_batch_create", "cw_batch_set_tile",
-           "cw_batch_workspace_bytes", "cw_batch_bind", "cw_batch_set_graph", "cw_batch_step", "cw_batch_destroy")
+           "cw_batch_workspace_bytes", "cw_batch_bind", "cw_batch_set_graph", "cw_batch_step", "cw_batch_destroy",
+           "cw_refined_create", "cw_refined_cells", "cw_refined_set_material_rz", "cw_refined_set_pml",
+           "cw_refined_cfl_dt", "cw_refined_set_dt", "cw_refined_add_source", "cw_refined_add_receiver",
+           "cw_refined_set_trace_capacity", "cw_refined_workspace_bytes", "cw_refined_bind", "cw_refined_step",
+           "cw_refined_get_field", "cw_refined_set_field", "cw_refined_get_traces", "cw_refined_energy",
+           "cw_refined_reset", "cw_refined_destroy")
 
 STORAGE = {"f32": 0, "f16": 1, "bf16": 2}
 
@@ -104,6 +109,23 @@ def load():
         "cw_batch_bind": [P, P, ctypes.c_uint64],
         "cw_batch_set_graph": [P, I32],
         "cw_batch_step": [P, I64],
+        "cw_refined_create": [ctypes.POINTER(_Grid), I32, ctypes.POINTER(I32), ctypes.POINTER(I32), ctypes.POINTER(P)],
+        "cw_refined_cells": [P, ctypes.POINTER(ctypes.c_uint64)],
+        "cw_refined_set_material_rz": [P, DP, DP, DP],
+        "cw_refined_set_pml": [P, I32, I32, D, D],
+        "cw_refined_cfl_dt": [P, DP],
+        "cw_refined_set_dt": [P, D],
+        "cw_refined_add_source": [P, I32, I32, I32, I32, DP, I64],
+        "cw_refined_add_receiver": [P, I32, I32, I32, I32, I32, ctypes.POINTER(I32)],
+        "cw_refined_set_trace_capacity": [P, I64],
+        "cw_refined_workspace_bytes": [P, ctypes.POINTER(ctypes.c_uint64)],
+        "cw_refined_bind": [P, P, ctypes.c_uint64, P],
+        "cw_refined_step": [P, I64],
+        "cw_refined_get_field": [P, I32, FP],
+        "cw_refined_set_field": [P, I32, FP],
+        "cw_refined_get_traces": [P, DP, I64, ctypes.POINTER(I64)],
+        "cw_refined_energy": [P, DP],
+        "cw_refined_reset": [P],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -111,6 +133,8 @@ def load():
         fn.restype = ctypes.c_int32
     lib.cw_destroy.argtypes = [P]
     lib.cw_destroy.restype = None
+    lib.cw_refined_destroy.argtypes = [P]
+    lib.cw_refined_destroy.restype = None
     lib.cw_batch_destroy.argtypes = [P]
     lib.cw_batch_destroy.restype = None
     lib.cw_last_error.argtypes = []
@@ -375,6 +399,119 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+class Refined:
+    """An azimuthally refined grid (see cw_refined_* in include/cwell.h):
+    zones = [(first_ring, ntheta), ...], ntheta doubling outwards.  Fields
+    are exchanged as the rings concatenated (ring i: ntheta_i x nz)."""
+
+    def __init__(self, nr: int, nz: int, dr: float, dz: float, zones):
+        self.lib = load()
+        self.zones = [(int(a), int(b)) for a, b in zones]
+        self.nr, self.nz, self.dr, self.dz = int(nr), int(nz), float(dr), float(dz)
+        g = _Grid(self.nr, self.zones[-1][1], self.nz, self.dr, self.dz)
+        first = (ctypes.c_int32 * len(self.zones))(*[a for a, _ in self.zones])
+        nth = (ctypes.c_int32 * len(self.zones))(*[b for _, b in self.zones])
+        h = ctypes.c_void_p()
+        _check(self.lib.cw_refined_create(ctypes.byref(g), len(self.zones), first, nth, ctypes.byref(h)))
+        self.h = h
+        self.nrec = 0
+        self.workspace = None
+        c = ctypes.c_uint64()
+        _check(self.lib.cw_refined_cells(self.h, ctypes.byref(c)))
+        self.cells = int(c.value)
+        self.ntheta = np.zeros(self.nr, dtype=int)
+        for q, (a, n) in enumerate(self.zones):
+            b = self.zones[q + 1][0] if q + 1 < len(self.zones) else self.nr
+            self.ntheta[a:b] = n
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.cw_refined_destroy(self.h)
+            self.h = None
+        self.workspace = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_material_rz(self, rho, lam, mu):
+        arrs = [np.ascontiguousarray(np.reshape(a, (self.nr, self.nz)), dtype=np.float64) for a in (rho, lam, mu)]
+        _check(self.lib.cw_refined_set_material_rz(self.h, *[_dp(a) for a in arrs]))
+
+    def set_pml(self, npml_r: int, npml_z: int, rc: float = 1e-3, alpha: float = 0.0):
+        _check(self.lib.cw_refined_set_pml(self.h, int(npml_r), int(npml_z), float(rc), float(alpha)))
+
+    def cfl_dt(self) -> float:
+        v = ctypes.c_double()
+        _check(self.lib.cw_refined_cfl_dt(self.h, ctypes.byref(v)))
+        return v.value
+
+    def set_dt(self, dt: float):
+        _check(self.lib.cw_refined_set_dt(self.h, float(dt)))
+        self.dt = float(dt)
+
+    def add_source(self, kind: str, i: int, j: int, k: int, w: Sequence[float]):
+        w = np.ascontiguousarray(w, dtype=np.float64)
+        _check(self.lib.cw_refined_add_source(self.h, SRC_KINDS[kind], i, j, k, _dp(w), len(w)))
+
+    def add_receiver(self, kind: str, i: int, j: int, k: int, field: Optional[str] = None) -> int:
+        rid = ctypes.c_int32()
+        fid = FIELDS.index(field) if field else 0
+        _check(self.lib.cw_refined_add_receiver(self.h, REC_KINDS[kind], fid, i, j, k, ctypes.byref(rid)))
+        self.nrec += 1
+        return rid.value
+
+    def set_trace_capacity(self, nsteps: int):
+        _check(self.lib.cw_refined_set_trace_capacity(self.h, int(nsteps)))
+        self.trace_cap = int(nsteps)
+
+    def workspace_bytes(self) -> int:
+        b = ctypes.c_uint64()
+        _check(self.lib.cw_refined_workspace_bytes(self.h, ctypes.byref(b)))
+        return b.value
+
+    def bind(self, device: str = "cuda", stream=None):
+        import torch
+        nbytes = self.workspace_bytes()
+        ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        ptr = ws.data_ptr()
+        off = (-ptr) % 256
+        if stream is None:
+            stream = torch.cuda.current_stream(ws.device)
+        self.stream = stream
+        self.workspace = ws
+        _check(self.lib.cw_refined_bind(self.h, ctypes.c_void_p(ptr + off), nbytes,
+                                        ctypes.c_void_p(stream.cuda_stream)))
+
+    def step(self, nsteps: int = 1):
+        _check(self.lib.cw_refined_step(self.h, int(nsteps)))
+
+    def traces(self, nsteps: int) -> np.ndarray:
+        out = np.zeros((max(self.nrec, 1), max(nsteps, 1)))
+        done = ctypes.c_int64()
+        _check(self.lib.cw_refined_get_traces(self.h, _dp(out), out.shape[1], ctypes.byref(done)))
+        return out[: self.nrec, : done.value]
+
+    def field(self, name: str) -> np.ndarray:
+        out = np.empty(self.cells, dtype=np.float32)
+        _check(self.lib.cw_refined_get_field(self.h, FIELDS.index(name), _fp(out)))
+        return out
+
+    def set_field(self, name: str, a):
+        a = np.ascontiguousarray(np.reshape(a, self.cells), dtype=np.float32)
+        _check(self.lib.cw_refined_set_field(self.h, FIELDS.index(name), _fp(a)))
+
+    def energy(self) -> float:
+        e = ctypes.c_double()
+        _check(self.lib.cw_refined_energy(self.h, ctypes.byref(e)))
+        return e.value
+
+    def reset(self):
+        _check(self.lib.cw_refined_reset(self.h))
 
 
 def cement_loss(sim: "Sim", window, dmu, dK):

@@ -232,6 +232,43 @@ def small_batched_case(count: int = 256, seed: int = 5) -> List[Workload]:
     return batched_case(count, seed, nr=48, nt=16, depths=(256, 384, 512), npml=8)
 
 
+def refined_zones(nr: int, ntheta_outer: int, ntheta_inner: int, dr: float) -> List[Tuple[int, int]]:
+    """Zones of an azimuthally refined grid that keep the outer resolution
+    and halve the azimuthal cell count each time the radius halves (Sec. 3):
+    with Q zones (ntheta_inner doubling up to ntheta_outer) and r_max =
+    nr dr, zone Q-1 holds the rings whose centre radius lies in
+    [r_max / 2, r_max), zone Q-2 those in [r_max / 4, r_max / 2), ..., zone
+    0 the rest.  Zones that would hold no ring are left out and the inner
+    cell counts halve from the next zone out.  Returns [(first_ring,
+    ntheta), ...]."""
+    q_count = int(round(np.log2(ntheta_outer / ntheta_inner))) + 1
+    if ntheta_inner < 1 or ntheta_inner * 2 ** (q_count - 1) != ntheta_outer:
+        raise ValueError("ntheta_outer / ntheta_inner must be a power of two")
+    r_max = nr * dr
+    centres = (np.arange(nr) + 0.5) * dr
+    firsts = []
+    for q in range(1, q_count):
+        first = int(np.searchsorted(centres, r_max / 2 ** (q_count - q), side="left"))
+        if 0 < first < nr and (not firsts or first > firsts[-1]):
+            firsts.append(first)
+    firsts = [0] + firsts
+    n = len(firsts)
+    return [(firsts[q], ntheta_outer // 2 ** (n - 1 - q)) for q in range(n)]
+
+
+def refined_production_case() -> Workload:
+    """The production workload (256 x 128 x 8192 cells of 2 mm, 20-cell
+    layer, 15 kHz axis source at k = 2048, 64 axis receivers) on the
+    azimuthally refined grid: 4 azimuthal cells below r = 16 mm, doubling
+    with the radius up to 128 from r = 256 mm (21856 cells per depth row
+    instead of 32768).  The time step is half of the refined grid's own
+    Courant limit."""
+    w = production_case()
+    w.name = "cased-well 256 x {4..128} x 8192 refined (2 mm)"
+    w.extra["zones"] = refined_zones(w.nr, w.nt, 4, w.dr)
+    return w
+
+
 def scaled_case(nr: int, nt: int, nz: int, steps: int = 50) -> Workload:
     """The production medium on a smaller grid (same 2 mm cells and layout
     fractions); used for parity at sizes the oracle finishes quickly."""

@@ -160,3 +160,67 @@ def test_workspace_size_accounts_for_everything():
         s2 = cwell.Sim(*shape, h, h)
         s2.set_material(*[np.repeat(m[:, None, :], 4, axis=1) for m in rz] if full else rz)
         assert base - s2.workspace_bytes() >= 3 * (n - 10 * 24) * 4 - 3 * 256
+
+
+def _refined(zones, nr=16, nz=64, ntheta=None):
+    lib = cwell.load()
+    g = cwell._Grid(nr, ntheta if ntheta is not None else zones[-1][1], nz, 5e-3, 5e-3)
+    first = (ctypes.c_int32 * len(zones))(*[a for a, _ in zones])
+    nth = (ctypes.c_int32 * len(zones))(*[b for _, b in zones])
+    h = ctypes.c_void_p()
+    rc = lib.cw_refined_create(ctypes.byref(g), len(zones), first, nth, ctypes.byref(h))
+    return lib, rc, h
+
+
+def test_refined_zone_validation():
+    """cw_refined_create refuses zones that do not start at ring 0, do not
+    double, are out of order or beyond the grid, a grid ntheta other than
+    the outermost zone's, and depths that are not a multiple of 4."""
+    for zones, kw in (([(1, 4), (4, 8)], {}), ([(0, 4), (4, 12)], {}), ([(0, 4), (4, 8), (4, 16)], {}),
+                      ([(0, 4), (20, 8)], {}), ([(0, 4), (4, 8)], {"ntheta": 16}), ([(0, 4), (4, 8)], {"nz": 62})):
+        lib, rc, h = _refined(zones, **kw)
+        assert rc == -2, (zones, kw, rc)
+    lib, rc, h = _refined([(0, 4), (4, 8), (9, 16)])
+    assert rc == 0
+    cells = ctypes.c_uint64()
+    assert lib.cw_refined_cells(h, ctypes.byref(cells)) == 0
+    assert cells.value == (4 * 4 + 5 * 8 + 7 * 16) * 64
+    lib.cw_refined_destroy(h)
+
+
+def test_refined_configuration_on_the_host():
+    """The whole configuration runs on the host: medium, layer (only inside
+    the outermost zone), time step under the Courant limit of every zone,
+    sources and receivers with each ring's own azimuthal index range, and
+    the workspace size."""
+    lib, rc, h = _refined([(0, 4), (4, 8), (9, 16)])
+    assert rc == 0
+    nr, nz = 16, 64
+    rho, lam, mu = inputs.cased_well(nr, 1, nz, 5e-3, 5e-3, z_top=0.16, radii=(0.02, 0.03, 0.045))
+    arrs = [np.ascontiguousarray(a[:, 0, :]) for a in (rho, lam, mu)]
+    dp = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    assert lib.cw_refined_set_material_rz(h, *[dp(a) for a in arrs]) == 0
+    assert lib.cw_refined_set_pml(h, 7, 5, ctypes.c_double(1e-3), ctypes.c_double(1e5)) == -2   # 7 rings in zone 2
+    assert lib.cw_refined_set_pml(h, 4, 5, ctypes.c_double(1e-3), ctypes.c_double(1e5)) == 0
+    dt = ctypes.c_double()
+    assert lib.cw_refined_cfl_dt(h, ctypes.byref(dt)) == 0
+    # Courant limit with each ring's own azimuthal width r_i 2 pi / ntheta_i
+    nth = np.array([4] * 4 + [8] * 5 + [16] * 7)
+    vp = np.sqrt((arrs[1] + 2 * arrs[2]) / arrs[0]).max(axis=1)
+    ra = (np.arange(nr) + 0.5) * 5e-3 * 2 * math.pi / nth
+    expect = (1.0 / (vp * np.sqrt(2 / 25e-6 + 1 / ra ** 2))).min()
+    assert dt.value == pytest.approx(expect, rel=1e-12)
+    assert lib.cw_refined_set_dt(h, ctypes.c_double(dt.value * 1.01)) == -4
+    assert lib.cw_refined_set_dt(h, ctypes.c_double(dt.value * 0.5)) == 0
+    w = np.ones(10)
+    assert lib.cw_refined_add_source(h, 0, 2, 4, 10, dp(w), 10) == -2      # ring 2 has 4 cells
+    assert lib.cw_refined_add_source(h, 0, 2, 3, 10, dp(w), 10) == 0
+    assert lib.cw_refined_add_source(h, 1, 12, 15, 10, dp(w), 10) == 0
+    rid = ctypes.c_int32()
+    assert lib.cw_refined_add_receiver(h, 0, 0, 0, -1, 20, ctypes.byref(rid)) == 0 and rid.value == 0
+    assert lib.cw_refined_add_receiver(h, 1, 3, 10, 7, 20, ctypes.byref(rid)) == 0 and rid.value == 1
+    assert lib.cw_refined_add_receiver(h, 1, 3, 10, 16, 20, ctypes.byref(rid)) == -2   # ring 10 has 16 cells
+    nb = ctypes.c_uint64()
+    assert lib.cw_refined_workspace_bytes(h, ctypes.byref(nb)) == 0
+    assert nb.value > 2 * 9 * 4 * (4 * 4 + 5 * 8 + 7 * 16) * 64
+    lib.cw_refined_destroy(h)

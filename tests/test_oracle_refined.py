@@ -209,6 +209,13 @@ def test_zone_plan_doubles_with_radius():
             assert (a1 + 0.5) * 5e-3 >= nr * 5e-3 / 2 ** (len(z) - z.index((a1, n1)))
 
 
+def test_workload_zones_are_the_oracle_plan():
+    """The workload description's zones (used by the HIP-side tests and the
+    benchmark) are the oracle's own plan."""
+    for args in ((256, 128, 4, 2e-3), (20, 64, 8, 5e-3), (37, 64, 8, 5e-3), (100, 64, 8, 5e-3), (5, 32, 1, 5e-3)):
+        assert inputs.refined_zones(*args) == R.zone_plan(*args), args
+
+
 def test_refinement_relaxes_the_courant_limit():
     """Coarser azimuthal steps near the axis lift the axis-limited time step
     (the production medium at 2 mm: uniform 128 vs zones from 4 to 128)."""
