@@ -308,7 +308,8 @@ void cw_batch_destroy(cw_batch *b);
    the transpose of that map times dtheta_fine / dtheta_coarse (which keeps
    the scheme's energy conserved).
    cw_refined_create: grid->ntheta must equal the outermost zone's ntheta
-   (at most 640), nz a multiple of 4, first_ring[0] = 0, first rings
+   (at most 229: the interpolation keeps a matrix and a tile in LDS), nz a
+   multiple of 4, first_ring[0] = 0, first rings
    increasing and below nr; CW_ERR_RANGE otherwise.  The medium must not
    vary along theta (cw_refined_set_material_rz, [nr][nz] float64).  The
    radial absorbing layer must lie inside the outermost zone.  Sources and

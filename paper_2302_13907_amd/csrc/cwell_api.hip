@@ -1596,7 +1596,9 @@ cw_status cw_refined_create(const cw_grid *g, int32_t nzones, const int32_t *fir
   if (first_ring[nzones - 1] >= g->nr) return fail(CW_ERR_RANGE, "a zone starts beyond the last ring");
   if (ntheta[nzones - 1] != g->ntheta)
     return fail(CW_ERR_RANGE, "the outermost zone's ntheta (%d) must be the grid's (%d)", ntheta[nzones - 1], g->ntheta);
-  if (interp_lds_bytes(g->ntheta) > 160 * 1024) return fail(CW_ERR_RANGE, "ntheta above 640 is not supported");
+  if (interp_lds_bytes(g->ntheta) > 160 * 1024)
+    return fail(CW_ERR_RANGE, "ntheta %d: the interpolation needs %zu bytes of LDS, above 160 KiB (ntheta <= 229)",
+                g->ntheta, interp_lds_bytes(g->ntheta));
   cw_refined *r = new (std::nothrow) cw_refined();
   if (!r) return fail(CW_ERR_NOMEM, "out of host memory");
   r->nr = g->nr; r->nz = g->nz; r->dr = g->dr; r->dz = g->dz;

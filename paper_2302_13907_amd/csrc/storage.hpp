@@ -15,25 +15,41 @@ namespace cw {
 typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
 typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 typedef __amdgpu_buffer_rsrc_t rsrc_t;
+// Cache policy of the field streams (bit 1 = non-temporal: the line is not
+// kept for reuse).  Every field value a launch writes is read only by a
+// later launch, long after it would have left the caches, so the stores are
+// non-temporal.  Measured on MI355X at 256 x 128 x 8192: 3 % faster in
+// float32 and bfloat16, 5 % fewer L2 fetches.  Non-temporal loads are 7-16 %
+// slower: the neighbouring columns re-read a value while it is still cached.
+#ifndef CW_NT_LOAD
+#define CW_NT_LOAD 0
+#endif
+#ifndef CW_NT_STORE
+#define CW_NT_STORE 1
+#endif
+constexpr int kFieldLoadAux = CW_NT_LOAD ? 2 : 0;
+constexpr int kFieldStoreAux = CW_NT_STORE ? 2 : 0;
 __device__ __forceinline__ rsrc_t make_rsrc(const void *base, unsigned nbytes)
 {
   // word 3: 32-bit data format, which untyped loads and stores require on this family
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)nbytes, 0x00020000);
 }
+template <int AUX = 0>
 __device__ __forceinline__ void ldb4(float (&o)[4], rsrc_t r, unsigned voff, unsigned soff)
 {
-  const u32x4 u = __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0);
+  const u32x4 u = __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, AUX);
   // copy the elements out first: a bit cast of a vector-element lvalue reads element 0
   const unsigned x = u.x, y = u.y, z = u.z, w = u.w;
   o[0] = __builtin_bit_cast(float, x); o[1] = __builtin_bit_cast(float, y);
   o[2] = __builtin_bit_cast(float, z); o[3] = __builtin_bit_cast(float, w);
 }
+template <int AUX = 0>
 __device__ __forceinline__ void stb4(rsrc_t r, unsigned voff, unsigned soff, const float (&v)[4])
 {
   u32x4 u;
   u.x = __builtin_bit_cast(unsigned, v[0]); u.y = __builtin_bit_cast(unsigned, v[1]);
   u.z = __builtin_bit_cast(unsigned, v[2]); u.w = __builtin_bit_cast(unsigned, v[3]);
-  __builtin_amdgcn_raw_buffer_store_b128(u, r, voff, soff, 0);
+  __builtin_amdgcn_raw_buffer_store_b128(u, r, voff, soff, AUX);
 }
 __device__ __forceinline__ float ldb1(rsrc_t r, unsigned voff, unsigned soff)
 {
@@ -47,9 +63,15 @@ struct StF32 {
   __device__ static const float *adv(const float *f, ptrdiff_t p) { return f + p; }
   __device__ static float *adv(float *f, ptrdiff_t p) { return f + p; }
   __device__ static float ld(const float *f, size_t p, float) { return f[p]; }
-  __device__ static void ldb(float (&o)[4], rsrc_t r, unsigned voff, unsigned soff, float) { ldb4(o, r, voff, soff); }
+  __device__ static void ldb(float (&o)[4], rsrc_t r, unsigned voff, unsigned soff, float)
+  {
+    ldb4<kFieldLoadAux>(o, r, voff, soff);
+  }
   __device__ static float ldb1(rsrc_t r, unsigned voff, unsigned soff, float) { return cw::ldb1(r, voff, soff); }
-  __device__ static void stb(rsrc_t r, unsigned voff, unsigned soff, const float (&v)[4], float) { stb4(r, voff, soff, v); }
+  __device__ static void stb(rsrc_t r, unsigned voff, unsigned soff, const float (&v)[4], float)
+  {
+    stb4<kFieldStoreAux>(r, voff, soff, v);
+  }
   __device__ static void st(float *f, size_t p, float v, float) { f[p] = v; }
   template <int V>
   __device__ static void ldv(float (&o)[V], const float *f, size_t p, float)
@@ -85,7 +107,7 @@ struct StF16 {
   }
   __device__ static void ldb(float (&o)[4], rsrc_t r, unsigned voff, unsigned soff, float s)
   {
-    const h4 v = __builtin_bit_cast(h4, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+    const h4 v = __builtin_bit_cast(h4, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, kFieldLoadAux));
     o[0] = (float)v[0] * s; o[1] = (float)v[1] * s; o[2] = (float)v[2] * s; o[3] = (float)v[3] * s;
   }
   __device__ static float ldb1(rsrc_t r, unsigned voff, unsigned soff, float s)
@@ -97,7 +119,7 @@ struct StF16 {
     h4 h;
     h[0] = (_Float16)(v[0] * is); h[1] = (_Float16)(v[1] * is);
     h[2] = (_Float16)(v[2] * is); h[3] = (_Float16)(v[3] * is);
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, h), r, voff, soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, h), r, voff, soff, kFieldStoreAux);
   }
   __device__ static void st(float *f, size_t p, float v, float is)
   {
@@ -147,7 +169,7 @@ struct StBF16 {
   }
   __device__ static void ldb(float (&o)[4], rsrc_t r, unsigned voff, unsigned soff, float)
   {
-    const u32x2 u = __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0);
+    const u32x2 u = __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, kFieldLoadAux);
     o[0] = __builtin_bit_cast(float, u.x << 16); o[1] = __builtin_bit_cast(float, u.x & 0xffff0000u);
     o[2] = __builtin_bit_cast(float, u.y << 16); o[3] = __builtin_bit_cast(float, u.y & 0xffff0000u);
   }
@@ -160,7 +182,7 @@ struct StBF16 {
     u32x2 u;
     u.x = (unsigned)pack(v[0]) | ((unsigned)pack(v[1]) << 16);
     u.y = (unsigned)pack(v[2]) | ((unsigned)pack(v[3]) << 16);
-    __builtin_amdgcn_raw_buffer_store_b64(u, r, voff, soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b64(u, r, voff, soff, kFieldStoreAux);
   }
   __device__ static void st(float *f, size_t p, float v, float)
   {

@@ -159,7 +159,7 @@ __device__ __forceinline__ void cpml_b(rsrc_t r, unsigned voff, unsigned soff, f
     p[e] = cb * p[e] + ca * X[e];
     X[e] += p[e];
   }
-  stb4(r, voff, soff, p);
+  stb4<kFieldStoreAux>(r, voff, soff, p);      // read again only by the next step
 }
 
 // 1 / s for a power-of-two scale s, exactly
