@@ -121,3 +121,62 @@ def test_theta_invariance_fullsize():
             assert np.abs(sl).max() > 0, name
         del f
     s.close()
+
+
+def test_refined_one_step_from_random_state_fullsize():
+    """The refined production grid (zones of 4 ... 128 azimuthal cells over
+    256 rings x 8192 depths, 179 M cells), one step from a seeded random
+    state, compared on whole depth planes (every ring of every zone, so the
+    six interfaces are crossed) against the refined oracle's step on 7-plane
+    crops; a source fires inside one crop."""
+    from oracle import refined as R
+    w = inputs.refined_production_case()
+    zones = w.extra["zones"]
+    med_rz = w.medium_rz()
+    announce("full size %s: one step from a random state" % (w.name,))
+    src_w = np.array([3.0e9])
+    g = cwell.Refined(w.nr, w.nz, w.dr, w.dz, zones)
+    g.set_material_rz(*med_rz)
+    g.set_pml(w.npml, w.npml, w.pml_rc, math.pi * w.f0)
+    dt = w.cfl_fraction * g.cfl_dt()
+    g.set_dt(dt)
+    g.add_source("volume", 0, -1, w.src_k, src_w)
+    g.bind("cuda:0")
+    nt = g.ntheta
+    offs = np.concatenate([[0], np.cumsum(nt * w.nz)])
+    rng = np.random.default_rng(78)
+    crops = {}
+    for name in FIELDS:
+        scale = 1.0 if name in VEL else 1e7
+        a = (scale * rng.standard_normal(g.cells, dtype=np.float32)).astype(np.float32)
+        g.set_field(name, a)
+        crops[name] = {kc: [a[offs[i]:offs[i + 1]].reshape(nt[i], w.nz)[:, kc - HALF:kc + HALF + 1].astype(np.float64)
+                            for i in range(w.nr)] for kc in WINDOWS}
+        del a
+    g.step(1)
+    got = {}
+    for name in FIELDS:
+        f = g.field(name)
+        got[name] = {kc: [f[offs[i]:offs[i + 1]].reshape(nt[i], w.nz)[:, kc].astype(np.float64) for i in range(w.nr)]
+                     for kc in WINDOWS}
+        del f
+    g.close()
+
+    for kc in WINDOWS:
+        o = R.RefinedOracle(w.nr, 2 * HALF + 1, w.dr, w.dz, zones)
+        o.set_material_rz(*[m[:, kc - HALF:kc + HALF + 1] for m in med_rz])
+        o.set_pml(w.npml, 0, w.pml_rc, math.pi * w.f0)   # radial layer only: the windows avoid the z layer
+        o.set_dt(dt)
+        if kc - HALF <= w.src_k <= kc + HALF:
+            o.add_source("volume", 0, -1, w.src_k - (kc - HALF), src_w)
+        for name in FIELDS:
+            o.set_field(name, np.concatenate([c.reshape(-1) for c in crops[name][kc]]))
+        o.run(1)
+        worst = 0.0
+        for name in FIELDS:
+            ref = [o.ring(name, i)[:, HALF] for i in range(w.nr)]
+            inc = max(np.abs(ref[i] - crops[name][kc][i][:, HALF]).max() for i in range(w.nr))
+            err = max(np.abs(got[name][kc][i] - ref[i]).max() for i in range(w.nr)) / inc
+            worst = max(worst, err)
+            assert err <= 1e-4, (kc, name, err)
+        announce("  depth %d: worst |gpu - oracle| / max|increment| = %.2e" % (kc, worst))
