@@ -15,6 +15,7 @@ namespace cw {
 typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
 typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 typedef __amdgpu_buffer_rsrc_t rsrc_t;
+typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
 // Cache policy of the field streams (bit 1 = non-temporal: the line is not
 // kept for reuse).  Every field value a launch writes is read only by a
 // later launch, long after it would have left the caches, so the stores are
@@ -156,11 +157,14 @@ struct StBF16 {
   {
     return reinterpret_cast<float *>(reinterpret_cast<unsigned short *>(f) + p);
   }
-  __device__ static unsigned short pack(float v)
+  // round to nearest even (the hardware conversion, two values per instruction)
+  __device__ static unsigned short pack(float v) { return __builtin_bit_cast(unsigned short, (__bf16)v); }
+  __device__ static unsigned pack2(float a, float b)
   {
-    unsigned u = __builtin_bit_cast(unsigned, v);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (unsigned short)(u >> 16);
+    bf2 h;
+    h[0] = (__bf16)a;
+    h[1] = (__bf16)b;
+    return __builtin_bit_cast(unsigned, h);
   }
   __device__ static float unpack(unsigned short h) { return __builtin_bit_cast(float, (unsigned)h << 16); }
   __device__ static float ld(const float *f, size_t p, float)
@@ -180,8 +184,8 @@ struct StBF16 {
   __device__ static void stb(rsrc_t r, unsigned voff, unsigned soff, const float (&v)[4], float)
   {
     u32x2 u;
-    u.x = (unsigned)pack(v[0]) | ((unsigned)pack(v[1]) << 16);
-    u.y = (unsigned)pack(v[2]) | ((unsigned)pack(v[3]) << 16);
+    u.x = pack2(v[0], v[1]);
+    u.y = pack2(v[2], v[3]);
     __builtin_amdgcn_raw_buffer_store_b64(u, r, voff, soff, kFieldStoreAux);
   }
   __device__ static void st(float *f, size_t p, float v, float)
@@ -201,8 +205,8 @@ struct StBF16 {
   {
     static_assert(V == 4, "four values per access");
     uint2 u;
-    u.x = (unsigned)pack(v[0]) | ((unsigned)pack(v[1]) << 16);
-    u.y = (unsigned)pack(v[2]) | ((unsigned)pack(v[3]) << 16);
+    u.x = pack2(v[0], v[1]);
+    u.y = pack2(v[2], v[3]);
     *reinterpret_cast<uint2 *>(reinterpret_cast<unsigned short *>(f) + p) = u;
   }
 };
