@@ -224,6 +224,142 @@ __global__ void __launch_bounds__(256) k_adj_velocity_gather(AdjArgs a)
   a.fb[SRT][p] += grt; a.fb[SRZ][p] += grz; a.fb[STZ][p] += gtz;
 }
 
+// ---- depth-vectorized gathers (nz a multiple of 4): one workgroup per
+// (ring, theta row, 1024 depth cells), four consecutive depth cells per
+// thread, 16-byte accesses; the depth neighbours of a thread's group come
+// from its own registers except at the group's two ends.  Each cell's
+// arithmetic is that of the one-cell gathers above, in the same order.
+constexpr int AW = 4;
+
+struct Col {
+  int i, j, jm, jp, kb;
+  bool live;
+  size_t p, pjm, pjp;       // cell offsets of the group in rows j, j-1, j+1 of ring i
+  size_t ring;              // values per ring
+};
+
+__device__ __forceinline__ bool col(const AdjArgs &a, Col &c)
+{
+  const int nbx = (a.nz / AW + 255) / 256;
+  const int bx = blockIdx.x % nbx, cc = blockIdx.x / nbx;
+  c.i = cc / a.nt;
+  c.j = cc - c.i * a.nt;
+  if (c.i >= a.nr) return false;
+  const int k0 = (bx * 256 + (int)threadIdx.x) * AW;
+  c.live = k0 < a.nz;
+  c.kb = c.live ? k0 : a.nz - AW;                  // dead lanes compute on a valid group, store nothing
+  c.jm = c.j == 0 ? a.nt - 1 : c.j - 1;
+  c.jp = c.j == a.nt - 1 ? 0 : c.j + 1;
+  c.ring = (size_t)a.nt * a.nz;
+  c.p = at(a, c.i, c.j, c.kb);
+  c.pjm = at(a, c.i, c.jm, c.kb);
+  c.pjp = at(a, c.i, c.jp, c.kb);
+  return true;
+}
+
+__device__ __forceinline__ void ld4(float (&o)[AW], const float *f, size_t q)
+{
+  const float4 v = *reinterpret_cast<const float4 *>(f + q);
+  o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
+}
+__device__ __forceinline__ void st4(float *f, size_t q, const float (&v)[AW])
+{
+  *reinterpret_cast<float4 *>(f + q) = make_float4(v[0], v[1], v[2], v[3]);
+}
+__device__ __forceinline__ void add4(float *f, size_t q, const float (&v)[AW])
+{
+  float o[AW];
+  ld4(o, f, q);
+  for (int e = 0; e < AW; e++) o[e] += v[e];
+  st4(f, q, o);
+}
+__global__ void __launch_bounds__(256) k_adj_stress_gather_v(AdjArgs a)
+{
+  Col c;
+  if (!col(a, c) || !c.live) return;               // a write-only pass: dead lanes have nothing to do
+  const int i = c.i, kb = c.kb;
+  const float ci = a.inv_rc[i], fi = a.inv_rf[i];
+  float *const *T = a.T;
+  const bool has_ip = i + 1 < a.nr, has_im = i >= 1;
+  const size_t pip = c.p + c.ring, pim = c.p - c.ring;
+  const float cip = has_ip ? a.inv_rc[i + 1] : 0.0f, fim = has_im ? a.inv_rf[i - 1] : 0.0f;
+  float t0[AW], t0i[AW], t1[AW], t1i[AW], t1jp[AW], t4[AW], t4jm[AW], t4m[AW], t6[AW], t3[AW], t3m[AW], t8[AW];
+  float t2[AW], t5[AW], t5m[AW], t7[AW], t7jm[AW];
+  ld4(t0, T[0], c.p); ld4(t1, T[1], c.p); ld4(t1jp, T[1], c.pjp);
+  ld4(t4, T[4], c.p); ld4(t4jm, T[4], c.pjm); ld4(t6, T[6], c.p);
+  ld4(t3, T[3], c.p); ld4(t8, T[8], c.p); ld4(t2, T[2], c.p); ld4(t5, T[5], c.p);
+  ld4(t7, T[7], c.p); ld4(t7jm, T[7], c.pjm);
+  if (has_ip) { ld4(t0i, T[0], pip); ld4(t1i, T[1], pip); }
+  if (has_im) { ld4(t4m, T[4], pim); ld4(t3m, T[3], pim); ld4(t5m, T[5], pim); }
+  const float t6b = kb >= 1 ? T[6][c.p - 1] : 0.0f, t8b = kb >= 1 ? T[8][c.p - 1] : 0.0f;
+  const float t2a = kb + AW < a.nz ? T[2][c.p + AW] : 0.0f;
+  float gr[AW], gt[AW], gz[AW];
+  for (int e = 0; e < AW; e++) {
+    const int k = kb + e;
+    float r = t0[e] * a.inv_dr + 0.5f * ci * t1[e];
+    if (has_ip) r += -t0i[e] * a.inv_dr + 0.5f * cip * t1i[e];
+    r += fi * (t4jm[e] - t4[e]) * a.inv_dth;
+    r -= t6[e] * a.inv_dz;
+    if (k >= 1) r += (e ? t6[e - 1] : t6b) * a.inv_dz;
+    float t = ci * (t1[e] - t1jp[e]) * a.inv_dth;
+    t += -t3[e] * a.inv_dr - 0.5f * fi * t4[e];
+    if (has_im) t += t3m[e] * a.inv_dr - 0.5f * fim * t4m[e];
+    t -= t8[e] * a.inv_dz;
+    if (k >= 1) t += (e ? t8[e - 1] : t8b) * a.inv_dz;
+    float z = t2[e] * a.inv_dz;
+    if (k + 1 < a.nz) z -= (e + 1 < AW ? t2[e + 1] : t2a) * a.inv_dz;
+    z -= t5[e] * a.inv_dr;
+    if (has_im) z += t5m[e] * a.inv_dr;
+    z += ci * (t7jm[e] - t7[e]) * a.inv_dth;
+    gr[e] = r; gt[e] = t; gz[e] = z;
+  }
+  add4(a.fb[VR], c.p, gr);
+  add4(a.fb[VT], c.p, gt);
+  add4(a.fb[VZ], c.p, gz);
+}
+
+__global__ void __launch_bounds__(256) k_adj_velocity_gather_v(AdjArgs a)
+{
+  Col c;
+  if (!col(a, c) || !c.live) return;
+  const int i = c.i, kb = c.kb;
+  const float ci = a.inv_rc[i], fi = a.inv_rf[i];
+  float *const *T = a.T;
+  const bool has_im = i >= 1, has_ip = i + 1 < a.nr;
+  const size_t pim = c.p - c.ring, pip = c.p + c.ring;
+  const float fim = has_im ? a.inv_rf[i - 1] : 0.0f, cip = has_ip ? a.inv_rc[i + 1] : 0.0f;
+  float t0[AW], t0m[AW], t1[AW], t1m[AW], t1jp[AW], t4[AW], t4jm[AW], t4p[AW], t8[AW], t3[AW], t3p[AW];
+  float t2[AW], t6[AW], t6p[AW], t7[AW], t7p[AW], t7jp[AW], t5[AW];
+  ld4(t0, T[0], c.p); ld4(t1, T[1], c.p); ld4(t1jp, T[1], c.pjp);
+  ld4(t4, T[4], c.p); ld4(t4jm, T[4], c.pjm); ld4(t8, T[8], c.p);
+  ld4(t3, T[3], c.p); ld4(t2, T[2], c.p); ld4(t6, T[6], c.p);
+  ld4(t7, T[7], c.p); ld4(t7jp, T[7], c.pjp); ld4(t5, T[5], c.p);
+  if (has_im) { ld4(t0m, T[0], pim); ld4(t1m, T[1], pim); }
+  if (has_ip) { ld4(t3p, T[3], pip); ld4(t4p, T[4], pip); ld4(t6p, T[6], pip); ld4(t7p, T[7], pip); }
+  const float t8b = kb >= 1 ? T[8][c.p - 1] : 0.0f;
+  const bool in_a = kb + AW < a.nz;
+  const float t2a = in_a ? T[2][c.p + AW] : 0.0f, t5a = in_a ? T[5][c.p + AW] : 0.0f;
+  float g[6][AW];
+  for (int e = 0; e < AW; e++) {
+    const int k = kb + e;
+    float rr = -t0[e] * a.inv_dr + 0.5f * fi * t1[e];
+    if (has_im) rr += t0m[e] * a.inv_dr + 0.5f * fim * t1m[e];
+    float tt = -0.5f * fi * t1[e] + ci * (t4jm[e] - t4[e]) * a.inv_dth;
+    if (has_im) tt -= 0.5f * fim * t1m[e];
+    float zz = -t8[e] * a.inv_dz;
+    if (k >= 1) zz += (e ? t8[e - 1] : t8b) * a.inv_dz;
+    float rt = fi * (t1[e] - t1jp[e]) * a.inv_dth + t3[e] * a.inv_dr + ci * t4[e];
+    if (has_ip) rt += -t3p[e] * a.inv_dr + cip * t4p[e];
+    float rz = t2[e] * a.inv_dz + t6[e] * a.inv_dr + 0.5f * ci * t7[e];
+    if (k + 1 < a.nz) rz -= (e + 1 < AW ? t2[e + 1] : t2a) * a.inv_dz;
+    if (has_ip) rz += -t6p[e] * a.inv_dr + 0.5f * cip * t7p[e];
+    float tz = t5[e] * a.inv_dz + ci * (t7[e] - t7jp[e]) * a.inv_dth;
+    if (k + 1 < a.nz) tz -= (e + 1 < AW ? t5[e + 1] : t5a) * a.inv_dz;
+    g[0][e] = rr; g[1][e] = tt; g[2][e] = zz; g[3][e] = rt; g[4][e] = rz; g[5][e] = tz;
+  }
+  for (int q = 0; q < 6; q++) add4(a.fb[SRR + q], c.p, g[q]);
+}
+
 // receivers: the loss's derivative with respect to sigma^{n+1}; weights
 // w[m] = 2 p_m(t_{n+1}) * (-1 / (3 cells of the receiver)); one block, the
 // receivers in order (two on one cell add in a fixed order)
@@ -356,6 +492,20 @@ hipError_t launch_adjoint_step(const AdjArgs &a, const Receiver *rec, int nrec, 
   if (nrec > 0 && w) hipLaunchKernelGGL(k_adj_receivers, dim3(1), dim3(256), 0, stream, a, rec, nrec, w);
   const size_t nc = (size_t)(g.i1 - g.i0) * a.nt * (g.k1 - g.k0);
   if (nc) hipLaunchKernelGGL(k_adj_gradient, grid_of(nc), dim3(256), 0, stream, a, g, Z, glam, gmu);
+  if (a.nz % AW == 0) {
+    const size_t nb = (size_t)((a.nz / AW + 255) / 256) * a.nt * a.nr;
+    if (nb > 0x7fffffffu) return hipErrorInvalidConfiguration;
+    const dim3 gv((unsigned)nb);
+    // terms one cell per thread (pointwise: measured on MI355X at 128 x 64 x 2048,
+    // a four-cells-per-thread form was slower, 268 vs 211 us and 224 vs 175 us),
+    // gathers four cells per thread (their depth neighbours come from registers:
+    // 210 vs 316 us and 285 vs 434 us)
+    hipLaunchKernelGGL(k_adj_stress_terms, grid_of(n), dim3(256), 0, stream, a);
+    hipLaunchKernelGGL(k_adj_stress_gather_v, gv, dim3(256), 0, stream, a);
+    hipLaunchKernelGGL(k_adj_velocity_terms, grid_of(n), dim3(256), 0, stream, a);
+    hipLaunchKernelGGL(k_adj_velocity_gather_v, gv, dim3(256), 0, stream, a);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(k_adj_stress_terms, grid_of(n), dim3(256), 0, stream, a);
   hipLaunchKernelGGL(k_adj_stress_gather, grid_of(n), dim3(256), 0, stream, a);
   hipLaunchKernelGGL(k_adj_velocity_terms, grid_of(n), dim3(256), 0, stream, a);

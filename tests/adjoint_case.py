@@ -24,8 +24,8 @@ SRC_K = 40
 REC_K = list(range(20, 44, 2))
 
 
-def medium(dmu=None, dK=None):
-    rho, lam, mu = inputs.cased_well(*SHAPE, H, H, z_top=KTOP * H, ramp=0.1, radii=RADII)
+def medium(dmu=None, dK=None, shape=SHAPE):
+    rho, lam, mu = inputs.cased_well(*shape, H, H, z_top=KTOP * H, ramp=0.1, radii=RADII)
     if dmu is not None:
         i0, i1, k0, nb, br = REGION
         K = lam + 2.0 * mu / 3.0
@@ -37,8 +37,8 @@ def medium(dmu=None, dK=None):
     return rho, lam, mu
 
 
-def oracle_sim(med, dt=None):
-    o = oracle.OracleSim(*SHAPE, H, H)
+def oracle_sim(med, dt=None, shape=SHAPE):
+    o = oracle.OracleSim(*shape, H, H)
     o.set_material(*med)
     o.set_pml(NPML, NPML, 1e-3, math.pi * F0)
     dt = dt or 0.5 * o.cfl_dt()

@@ -19,9 +19,9 @@ pytestmark = pytest.mark.gpu
 GRAD_TOL = 1e-4
 
 
-def _gpu_sim(dt, every):
-    s = cwell.Sim(*C.SHAPE, C.H, C.H)
-    s.set_material(*C.medium())
+def _gpu_sim(dt, every, shape=C.SHAPE):
+    s = cwell.Sim(*shape, C.H, C.H)
+    s.set_material(*C.medium(shape=shape))
     s.set_pml(C.NPML, C.NPML, 1e-3, math.pi * C.F0)
     s.set_dt(dt)
     s.add_source("volume", 0, -1, C.SRC_K, cwell.ricker(C.F0, (np.arange(C.STEPS) + 0.5) * dt))
@@ -37,9 +37,15 @@ def _reference():
     return o.gradient(C.STEPS, C.WINDOW, C.REGION), dt
 
 
-def test_gradient_matches_oracle():
-    (L, gm, gk), dt = _reference()
-    s = _gpu_sim(dt, 64)
+@pytest.mark.parametrize("nz", [C.SHAPE[2], C.SHAPE[2] + 2])
+def test_gradient_matches_oracle(nz):
+    """nz = 96: the depth-vectorized adjoint kernels (four cells per thread,
+    most lanes of each workgroup past the last depth); nz = 98: the one-cell
+    kernels."""
+    shape = (C.SHAPE[0], C.SHAPE[1], nz)
+    o, dt = C.oracle_sim(C.medium(shape=shape), shape=shape)
+    L, gm, gk = o.gradient(C.STEPS, C.WINDOW, C.REGION)
+    s = _gpu_sim(dt, 64, shape)
     Lg, gmg, gkg = s.gradient(C.WINDOW)
     announce("loss gpu %.9g oracle %.9g (rel %.2e)" % (Lg, L, abs(Lg - L) / L))
     assert abs(Lg - L) <= 1e-4 * L
