@@ -56,12 +56,16 @@ def algorithmic_bytes(kernel: str, w, n_r: int, n_z: int, fb: int = 4, axisym: b
     raise ValueError(kernel)
 
 
+# the sources the profiled step kernels (two-pass, fused, march, sources, receivers) are built from
+PROFILED_SOURCES = ("cwell_internal.hpp", "storage.hpp", "vec_common.hpp", "step_basic.hip", "step_vec.hip",
+                    "step_fused.hip", "step_march.hip")
+
+
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2302_13907_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".hpp")):
-            h.update(open(os.path.join(csrc, f), "rb").read())
+    for f in PROFILED_SOURCES:
+        h.update(open(os.path.join(csrc, f), "rb").read())
     return h.hexdigest()[:16]
 
 
