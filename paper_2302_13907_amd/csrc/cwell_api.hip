@@ -1528,6 +1528,8 @@ struct cw_refined {
   int rings(int q) const { return (q + 1 < (int)first.size() ? first[q + 1] : nr) - first[q]; }
 };
 
+}  // extern "C"
+
 namespace {
 
 // Trigonometric interpolation kernel of n equispaced samples (the even-n
@@ -1578,6 +1580,8 @@ size_t refined_bytes(const cw_refined *r, size_t *zone_bytes, size_t *batch_off,
 }
 
 }  // namespace
+
+extern "C" {
 
 cw_status cw_refined_create(const cw_grid *g, int32_t nzones, const int32_t *first_ring, const int32_t *ntheta,
                             cw_refined **out)
