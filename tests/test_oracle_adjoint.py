@@ -7,7 +7,8 @@
    layer-memory recursion against the forward step.
 2. Gradient: the adjoint gradient of the receiver loss with respect to the
    cement moduli of z-bins agrees with central finite differences of the
-   FP64 forward run (relative step 1e-4), bin by bin."""
+   FP64 forward run (relative step 1e-4), bin by bin, and each difference
+   resolves a loss change far above the float64 rounding of the loss."""
 import math
 
 import numpy as np
@@ -74,6 +75,17 @@ def test_gradient_matches_finite_differences():
         e[b] = 1e-4 * mu_c
         fd = (loss(e, z) - loss(-e, z)) / (2 * e[b])
         assert abs(gm[b] - fd) <= 1e-5 * abs(fd), (b, "mu", gm[b], fd)
+        _well_conditioned(fd, e[b], L)
         e[b] = 1e-4 * K_c
         fd = (loss(z, e) - loss(z, -e)) / (2 * e[b])
         assert abs(gk[b] - fd) <= 1e-5 * abs(fd), (b, "K", gk[b], fd)
+        _well_conditioned(fd, e[b], L)
+    # relative sensitivities |dL/dtheta| |theta| / L of the checked bins
+    assert abs(gm[0]) * mu_c / L > 1e-4 and abs(gk[0]) * K_c / L > 1e-5, (gm[0] * mu_c / L, gk[0] * K_c / L)
+
+
+def _well_conditioned(fd, h, L):
+    """The loss difference a central difference resolves is many orders of
+    magnitude above the float64 rounding of the loss itself, so the check
+    measures the gradient, not rounding noise."""
+    assert abs(fd) * 2 * h >= 1e6 * np.finfo(np.float64).eps * L, (fd, h, L)
