@@ -273,6 +273,78 @@ def cpu_baseline(w, target_s: float):
                       "no z layer), %d FP64 steps in %.1f s" % (w.nr, w.nt, nzs, steps, el)}
 
 
+ORACLE_TIMING_CASES = {
+    # name: (workload, steps of a full run, (warm-up, timed) steps at every thread,
+    # (warm-up, timed) at one thread); s_per_full_run scales the timed steps to a full run
+    "parity": ("parity", 300, (0, 300), (0, 300)),
+    "parity-long": ("parity", 3000, (0, 3000), (0, 600)),
+    "production": ("production", 2000, (2, 20), (1, 1)),
+}
+
+
+def oracle_timing_case(name: str):
+    """One timing of the FP64 oracle (host only): the named case at the
+    thread count this process was started with."""
+    import numpy as np
+    import oracle
+    from paper_2302_13907_amd import inputs
+    wl, full, every, one = ORACLE_TIMING_CASES[name]
+    w = inputs.parity_case() if wl == "parity" else inputs.production_case()
+    warm, steps = one if oracle.threads() == 1 else every
+    t0 = time.perf_counter()
+    o = oracle.OracleSim(w.nr, w.nt, w.nz, w.dr, w.dz)
+    o.set_material(*w.medium())
+    o.set_pml(w.npml, w.npml, w.pml_rc, math.pi * w.f0)
+    dt = w.cfl_fraction * o.cfl_dt()
+    o.set_dt(dt)
+    o.add_source("volume", 0, -1, w.src_k, oracle.ricker(w.f0, (np.arange(warm + steps) + 0.5) * dt))
+    for k in w.rec_k:
+        o.add_receiver("pressure", 0, -1, k)
+    setup = time.perf_counter() - t0
+    log("  set up in %.1f s" % setup)
+    if warm:
+        o.run(warm)
+        log("  %d warm-up steps done" % warm)
+    t0 = time.perf_counter()
+    o.run(steps)
+    el = time.perf_counter() - t0
+    return {"case": "%s, %d timed steps after %d" % (w.name.split(",")[0], steps, warm),
+            "threads": oracle.threads(), "setup_s": round(setup, 2), "s": round(el, 3),
+            "Gcell_per_s": round(w.cells * steps / el / 1e9, 5),
+            "full_run_steps": full, "s_per_full_run": round(el / steps * full, 1)}
+
+
+def oracle_timing():
+    """The FP64 oracle on the host: each case with every hardware thread and
+    with one, in child processes (the thread count is fixed at start)."""
+    import platform
+    import subprocess
+    model = platform.processor()
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    out = {"host_cpu": model, "nproc": os.cpu_count(), "cases": []}
+    for name in ORACLE_TIMING_CASES:
+        for threads in (None, 1):
+            env = dict(os.environ)
+            if threads:
+                env["OMP_NUM_THREADS"] = str(threads)
+            log("oracle timing: %s, %s threads" % (name, threads or env.get("OMP_NUM_THREADS", "all")))
+            r = subprocess.run([sys.executable, "-u", os.path.abspath(__file__), "--oracle-timing-case", name],
+                               env=env, stdout=subprocess.PIPE, text=True)
+            if r.returncode != 0:
+                raise RuntimeError("oracle timing of %s failed" % name)
+            res = json.loads(r.stdout.strip().splitlines()[-1])
+            log("  " + json.dumps(res))
+            out["cases"].append(res)
+    return out
+
+
 def run_steps(w, storage: str, path: str, warmup: int, steps: int, graph: int = 0, profile: bool = True):
     """Set up workload w, bind it, run warmup + timed steps; returns
     (seconds for the timed steps, {kernel: (ms, launches)}, traces).  With
@@ -557,7 +629,17 @@ def main():
                          "'name command' per line, and exit" % ", ".join(PROFILE_VARIANTS))
     ap.add_argument("--ingest-profiles", nargs=2, metavar=("VARIANT", "OUTDIR"),
                     help="summarise the outputs of those commands into profiles/ and exit")
+    ap.add_argument("--oracle-timing", action="store_true",
+                    help="time the FP64 oracle on the host (parity case at 300 and 3000 steps, a "
+                         "production-size sample; every thread and one), print one JSON line and exit")
+    ap.add_argument("--oracle-timing-case", choices=tuple(ORACLE_TIMING_CASES), help=argparse.SUPPRESS)
     args = ap.parse_args()
+    if args.oracle_timing_case:
+        print(json.dumps(oracle_timing_case(args.oracle_timing_case)))
+        return
+    if args.oracle_timing:
+        print(json.dumps({"oracle_timing": oracle_timing()}))
+        return
     if args.print_profile_commands:
         for name, cmd in profile_commands(*args.print_profile_commands):
             print(name, cmd)

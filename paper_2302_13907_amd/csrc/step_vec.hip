@@ -26,10 +26,13 @@ constexpr int kRows = CW_VEC_ROWS;
 // Minimum wavefronts per SIMD the compiler sizes each kernel's registers
 // for (1: no constraint).  Measured on MI355X at 256 x 128 x 8192: asking
 // for 6 makes the 16-bit velocity kernels and the bfloat16 stress kernel
-// 10-20 % faster; it gains nothing in float32, and the float16 stress
-// kernel, whose scale tracking needs more registers, then spills and slows.
+// 10-20 % faster; 8 makes the float32 stress kernel 1 % faster (64
+// registers, a few scalar values kept in vector lanes), while 6 or 7 for
+// the float32 velocity kernel changes nothing; the float16 stress kernel,
+// whose scale tracking needs more registers, spills and slows when
+// constrained.
 #ifndef CW_VEC_WAVES
-template <class S> struct Occupancy { static constexpr int vel = 1, str = 1; };
+template <class S> struct Occupancy { static constexpr int vel = 1, str = 8; };
 template <> struct Occupancy<StF16> { static constexpr int vel = 6, str = 1; };
 template <> struct Occupancy<StBF16> { static constexpr int vel = 6, str = 6; };
 #else
