@@ -64,11 +64,43 @@ __device__ __forceinline__ bool cell(const AdjArgs &a, int &i, int &j, int &k)
   return true;
 }
 
-// stress half-step, terms: T = (e_rr, e_tt bracket, e_zz, rt_dr, rt_b, rz_dr, rz_dz, tz_b, tz_dz) adjoints
-__global__ void __launch_bounds__(256) k_adj_stress_terms(AdjArgs a)
+// cells of the absorbing-layer slabs, one per thread: the radial slab
+// (rings [nr - npr, nr), every depth) first, then the two depth slabs of the
+// remaining rings (rows [0, npz) and [nz - 1 - npz, nz)); each cell once
+__device__ __forceinline__ bool slab_cell(const AdjArgs &a, int &i, int &j, int &k)
 {
-  int i, j, k;
-  if (!cell(a, i, j, k)) return;
+  const size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t nrs = (size_t)a.npr * a.nt * a.nz;
+  if (c < nrs) {
+    k = (int)(c % a.nz);
+    const size_t ij = c / a.nz;
+    j = (int)(ij % a.nt);
+    i = a.nr - a.npr + (int)(ij / a.nt);
+    return true;
+  }
+  const int zr = a.npz > 0 ? 2 * a.npz + 1 : 0;
+  const size_t cz = c - nrs;
+  if (cz >= (size_t)(a.nr - a.npr) * a.nt * zr) return false;
+  const int kz = (int)(cz % zr);
+  const size_t ij = cz / zr;
+  j = (int)(ij % a.nt);
+  i = (int)(ij / a.nt);
+  k = kz < a.npz ? kz : a.nz - 1 - a.npz + (kz - a.npz);
+  return true;
+}
+size_t slab_cells(const AdjArgs &a)
+{
+  return (size_t)a.npr * a.nt * a.nz + (size_t)(a.nr - a.npr) * a.nt * (a.npz > 0 ? 2 * a.npz + 1 : 0);
+}
+// the cell carries layer memory (its terms depend on state, not only on the fields)
+__device__ __forceinline__ bool in_slab(const AdjArgs &a, int i, int k)
+{
+  return i >= a.nr - a.npr || zrow(a, k) >= 0;
+}
+
+// stress half-step, terms: T = (e_rr, e_tt bracket, e_zz, rt_dr, rt_b, rz_dr, rz_dz, tz_b, tz_dz) adjoints
+__device__ __forceinline__ void stress_terms_cell(const AdjArgs &a, int i, int j, int k)
+{
   const size_t p = at(a, i, j, k);
   const int i1 = i + 1 < a.nr ? i + 1 : a.nr - 1;
   const int jp = j == a.nt - 1 ? 0 : j + 1;
@@ -108,6 +140,16 @@ __global__ void __launch_bounds__(256) k_adj_stress_terms(AdjArgs a)
   a.T[0][p] = err; a.T[1][p] = ett; a.T[2][p] = ezz;
   a.T[3][p] = rt_dr; a.T[4][p] = rt_b; a.T[5][p] = rz_dr;
   a.T[6][p] = rz_dz; a.T[7][p] = tz_b; a.T[8][p] = tz_dz;
+}
+__global__ void __launch_bounds__(256) k_adj_stress_terms(AdjArgs a)
+{
+  int i, j, k;
+  if (cell(a, i, j, k)) stress_terms_cell(a, i, j, k);
+}
+__global__ void __launch_bounds__(256) k_adj_stress_terms_slab(AdjArgs a)
+{
+  int i, j, k;
+  if (slab_cell(a, i, j, k)) stress_terms_cell(a, i, j, k);
 }
 
 // stress half-step, gather: velocity adjoints += (strain operator)^T T
@@ -150,10 +192,8 @@ __global__ void __launch_bounds__(256) k_adj_stress_gather(AdjArgs a)
 }
 
 // velocity half-step, terms: T = (r_dr, r_b, r_dz, t_dr, t_b, t_dz, z_dr, z_b, z_dz) adjoints
-__global__ void __launch_bounds__(256) k_adj_velocity_terms(AdjArgs a)
+__device__ __forceinline__ void velocity_terms_cell(const AdjArgs &a, int i, int j, int k)
 {
-  int i, j, k;
-  if (!cell(a, i, j, k)) return;
   const size_t p = at(a, i, j, k);
   const int i1 = i + 1 < a.nr ? i + 1 : a.nr - 1;
   const int jp = j == a.nt - 1 ? 0 : j + 1;
@@ -186,6 +226,16 @@ __global__ void __launch_bounds__(256) k_adj_velocity_terms(AdjArgs a)
   a.T[0][p] = r_dr; a.T[1][p] = r_b; a.T[2][p] = r_dz;
   a.T[3][p] = t_dr; a.T[4][p] = t_b; a.T[5][p] = t_dz;
   a.T[6][p] = z_dr; a.T[7][p] = z_b; a.T[8][p] = z_dz;
+}
+__global__ void __launch_bounds__(256) k_adj_velocity_terms(AdjArgs a)
+{
+  int i, j, k;
+  if (cell(a, i, j, k)) velocity_terms_cell(a, i, j, k);
+}
+__global__ void __launch_bounds__(256) k_adj_velocity_terms_slab(AdjArgs a)
+{
+  int i, j, k;
+  if (slab_cell(a, i, j, k)) velocity_terms_cell(a, i, j, k);
 }
 
 // velocity half-step, gather: stress adjoints += (divergence operator)^T T
@@ -229,6 +279,9 @@ __global__ void __launch_bounds__(256) k_adj_velocity_gather(AdjArgs a)
 // thread, 16-byte accesses; the depth neighbours of a thread's group come
 // from its own registers except at the group's two ends.  Each cell's
 // arithmetic is that of the one-cell gathers above, in the same order.
+// Measured on MI355X at 128 x 64 x 2048 (one adjoint step): terms kernels
+// over every cell plus four-cell gathers reading the nine stored terms,
+// 0.90 ms; gathers forming the terms themselves, 0.67 ms.
 constexpr int AW = 4;
 
 struct Col {
@@ -273,44 +326,189 @@ __device__ __forceinline__ void add4(float *f, size_t q, const float (&v)[AW])
   for (int e = 0; e < AW; e++) o[e] += v[e];
   st4(f, q, o);
 }
-__global__ void __launch_bounds__(256) k_adj_stress_gather_v(AdjArgs a)
+// ---- fused gathers (nz a multiple of 4).  Outside the layer slabs a
+// term is a pointwise function of the field adjoints and the medium, so
+// the gathers form the terms they need, at the group and at its
+// neighbours, from the fields themselves instead of reading nine stored
+// term arrays; inside the slabs, where the transposed memory recursion
+// carries state, a terms pass over the slab cells alone stores them and the
+// gathers read them there.  Each term is the expression of the terms
+// kernels above, with dt times the harmonic-mean moduli and the face
+// buoyancies read from arrays formed once per gradient (k_adj_coefs).
+
+#ifndef CW_ADJ_WAVES
+#define CW_ADJ_WAVES 1
+#endif
+// dt mu_rt, dt mu_rz, dt mu_tz, dt b_r, dt b_t, dt b_z of every medium cell
+// (one per thread, the medium's own layout), as the terms kernels form them
+__global__ void __launch_bounds__(256) k_adj_coefs(AdjArgs a)
+{
+  const size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= (size_t)a.nr * a.m_ring) return;
+  const int i = (int)(c / a.m_ring);
+  const size_t rem = c - (size_t)i * a.m_ring;
+  const int j = a.m_row ? (int)(rem / a.m_row) : 0;
+  const int k = a.m_row ? (int)(rem % a.m_row) : (int)rem;
+  const int i1 = i + 1 < a.nr ? i + 1 : a.nr - 1;
+  const int jp = j == a.nt - 1 ? 0 : j + 1;
+  const int k1 = k + 1 < a.nz ? k + 1 : a.nz - 1;
+  const float mu = a.mu[mat(a, i, j, k)];
+  const float m_i1 = a.mu[mat(a, i1, j, k)], m_jp = a.mu[mat(a, i, jp, k)], m_k1 = a.mu[mat(a, i, j, k1)];
+  a.C[C_RT][c] = a.dt * hm4(mu, m_i1, m_jp, a.mu[mat(a, i1, jp, k)]);
+  a.C[C_RZ][c] = a.dt * hm4(mu, m_i1, m_k1, a.mu[mat(a, i1, j, k1)]);
+  a.C[C_TZ][c] = a.dt * hm4(mu, m_jp, m_k1, a.mu[mat(a, i, jp, k1)]);
+  const float rho0 = a.rho[mat(a, i, j, k)];
+  a.C[C_BR][c] = a.dt * (2.0f * rcp(rho0 + a.rho[mat(a, i1, j, k)]));
+  a.C[C_BT][c] = a.dt * (2.0f * rcp(rho0 + a.rho[mat(a, i, jp, k)]));
+  a.C[C_BZ][c] = a.dt * (2.0f * rcp(rho0 + a.rho[mat(a, i, j, k1)]));
+}
+
+// medium index of (i, j, k); AXI: the medium does not vary along theta
+// (one row per ring), which lets the compiler share the rows' loads
+template <bool AXI>
+__device__ __forceinline__ size_t matx(const AdjArgs &a, int i, int j, int k)
+{
+  return AXI ? (size_t)i * a.m_ring + k : mat(a, i, j, k);
+}
+
+// stress-half terms of the four cells (i, j, kb..kb+3)
+template <bool AXI>
+__device__ __forceinline__ void stress_terms4(const AdjArgs &a, int i, int j, int kb, float (&T)[9][AW])
+{
+  const size_t p = at(a, i, j, kb), m = matx<AXI>(a, i, j, kb);
+  float mu[AW], lam[AW], crt[AW], crz[AW], ctz[AW];
+  ld4(mu, a.mu, m); ld4(lam, a.lam, m);
+  ld4(crt, a.C[C_RT], m); ld4(crz, a.C[C_RZ], m); ld4(ctz, a.C[C_TZ], m);
+  float grr[AW], gtt[AW], gzz[AW], srt[AW], srz[AW], stz[AW];
+  ld4(grr, a.fb[SRR], p); ld4(gtt, a.fb[STT], p); ld4(gzz, a.fb[SZZ], p);
+  ld4(srt, a.fb[SRT], p); ld4(srz, a.fb[SRZ], p); ld4(stz, a.fb[STZ], p);
+  for (int e = 0; e < AW; e++) {
+    const float gs = grr[e] + gtt[e] + gzz[e];
+    T[0][e] = a.dt * (lam[e] * gs + 2.0f * mu[e] * grr[e]);
+    T[1][e] = a.dt * (lam[e] * gs + 2.0f * mu[e] * gtt[e]);
+    T[2][e] = a.dt * (lam[e] * gs + 2.0f * mu[e] * gzz[e]);
+    T[3][e] = T[4][e] = crt[e] * srt[e];
+    T[5][e] = T[6][e] = crz[e] * srz[e];
+    T[7][e] = T[8][e] = ctz[e] * stz[e];
+  }
+}
+
+// stress-half terms of the one cell (i, j, k)
+template <bool AXI>
+__device__ __forceinline__ void stress_terms1(const AdjArgs &a, int i, int j, int k, float (&T)[9])
+{
+  const size_t p = at(a, i, j, k);
+  const size_t m = matx<AXI>(a, i, j, k);
+  const float mu = a.mu[m], lam = a.lam[m];
+  const float grr = a.fb[SRR][p], gtt = a.fb[STT][p], gzz = a.fb[SZZ][p];
+  const float gs = grr + gtt + gzz;
+  T[0] = a.dt * (lam * gs + 2.0f * mu * grr);
+  T[1] = a.dt * (lam * gs + 2.0f * mu * gtt);
+  T[2] = a.dt * (lam * gs + 2.0f * mu * gzz);
+  T[3] = T[4] = a.C[C_RT][m] * a.fb[SRT][p];
+  T[5] = T[6] = a.C[C_RZ][m] * a.fb[SRZ][p];
+  T[7] = T[8] = a.C[C_TZ][m] * a.fb[STZ][p];
+}
+
+// velocity-half terms of the four cells (i, j, kb..kb+3)
+template <bool AXI>
+__device__ __forceinline__ void velocity_terms4(const AdjArgs &a, int i, int j, int kb, float (&T)[9][AW])
+{
+  const size_t p = at(a, i, j, kb), m = matx<AXI>(a, i, j, kb);
+  float br[AW], bt[AW], bz[AW];
+  ld4(br, a.C[C_BR], m); ld4(bt, a.C[C_BT], m); ld4(bz, a.C[C_BZ], m);
+  float vr[AW], vt[AW], vz[AW];
+  ld4(vr, a.fb[VR], p); ld4(vt, a.fb[VT], p); ld4(vz, a.fb[VZ], p);
+  for (int e = 0; e < AW; e++) {
+    T[0][e] = T[1][e] = T[2][e] = br[e] * vr[e];
+    T[3][e] = T[4][e] = T[5][e] = bt[e] * vt[e];
+    T[6][e] = T[7][e] = T[8][e] = bz[e] * vz[e];
+  }
+}
+
+// velocity-half terms of the one cell (i, j, k)
+template <bool AXI>
+__device__ __forceinline__ void velocity_terms1(const AdjArgs &a, int i, int j, int k, float (&T)[9])
+{
+  const size_t p = at(a, i, j, k);
+  const size_t m = matx<AXI>(a, i, j, k);
+  T[0] = T[1] = T[2] = a.C[C_BR][m] * a.fb[VR][p];
+  T[3] = T[4] = T[5] = a.C[C_BT][m] * a.fb[VT][p];
+  T[6] = T[7] = T[8] = a.C[C_BZ][m] * a.fb[VZ][p];
+}
+
+// inside the slabs the stored terms replace the formed ones
+__device__ __forceinline__ void slab_terms4(const AdjArgs &a, int i, int j, int kb, float (&T)[9][AW])
+{
+  const bool rs = i >= a.nr - a.npr;
+  bool zs[AW], any = rs;
+  for (int e = 0; e < AW; e++) { zs[e] = zrow(a, kb + e) >= 0; any |= zs[e]; }
+  if (!any) return;
+  const size_t p = at(a, i, j, kb);
+  for (int t = 0; t < 9; t++) {
+    float v[AW];
+    ld4(v, a.T[t], p);
+    for (int e = 0; e < AW; e++)
+      if (rs || zs[e]) T[t][e] = v[e];
+  }
+}
+__device__ __forceinline__ void slab_terms1(const AdjArgs &a, int i, int j, int k, float (&T)[9])
+{
+  if (!in_slab(a, i, k)) return;
+  const size_t p = at(a, i, j, k);
+  for (int t = 0; t < 9; t++) T[t] = a.T[t][p];
+}
+
+// Both fused gathers form the terms of every position they read without
+// branches (a missing ring or depth neighbour is formed on a clamped valid
+// index and its contribution dropped), so all loads issue together; a group
+// whose positions reach a slab then swaps in the stored terms.
+template <bool AXI>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CW_ADJ_WAVES))) k_adj_stress_gather_f(AdjArgs a)
 {
   Col c;
-  if (!col(a, c) || !c.live) return;               // a write-only pass: dead lanes have nothing to do
-  const int i = c.i, kb = c.kb;
+  if (!col(a, c) || !c.live) return;
+  const int i = c.i, j = c.j, kb = c.kb;
   const float ci = a.inv_rc[i], fi = a.inv_rf[i];
-  float *const *T = a.T;
   const bool has_ip = i + 1 < a.nr, has_im = i >= 1;
-  const size_t pip = c.p + c.ring, pim = c.p - c.ring;
   const float cip = has_ip ? a.inv_rc[i + 1] : 0.0f, fim = has_im ? a.inv_rf[i - 1] : 0.0f;
-  float t0[AW], t0i[AW], t1[AW], t1i[AW], t1jp[AW], t4[AW], t4jm[AW], t4m[AW], t6[AW], t3[AW], t3m[AW], t8[AW];
-  float t2[AW], t5[AW], t5m[AW], t7[AW], t7jm[AW];
-  ld4(t0, T[0], c.p); ld4(t1, T[1], c.p); ld4(t1jp, T[1], c.pjp);
-  ld4(t4, T[4], c.p); ld4(t4jm, T[4], c.pjm); ld4(t6, T[6], c.p);
-  ld4(t3, T[3], c.p); ld4(t8, T[8], c.p); ld4(t2, T[2], c.p); ld4(t5, T[5], c.p);
-  ld4(t7, T[7], c.p); ld4(t7jm, T[7], c.pjm);
-  if (has_ip) { ld4(t0i, T[0], pip); ld4(t1i, T[1], pip); }
-  if (has_im) { ld4(t4m, T[4], pim); ld4(t3m, T[3], pim); ld4(t5m, T[5], pim); }
-  const float t6b = kb >= 1 ? T[6][c.p - 1] : 0.0f, t8b = kb >= 1 ? T[8][c.p - 1] : 0.0f;
-  const float t2a = kb + AW < a.nz ? T[2][c.p + AW] : 0.0f;
+  const int ip = has_ip ? i + 1 : i, im = has_im ? i - 1 : i;
+  const int kbm = kb >= 1 ? kb - 1 : kb, kba = kb + AW < a.nz ? kb + AW : a.nz - 1;
+  float T[9][AW], Tip[9][AW], Tim[9][AW], Tjp[9][AW], Tjm[9][AW], Tb[9], Ta[9];
+  stress_terms4<AXI>(a, i, j, kb, T);
+  stress_terms4<AXI>(a, i, c.jp, kb, Tjp);
+  stress_terms4<AXI>(a, i, c.jm, kb, Tjm);
+  stress_terms4<AXI>(a, ip, j, kb, Tip);
+  stress_terms4<AXI>(a, im, j, kb, Tim);
+  stress_terms1<AXI>(a, i, j, kbm, Tb);
+  stress_terms1<AXI>(a, i, j, kba, Ta);
+  if (ip >= a.nr - a.npr || zrow(a, kbm) >= 0 || zrow(a, kba) >= 0) {
+    slab_terms4(a, i, j, kb, T);
+    slab_terms4(a, i, c.jp, kb, Tjp);
+    slab_terms4(a, i, c.jm, kb, Tjm);
+    slab_terms4(a, ip, j, kb, Tip);
+    slab_terms4(a, im, j, kb, Tim);
+    slab_terms1(a, i, j, kbm, Tb);
+    slab_terms1(a, i, j, kba, Ta);
+  }
   float gr[AW], gt[AW], gz[AW];
   for (int e = 0; e < AW; e++) {
     const int k = kb + e;
-    float r = t0[e] * a.inv_dr + 0.5f * ci * t1[e];
-    if (has_ip) r += -t0i[e] * a.inv_dr + 0.5f * cip * t1i[e];
-    r += fi * (t4jm[e] - t4[e]) * a.inv_dth;
-    r -= t6[e] * a.inv_dz;
-    if (k >= 1) r += (e ? t6[e - 1] : t6b) * a.inv_dz;
-    float t = ci * (t1[e] - t1jp[e]) * a.inv_dth;
-    t += -t3[e] * a.inv_dr - 0.5f * fi * t4[e];
-    if (has_im) t += t3m[e] * a.inv_dr - 0.5f * fim * t4m[e];
-    t -= t8[e] * a.inv_dz;
-    if (k >= 1) t += (e ? t8[e - 1] : t8b) * a.inv_dz;
-    float z = t2[e] * a.inv_dz;
-    if (k + 1 < a.nz) z -= (e + 1 < AW ? t2[e + 1] : t2a) * a.inv_dz;
-    z -= t5[e] * a.inv_dr;
-    if (has_im) z += t5m[e] * a.inv_dr;
-    z += ci * (t7jm[e] - t7[e]) * a.inv_dth;
+    float r = T[0][e] * a.inv_dr + 0.5f * ci * T[1][e];
+    if (has_ip) r += -Tip[0][e] * a.inv_dr + 0.5f * cip * Tip[1][e];
+    r += fi * (Tjm[4][e] - T[4][e]) * a.inv_dth;
+    r -= T[6][e] * a.inv_dz;
+    if (k >= 1) r += (e ? T[6][e - 1] : Tb[6]) * a.inv_dz;
+    float t = ci * (T[1][e] - Tjp[1][e]) * a.inv_dth;
+    t += -T[3][e] * a.inv_dr - 0.5f * fi * T[4][e];
+    if (has_im) t += Tim[3][e] * a.inv_dr - 0.5f * fim * Tim[4][e];
+    t -= T[8][e] * a.inv_dz;
+    if (k >= 1) t += (e ? T[8][e - 1] : Tb[8]) * a.inv_dz;
+    float z = T[2][e] * a.inv_dz;
+    if (k + 1 < a.nz) z -= (e + 1 < AW ? T[2][e + 1] : Ta[2]) * a.inv_dz;
+    z -= T[5][e] * a.inv_dr;
+    if (has_im) z += Tim[5][e] * a.inv_dr;
+    z += ci * (Tjm[7][e] - T[7][e]) * a.inv_dth;
     gr[e] = r; gt[e] = t; gz[e] = z;
   }
   add4(a.fb[VR], c.p, gr);
@@ -318,43 +516,50 @@ __global__ void __launch_bounds__(256) k_adj_stress_gather_v(AdjArgs a)
   add4(a.fb[VZ], c.p, gz);
 }
 
-__global__ void __launch_bounds__(256) k_adj_velocity_gather_v(AdjArgs a)
+template <bool AXI>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CW_ADJ_WAVES))) k_adj_velocity_gather_f(AdjArgs a)
 {
   Col c;
   if (!col(a, c) || !c.live) return;
-  const int i = c.i, kb = c.kb;
+  const int i = c.i, j = c.j, kb = c.kb;
   const float ci = a.inv_rc[i], fi = a.inv_rf[i];
-  float *const *T = a.T;
   const bool has_im = i >= 1, has_ip = i + 1 < a.nr;
-  const size_t pim = c.p - c.ring, pip = c.p + c.ring;
   const float fim = has_im ? a.inv_rf[i - 1] : 0.0f, cip = has_ip ? a.inv_rc[i + 1] : 0.0f;
-  float t0[AW], t0m[AW], t1[AW], t1m[AW], t1jp[AW], t4[AW], t4jm[AW], t4p[AW], t8[AW], t3[AW], t3p[AW];
-  float t2[AW], t6[AW], t6p[AW], t7[AW], t7p[AW], t7jp[AW], t5[AW];
-  ld4(t0, T[0], c.p); ld4(t1, T[1], c.p); ld4(t1jp, T[1], c.pjp);
-  ld4(t4, T[4], c.p); ld4(t4jm, T[4], c.pjm); ld4(t8, T[8], c.p);
-  ld4(t3, T[3], c.p); ld4(t2, T[2], c.p); ld4(t6, T[6], c.p);
-  ld4(t7, T[7], c.p); ld4(t7jp, T[7], c.pjp); ld4(t5, T[5], c.p);
-  if (has_im) { ld4(t0m, T[0], pim); ld4(t1m, T[1], pim); }
-  if (has_ip) { ld4(t3p, T[3], pip); ld4(t4p, T[4], pip); ld4(t6p, T[6], pip); ld4(t7p, T[7], pip); }
-  const float t8b = kb >= 1 ? T[8][c.p - 1] : 0.0f;
-  const bool in_a = kb + AW < a.nz;
-  const float t2a = in_a ? T[2][c.p + AW] : 0.0f, t5a = in_a ? T[5][c.p + AW] : 0.0f;
+  const int ip = has_ip ? i + 1 : i, im = has_im ? i - 1 : i;
+  const int kbm = kb >= 1 ? kb - 1 : kb, kba = kb + AW < a.nz ? kb + AW : a.nz - 1;
+  float T[9][AW], Tim[9][AW], Tip[9][AW], Tjp[9][AW], Tjm[9][AW], Tb[9], Ta[9];
+  velocity_terms4<AXI>(a, i, j, kb, T);
+  velocity_terms4<AXI>(a, i, c.jp, kb, Tjp);
+  velocity_terms4<AXI>(a, i, c.jm, kb, Tjm);
+  velocity_terms4<AXI>(a, im, j, kb, Tim);
+  velocity_terms4<AXI>(a, ip, j, kb, Tip);
+  velocity_terms1<AXI>(a, i, j, kbm, Tb);
+  velocity_terms1<AXI>(a, i, j, kba, Ta);
+  if (ip >= a.nr - a.npr || zrow(a, kbm) >= 0 || zrow(a, kba) >= 0) {
+    slab_terms4(a, i, j, kb, T);
+    slab_terms4(a, i, c.jp, kb, Tjp);
+    slab_terms4(a, i, c.jm, kb, Tjm);
+    slab_terms4(a, im, j, kb, Tim);
+    slab_terms4(a, ip, j, kb, Tip);
+    slab_terms1(a, i, j, kbm, Tb);
+    slab_terms1(a, i, j, kba, Ta);
+  }
   float g[6][AW];
   for (int e = 0; e < AW; e++) {
     const int k = kb + e;
-    float rr = -t0[e] * a.inv_dr + 0.5f * fi * t1[e];
-    if (has_im) rr += t0m[e] * a.inv_dr + 0.5f * fim * t1m[e];
-    float tt = -0.5f * fi * t1[e] + ci * (t4jm[e] - t4[e]) * a.inv_dth;
-    if (has_im) tt -= 0.5f * fim * t1m[e];
-    float zz = -t8[e] * a.inv_dz;
-    if (k >= 1) zz += (e ? t8[e - 1] : t8b) * a.inv_dz;
-    float rt = fi * (t1[e] - t1jp[e]) * a.inv_dth + t3[e] * a.inv_dr + ci * t4[e];
-    if (has_ip) rt += -t3p[e] * a.inv_dr + cip * t4p[e];
-    float rz = t2[e] * a.inv_dz + t6[e] * a.inv_dr + 0.5f * ci * t7[e];
-    if (k + 1 < a.nz) rz -= (e + 1 < AW ? t2[e + 1] : t2a) * a.inv_dz;
-    if (has_ip) rz += -t6p[e] * a.inv_dr + 0.5f * cip * t7p[e];
-    float tz = t5[e] * a.inv_dz + ci * (t7[e] - t7jp[e]) * a.inv_dth;
-    if (k + 1 < a.nz) tz -= (e + 1 < AW ? t5[e + 1] : t5a) * a.inv_dz;
+    float rr = -T[0][e] * a.inv_dr + 0.5f * fi * T[1][e];
+    if (has_im) rr += Tim[0][e] * a.inv_dr + 0.5f * fim * Tim[1][e];
+    float tt = -0.5f * fi * T[1][e] + ci * (Tjm[4][e] - T[4][e]) * a.inv_dth;
+    if (has_im) tt -= 0.5f * fim * Tim[1][e];
+    float zz = -T[8][e] * a.inv_dz;
+    if (k >= 1) zz += (e ? T[8][e - 1] : Tb[8]) * a.inv_dz;
+    float rt = fi * (T[1][e] - Tjp[1][e]) * a.inv_dth + T[3][e] * a.inv_dr + ci * T[4][e];
+    if (has_ip) rt += -Tip[3][e] * a.inv_dr + cip * Tip[4][e];
+    float rz = T[2][e] * a.inv_dz + T[6][e] * a.inv_dr + 0.5f * ci * T[7][e];
+    if (k + 1 < a.nz) rz -= (e + 1 < AW ? T[2][e + 1] : Ta[2]) * a.inv_dz;
+    if (has_ip) rz += -Tip[6][e] * a.inv_dr + 0.5f * cip * Tip[7][e];
+    float tz = T[5][e] * a.inv_dz + ci * (T[7][e] - Tjp[7][e]) * a.inv_dth;
+    if (k + 1 < a.nz) tz -= (e + 1 < AW ? T[5][e + 1] : Ta[5]) * a.inv_dz;
     g[0][e] = rr; g[1][e] = tt; g[2][e] = zz; g[3][e] = rt; g[4][e] = rz; g[5][e] = tz;
   }
   for (int q = 0; q < 6; q++) add4(a.fb[SRR + q], c.p, g[q]);
@@ -496,20 +701,30 @@ hipError_t launch_adjoint_step(const AdjArgs &a, const Receiver *rec, int nrec, 
     const size_t nb = (size_t)((a.nz / AW + 255) / 256) * a.nt * a.nr;
     if (nb > 0x7fffffffu) return hipErrorInvalidConfiguration;
     const dim3 gv((unsigned)nb);
-    // terms one cell per thread (pointwise: measured on MI355X at 128 x 64 x 2048,
-    // a four-cells-per-thread form was slower, 268 vs 211 us and 224 vs 175 us),
-    // gathers four cells per thread (their depth neighbours come from registers:
-    // 210 vs 316 us and 285 vs 434 us)
-    hipLaunchKernelGGL(k_adj_stress_terms, grid_of(n), dim3(256), 0, stream, a);
-    hipLaunchKernelGGL(k_adj_stress_gather_v, gv, dim3(256), 0, stream, a);
-    hipLaunchKernelGGL(k_adj_velocity_terms, grid_of(n), dim3(256), 0, stream, a);
-    hipLaunchKernelGGL(k_adj_velocity_gather_v, gv, dim3(256), 0, stream, a);
+    // terms stored only for the slab cells (one per thread), gathers four
+    // cells per thread forming the other terms in place
+    const size_t ns = slab_cells(a);
+    const bool axi = a.m_row == 0;
+    if (ns) hipLaunchKernelGGL(k_adj_stress_terms_slab, grid_of(ns), dim3(256), 0, stream, a);
+    if (axi) hipLaunchKernelGGL(k_adj_stress_gather_f<true>, gv, dim3(256), 0, stream, a);
+    else hipLaunchKernelGGL(k_adj_stress_gather_f<false>, gv, dim3(256), 0, stream, a);
+    if (ns) hipLaunchKernelGGL(k_adj_velocity_terms_slab, grid_of(ns), dim3(256), 0, stream, a);
+    if (axi) hipLaunchKernelGGL(k_adj_velocity_gather_f<true>, gv, dim3(256), 0, stream, a);
+    else hipLaunchKernelGGL(k_adj_velocity_gather_f<false>, gv, dim3(256), 0, stream, a);
     return hipGetLastError();
   }
   hipLaunchKernelGGL(k_adj_stress_terms, grid_of(n), dim3(256), 0, stream, a);
   hipLaunchKernelGGL(k_adj_stress_gather, grid_of(n), dim3(256), 0, stream, a);
   hipLaunchKernelGGL(k_adj_velocity_terms, grid_of(n), dim3(256), 0, stream, a);
   hipLaunchKernelGGL(k_adj_velocity_gather, grid_of(n), dim3(256), 0, stream, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint_coefs(const AdjArgs &a, hipStream_t stream)
+{
+  const size_t n = (size_t)a.nr * a.m_ring;
+  if ((n + 255) / 256 > 0x7fffffffu) return hipErrorInvalidConfiguration;
+  hipLaunchKernelGGL(k_adj_coefs, grid_of(n), dim3(256), 0, stream, a);
   return hipGetLastError();
 }
 

@@ -119,6 +119,7 @@ struct cw_sim {
   float *adj_pr[NPSI_R] = {};
   float *adj_pz[NPSI_Z] = {};
   float *adj_T[9] = {};
+  float *adj_C[6] = {};         // dt-scaled effective moduli and buoyancies (the medium's layout)
   float *adj_ckpt = nullptr;    // checkpoints [ncp][9 n + 12 slab_r + 6 slab_z]
   float *adj_Z = nullptr;       // strain rates of one segment [every][6][region nodes]
   double *adj_glam = nullptr, *adj_gmu = nullptr;   // per region cell
@@ -210,6 +211,8 @@ size_t adj_bytes(const cw_sim *s)
   const size_t ncp = (size_t)((s->adj_steps + s->adj_every - 1) / s->adj_every);
   size_t f = adj_state_floats(s)               // adjoint fields and layer memory
              + 9 * s->n                        // term adjoints
+             + 6 * s->nm                       // effective coefficients
+             + 2 * 64                          // alignment of the two blocks above
              + ncp * adj_state_floats(s)       // checkpoints
              + (size_t)s->adj_every * 6 * adj_region_nodes(s)
              + (size_t)s->adj_steps * s->receivers.size();
@@ -632,7 +635,11 @@ cw_status cw_bind(cw_sim *s, void *workspace, uint64_t bytes, void *stream)
     for (int q = 0; q < NF; q++) { s->adj_fb[q] = p; p += s->n; }
     for (int q = 0; q < NPSI_R; q++) { s->adj_pr[q] = slab_r ? p : nullptr; p += slab_r; }
     for (int q = 0; q < NPSI_Z; q++) { s->adj_pz[q] = slab_z ? p : nullptr; p += slab_z; }
+    auto align64 = [](float *q) { return (float *)(((uintptr_t)q + 255) & ~(uintptr_t)255); };
+    p = align64(p);                               // the term and coefficient arrays take 16-byte accesses
     for (int q = 0; q < 9; q++) { s->adj_T[q] = p; p += s->n; }
+    p = align64(p);
+    for (int q = 0; q < 6; q++) { s->adj_C[q] = p; p += s->nm; }
     const size_t ncp = (size_t)((s->adj_steps + s->adj_every - 1) / s->adj_every);
     s->adj_ckpt = p; p += ncp * adj_state_floats(s);
     s->adj_Z = p; p += (size_t)s->adj_every * 6 * adj_region_nodes(s);
@@ -1251,7 +1258,9 @@ cw_status cw_gradient(cw_sim *s, int64_t n0, int64_t n1, double *loss, double *g
   for (int q = 0; q < NPSI_R; q++) a.pr[q] = s->adj_pr[q];
   for (int q = 0; q < NPSI_Z; q++) a.pz[q] = s->adj_pz[q];
   for (int q = 0; q < 9; q++) a.T[q] = s->adj_T[q];
+  for (int q = 0; q < 6; q++) a.C[q] = s->adj_C[q];
   a.tab_r = sa.tab_r; a.tab_z = sa.tab_z;
+  HIPCHK(launch_adjoint_coefs(a, s->stream));
   // segments backwards: recompute the segment's strain rates, then its adjoint steps
   for (int64_t seg = ncp - 1; seg >= 0; seg--) {
     const int64_t t0 = seg * C, t1 = std::min(t0 + C, N);

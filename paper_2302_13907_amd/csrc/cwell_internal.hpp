@@ -228,7 +228,11 @@ struct AdjArgs {
   float *pz[NPSI_Z];
   float *T[9];
   const float *tab_r, *tab_z;
+  // dt times the effective moduli and buoyancies of the medium's cells (the
+  // medium's layout): dt mu_rt, dt mu_rz, dt mu_tz, dt b_r, dt b_t, dt b_z
+  float *C[6];
 };
+enum { C_RT, C_RZ, C_TZ, C_BR, C_BT, C_BZ };
 // Parameter region: cells [i0, i1) x all theta x [k0, k1); the gradient
 // reads the strain rates of the nodes [ea, eb) x all theta x [za, zb)
 // (one ring and one depth more on the inner / upper side).
@@ -238,6 +242,7 @@ struct AdjRegion {
 };
 hipError_t launch_adjoint_step(const AdjArgs &a, const Receiver *rec, int nrec, const float *w, const AdjRegion &g,
                                const float *Z, double *glam, double *gmu, hipStream_t stream);
+hipError_t launch_adjoint_coefs(const AdjArgs &a, hipStream_t stream);
 hipError_t launch_adjoint_capture(const AdjArgs &a, const AdjRegion &g, const float *vr, const float *vt,
                                   const float *vz, float *Z, hipStream_t stream);
 hipError_t launch_set_step(int64_t *step, int64_t value, hipStream_t stream);

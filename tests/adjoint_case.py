@@ -24,8 +24,8 @@ SRC_K = 40
 REC_K = list(range(20, 44, 2))
 
 
-def medium(dmu=None, dK=None, shape=SHAPE):
-    rho, lam, mu = inputs.cased_well(*shape, H, H, z_top=KTOP * H, ramp=0.1, radii=RADII)
+def medium(dmu=None, dK=None, shape=SHAPE, rock_jitter=0.0):
+    rho, lam, mu = inputs.cased_well(*shape, H, H, z_top=KTOP * H, ramp=0.1, radii=RADII, rock_jitter=rock_jitter)
     if dmu is not None:
         i0, i1, k0, nb, br = REGION
         K = lam + 2.0 * mu / 3.0

@@ -3,7 +3,7 @@ gradient) against the FP64 oracle's adjoint gradient on the thin-well case;
 independence of the checkpoint spacing; the torch.autograd wrapper.
 
 Measured on MI355X: loss relative error 1.1e-7, per-bin gradient relative
-error (bins above 1e-3 of the largest) 4.5e-6; the bound asserted is 1e-4."""
+error (bins above 1e-3 of the largest) 4.6e-6; the bound asserted is 1e-4."""
 import math
 
 import numpy as np
@@ -19,9 +19,9 @@ pytestmark = pytest.mark.gpu
 GRAD_TOL = 1e-4
 
 
-def _gpu_sim(dt, every, shape=C.SHAPE):
+def _gpu_sim(dt, every, shape=C.SHAPE, rock_jitter=0.0):
     s = cwell.Sim(*shape, C.H, C.H)
-    s.set_material(*C.medium(shape=shape))
+    s.set_material(*C.medium(shape=shape, rock_jitter=rock_jitter))
     s.set_pml(C.NPML, C.NPML, 1e-3, math.pi * C.F0)
     s.set_dt(dt)
     s.add_source("volume", 0, -1, C.SRC_K, cwell.ricker(C.F0, (np.arange(C.STEPS) + 0.5) * dt))
@@ -37,15 +37,16 @@ def _reference():
     return o.gradient(C.STEPS, C.WINDOW, C.REGION), dt
 
 
-@pytest.mark.parametrize("nz", [C.SHAPE[2], C.SHAPE[2] + 2])
-def test_gradient_matches_oracle(nz):
+@pytest.mark.parametrize("nz,jitter", [(C.SHAPE[2], 0.0), (C.SHAPE[2] + 2, 0.0), (C.SHAPE[2], 0.02)])
+def test_gradient_matches_oracle(nz, jitter):
     """nz = 96: the depth-vectorized adjoint kernels (four cells per thread,
-    most lanes of each workgroup past the last depth); nz = 98: the one-cell
-    kernels."""
+    most lanes of each workgroup past the last depth), with a medium that
+    does not vary along theta and with rock moduli jittered cell by cell
+    (a 3-D medium); nz = 98: the one-cell kernels."""
     shape = (C.SHAPE[0], C.SHAPE[1], nz)
-    o, dt = C.oracle_sim(C.medium(shape=shape), shape=shape)
+    o, dt = C.oracle_sim(C.medium(shape=shape, rock_jitter=jitter), shape=shape)
     L, gm, gk = o.gradient(C.STEPS, C.WINDOW, C.REGION)
-    s = _gpu_sim(dt, 64, shape)
+    s = _gpu_sim(dt, 64, shape, jitter)
     Lg, gmg, gkg = s.gradient(C.WINDOW)
     announce("loss gpu %.9g oracle %.9g (rel %.2e)" % (Lg, L, abs(Lg - L) / L))
     assert abs(Lg - L) <= 1e-4 * L
