@@ -50,6 +50,10 @@ ORACLE_PINS = {
         "tests/test_oracle_physics.py::test_pml_reflection_bound",
     "Courant limit: stability margin by power iteration":
         "tests/test_oracle_pins.py::test_cfl_margin",
+    "Courant limit: sufficient and nearly sharp where the axis ring's azimuthal width dominates":
+        "tests/test_oracle_pins.py::test_cfl_margin_near_axis",
+    "pins reject planted mistakes (signs, terms, indices, operands, radii, normalisations)":
+        "tests/test_oracle_mutants.py::test_pins_reject_mutant",
     "Ricker pulse of Sec. 2: zeros, extrema, zero mean, spectral peak":
         "tests/test_oracle_pins.py::test_ricker_properties",
     "adjoint step (orc_adjoint_step): exact transpose of the step, layer included":

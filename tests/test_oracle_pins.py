@@ -388,6 +388,28 @@ def test_cfl_margin():
     assert growth[1] > 1e3 * growth[0], growth
 
 
+def test_cfl_margin_near_axis():
+    """Where the azimuthal width r_0 dth of the axis ring is far below dr
+    (48 azimuthal cells, a homogeneous fluid), the same Courant limit is
+    still sufficient and nearly sharp: 1.9 < omega_max * dt_cfl < 2, and a
+    random state stepped at dt_cfl keeps its energy.  Without the azimuthal
+    term the limit would be ten times too large."""
+    shape = (6, 48, 8)
+    full = lambda v: np.full(shape, v)
+    o = OracleSim(*shape, 0.01, 0.01)
+    o.set_material(full(1000.0), full(2.25e9), full(0.0))
+    dtc = o.cfl_dt()
+    o.set_dt(dtc)
+    wdt = _omega_max(o, shape, iters=600) * dtc
+    assert 1.9 < wdt < 2.0, wdt
+    o2 = OracleSim(*shape, 0.01, 0.01)
+    o2.set_material(full(1000.0), full(2.25e9), full(0.0))
+    o2.set_dt(dtc)
+    _isotropic_initial(o2, shape, full(1000.0), full(2.25e9), full(0.0), seed=4)
+    _, E = o2.run(2000, energy=True)
+    assert np.abs(E / E[0] - 1).max() < 1e-9
+
+
 def test_ricker_properties():
     """Ricker pulse of Sec. 2: peak 1 at the delay 2/f0, zeros at
     +-1/(sqrt(2) pi f0) around it, minima -2 exp(-3/2) at
