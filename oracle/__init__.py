@@ -70,6 +70,10 @@ ORACLE_PINS = {
         "tests/test_oracle_refined.py::test_energy_conserved_across_zones",
     "refined grid: axisymmetric solution equals the one-cell uniform grid":
         "tests/test_oracle_refined.py::test_axisymmetric_solution_is_that_of_the_uniform_grid",
+    "refined grid: every field crosses an interface at its own azimuthal nodes":
+        "tests/test_oracle_refined.py::test_interface_maps_each_field_on_its_own_nodes",
+    "refined grid: pins reject planted mistakes in the interpolation":
+        "tests/test_oracle_mutants.py::test_refined_pins_reject_mutant",
     "refined grid: order-one wave follows the fine uniform grid":
         "tests/test_oracle_refined.py::test_order_one_wave_close_to_the_fine_uniform_grid",
 }

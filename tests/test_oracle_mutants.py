@@ -180,3 +180,75 @@ def test_sources_are_unique_and_the_original_passes():
     import test_oracle_pins as tp
     tp.test_energy_conserved()
     tp.test_reciprocity()
+
+
+# ---- the refined-grid oracle (numpy): mutants of its source, loaded as a
+# separate module and swapped in for the refined-oracle pins
+
+REFINED_MUTANTS = {
+    "half-integer phase shift with the wrong sign": (
+        "    return 0.5 * (2.0 * math.pi / nf) - 0.5 * (2.0 * math.pi / nc)",
+        "    return 0.5 * (2.0 * math.pi / nc) - 0.5 * (2.0 * math.pi / nf)"),
+    "fine-to-coarse map without the factor 1/2": (
+        "    x = np.fft.ifft(c, axis=0) * 0.5",
+        "    x = np.fft.ifft(c, axis=0) * 1.0"),
+    "half-integer fields interpolated as if on integer nodes": (
+        "        half = name in HALF",
+        "        half = False"),
+}
+
+
+def _refined_pins():
+    """(name, callable) of every refined-oracle pin, parametrizations expanded."""
+    import itertools
+    import test_oracle_refined as tr
+    out = []
+    for name in sorted(n for n in dir(tr) if n.startswith("test_")):
+        fn = getattr(tr, name)
+        marks = [m for m in getattr(fn, "pytestmark", []) if m.name == "parametrize"]
+        grids = [[(m.args[0], v) for v in m.args[1]] for m in marks]
+        for combo in itertools.product(*grids):
+            kw = dict(combo)
+            out.append(("%s%s" % (name, kw or ""), (lambda f=fn, k=kw: f(**k))))
+    return out
+
+
+def _refined_mutant(mutation):
+    import types
+    from oracle import refined
+    src = open(refined.__file__).read()
+    for orig, repl in _edits(mutation):
+        assert src.count(orig) == 1, orig
+        src = src.replace(orig, repl)
+    mod = types.ModuleType("refined_mutant")
+    mod.__file__ = refined.__file__
+    exec(compile(src, refined.__file__, "exec"), mod.__dict__)
+    return mod
+
+
+@pytest.mark.parametrize("name", list(REFINED_MUTANTS))
+def test_refined_pins_reject_mutant(name, monkeypatch):
+    import test_oracle_refined as tr
+    monkeypatch.setattr(tr, "R", _refined_mutant(REFINED_MUTANTS[name]))
+    caught = None
+    for pin, fn in _refined_pins():
+        try:
+            fn()
+        except (AssertionError, ValueError, FloatingPointError):
+            caught = pin
+            break
+    print("%s: rejected by %s" % (name, caught))
+    assert caught is not None, "no refined-grid pin rejects the mutant: " + name
+
+
+def test_refined_unmutated_module_passes():
+    """The loader itself changes nothing: the unmutated source, loaded the
+    same way, passes every refined-grid pin."""
+    import test_oracle_refined as tr
+    saved = tr.R
+    tr.R = _refined_mutant([])
+    try:
+        for pin, fn in _refined_pins():
+            fn()
+    finally:
+        tr.R = saved

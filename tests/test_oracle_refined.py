@@ -165,6 +165,33 @@ def test_axisymmetric_solution_is_that_of_the_uniform_grid():
     assert max(np.abs(a).max() for a in r.f["vt"]) == 0.0
 
 
+# azimuthal node of each field on the staggered grid (the positions the
+# uniform-grid operator pin samples at): theta_j, or theta_{j+1/2} for v_theta,
+# s_rtheta and s_thetaz
+THETA_HALF = {"vr": False, "vt": True, "vz": False, "srr": False, "stt": False, "szz": False,
+              "srt": True, "srz": False, "stz": True}
+
+
+def test_interface_maps_each_field_on_its_own_nodes():
+    """Across a zone interface every field is carried between the two
+    azimuthal grids at its own nodes: a band-limited field sampled at its
+    nodes on every ring is mapped exactly onto the neighbour ring's samples,
+    coarse to fine and fine to coarse."""
+    nr, nz = 6, 5
+    r = R.RefinedOracle(nr, nz, 5e-3, 5e-3, [(0, 4), (3, 8)])
+    rng = np.random.default_rng(3)
+    for name, half in THETA_HALF.items():
+        f = _trig(rng, 4)                           # orders 0 and 1: resolved by the 4-cell rings
+        rings = []
+        for i in range(nr):
+            n = r.nt[i]
+            th = (np.arange(n) + (0.5 if half else 0.0)) * 2 * math.pi / n
+            rings.append(np.repeat(f(th)[:, None], nz, axis=1))
+        r.set_field(name, np.concatenate([x.reshape(-1) for x in rings]))
+        assert np.allclose(r._nb(name, 3, -1), rings[3], rtol=0, atol=1e-12), name    # coarse ring 2 seen from ring 3
+        assert np.allclose(r._nb(name, 2, 1), rings[2], rtol=0, atol=1e-12), name     # fine ring 3 seen from ring 2
+
+
 def test_order_one_wave_close_to_the_fine_uniform_grid():
     """A smooth initial radial velocity of azimuthal order 1 near the axis
     (g(r, z) cos theta): the refined grid, twice coarser in theta next to
