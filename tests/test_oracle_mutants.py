@@ -81,6 +81,15 @@ MUTANTS = {
     "Courant limit without the azimuthal term": (
         "double g = sqrt(1.0 / (s->dr * s->dr) + 1.0 / (ra * ra) + 1.0 / (s->dz * s->dz));",
         "double g = sqrt(1.0 / (s->dr * s->dr) + 1.0 / (s->dz * s->dz));"),
+    "transposed layer recursion returning the memory instead of the input": (
+        "  pb[q][p] = b * t;\n  return outb + a * t;",
+        "  pb[q][p] = b * t;\n  return a * t;"),
+    "transposed e_rr scattered to the wrong ring": (
+        "  addv(s, vr, i, j, k, err / s->dr);\n  addv(s, vr, i - 1, j, k, -err / s->dr);",
+        "  addv(s, vr, i + 1, j, k, err / s->dr);\n  addv(s, vr, i, j, k, -err / s->dr);"),
+    "transposed g_tz depth part with the wrong sign": (
+        "  addv(s, fb[VT], i, j, k + 1, Dz / s->dz);\n  addv(s, fb[VT], i, j, k, -Dz / s->dz);",
+        "  addv(s, fb[VT], i, j, k + 1, -Dz / s->dz);\n  addv(s, fb[VT], i, j, k, Dz / s->dz);"),
     "Ricker pulse delayed by 1/f0 instead of 2/f0": (
         "double tau = t - 2.0 / f0;",
         "double tau = t - 1.0 / f0;"),
