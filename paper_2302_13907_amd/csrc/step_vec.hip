@@ -24,17 +24,19 @@ using namespace vec;
 #endif
 constexpr int kRows = CW_VEC_ROWS;
 // Minimum wavefronts per SIMD the compiler sizes each kernel's registers
-// for (1: no constraint).  Measured on MI355X at 256 x 128 x 8192: asking
-// for 6 makes the 16-bit velocity kernels and the bfloat16 stress kernel
-// 10-20 % faster; 8 makes the float32 stress kernel 1 % faster (64
-// registers, a few scalar values kept in vector lanes), while 6 or 7 for
-// the float32 velocity kernel changes nothing; the float16 stress kernel,
-// whose scale tracking needs more registers, spills and slows when
-// constrained.
+// for (1: no constraint).  Measured on MI355X at 256 x 128 x 8192 (ms per
+// launch, velocity / stress):
+//   float32:  stress 8 -> 3.455 against 3.489 unconstrained (64 registers, a
+//             few scalar values kept in vector lanes); velocity 6 or 7 change
+//             nothing;
+//   bfloat16: 7 / 7 -> 1.815 / 2.209, against 1.904 / 2.340 at 6 / 6 and
+//             2.369 / 2.759 at 8 / 8;
+//   float16:  5 / 7 -> 2.097 / 2.375, against 2.129 / 2.617 at 6 / none;
+//             8 spills.
 #ifndef CW_VEC_WAVES
 template <class S> struct Occupancy { static constexpr int vel = 1, str = 8; };
-template <> struct Occupancy<StF16> { static constexpr int vel = 6, str = 1; };
-template <> struct Occupancy<StBF16> { static constexpr int vel = 6, str = 6; };
+template <> struct Occupancy<StF16> { static constexpr int vel = 5, str = 7; };
+template <> struct Occupancy<StBF16> { static constexpr int vel = 7, str = 7; };
 #else
 template <class S> struct Occupancy { static constexpr int vel = CW_VEC_WAVES, str = CW_VEC_WAVES; };
 #endif
