@@ -336,6 +336,8 @@ __device__ __forceinline__ void add4(float *f, size_t q, const float (&v)[AW])
 // kernels above, with dt times the harmonic-mean moduli and the face
 // buoyancies read from arrays formed once per gradient (k_adj_coefs).
 
+// Minimum wavefronts per SIMD of the fused gathers (1: no constraint).  On
+// MI355X at 128 x 64 x 2048, 4 changes nothing and 5 or 6 spill and slow.
 #ifndef CW_ADJ_WAVES
 #define CW_ADJ_WAVES 1
 #endif
