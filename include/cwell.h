@@ -192,7 +192,8 @@ cw_status cw_set_storage(cw_sim *s, int32_t storage);
    CW_PATH_TWO_PASS: a velocity launch and a stress launch per step (plus
    source launches), any number of sources and any storage; one workgroup
    per (ring, theta row) depth segment, 4 depth cells per thread when nz is
-   a multiple of 4, one cell per thread otherwise.
+   a multiple of 4 and a ring of one float32 array is under 4 GiB, one cell
+   per thread otherwise.
    CW_PATH_MARCH: the same two launches in radial-march form (when nz is a
    multiple of 4 and a ring of one array is under 2 GiB; otherwise as
    CW_PATH_TWO_PASS): each wavefront owns one theta row and 256 depth cells
@@ -275,7 +276,8 @@ cw_status cw_gradient(cw_sim *s, int64_t n0, int64_t n1, double *loss, double *g
    (plus batched source, receiver and step-counter launches), so small and
    uneven instances share the device.  Every simulation must be bound on
    one device and one stream, use float32 storage, have nz a multiple of 4
-   and have done steps of one parity; each keeps its own state, sources,
+   and rings of one array under 4 GiB (CW_ERR_RANGE otherwise), and have
+   done steps of one parity; each keeps its own state, sources,
    receivers and traces (cw_get_traces, cw_get_field etc. work as usual) and
    gives bitwise the results of stepping it alone with CW_PATH_TWO_PASS.
    The batch descriptor lives in a small caller-owned device workspace
@@ -309,7 +311,8 @@ void cw_batch_destroy(cw_batch *b);
    the scheme's energy conserved).
    cw_refined_create: grid->ntheta must equal the outermost zone's ntheta
    (at most 229: the interpolation keeps a matrix and a tile in LDS), nz a
-   multiple of 4, first_ring[0] = 0, first rings
+   multiple of 4 with ntheta * nz * 4 bytes under 4 GiB, first_ring[0] = 0,
+   first rings
    increasing and below nr; CW_ERR_RANGE otherwise.  The medium must not
    vary along theta (cw_refined_set_material_rz, [nr][nz] float64).  The
    radial absorbing layer must lie inside the outermost zone.  Sources and

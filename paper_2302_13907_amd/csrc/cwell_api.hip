@@ -737,7 +737,7 @@ cw_status cw_step(cw_sim *s, int64_t nsteps)
   // two-pass kernel form: one workgroup per column segment (default) or the
   // radial march, both with 4 depth cells per thread; one thread per cell
   // when nz is not a multiple of 4
-  const bool vec = kUseVec && vec_applies(s->nz);
+  const bool vec = kUseVec && vec_applies(s->nt, s->nz);
   const bool march = vec && s->path == CW_PATH_MARCH && march_applies(s->nt, s->nz);
   auto velocity = [&](const StepArgs &a) {
     return march ? launch_velocity_march(a, s->storage, s->stream)
@@ -1326,7 +1326,8 @@ static cw_status check_batch_member(const cw_batch *b, const cw_sim *s)
   if (!s) return fail(CW_ERR_ARG, "null simulation in the batch");
   if (!s->bound) return fail(CW_ERR_STATE, "every simulation of a batch must be bound");
   if (s->storage != ST_F32) return fail(CW_ERR_STATE, "batches take float32 storage");
-  if (!vec_applies(s->nz)) return fail(CW_ERR_RANGE, "batches need nz a multiple of 4 (have %d)", s->nz);
+  if (!vec_applies(s->nt, s->nz))
+    return fail(CW_ERR_RANGE, "batches need nz a multiple of 4 and rings below 4 GiB (have %d x %d)", s->nt, s->nz);
   if (!b->sims.empty()) {
     const cw_sim *f = b->sims[0];
     if (s->device != f->device || s->stream != f->stream)
@@ -1612,6 +1613,9 @@ cw_status cw_refined_create(const cw_grid *g, int32_t nzones, const int32_t *fir
   if (interp_lds_bytes(g->ntheta) > 160 * 1024)
     return fail(CW_ERR_RANGE, "ntheta %d: the interpolation needs %zu bytes of LDS, above 160 KiB (ntheta <= 229)",
                 g->ntheta, interp_lds_bytes(g->ntheta));
+  if (!vec_applies(g->ntheta, g->nz))
+    return fail(CW_ERR_RANGE, "a ring of %d x %d cells reaches 4 GiB (the zones' kernels address a ring with 32-bit offsets)",
+                g->ntheta, g->nz);
   cw_refined *r = new (std::nothrow) cw_refined();
   if (!r) return fail(CW_ERR_NOMEM, "out of host memory");
   r->nr = g->nr; r->nz = g->nz; r->dr = g->dr; r->dz = g->dz;

@@ -184,7 +184,9 @@ hipError_t launch_step_done(int64_t *step, hipStream_t stream);
 hipError_t launch_rescale(float *scl_written, float *scl_next, unsigned *maxabs, hipStream_t stream);
 constexpr int kF16TargetExp = 11;   // scaled float16 maxima land in [2^10, 2^11)
 // depth-vectorized two-pass kernels (4 cells per thread), when nz % 4 == 0
-bool vec_applies(int nz);
+// the depth-vectorized kernels apply: nz a multiple of 4, and one ring of a
+// float32 array below 4 GiB (it is addressed with 32-bit byte offsets)
+bool vec_applies(int nt, int nz);
 // One instance of a batched two-pass step (float32 storage): its step
 // arguments for both buffer parities (parity p reads fields[p] and writes
 // fields[1 - p]), its tile shape and share of the batched grid, and its

@@ -352,7 +352,7 @@ hipError_t dispatch(int storage, F &&f)
 }  // namespace
 
 // a ring of one float32 array must fit a buffer resource (byte offsets below 2^31)
-bool march_applies(int nt, int nz) { return vec_applies(nz) && (uint64_t)nt * nz * 4 <= 0x7fffffffull; }
+bool march_applies(int nt, int nz) { return vec_applies(nt, nz) && (uint64_t)nt * nz * 4 <= 0x7fffffffull; }
 
 hipError_t launch_velocity_march(const StepArgs &a, int storage, hipStream_t stream)
 {

@@ -373,13 +373,13 @@ hipError_t dispatch(int storage, F &&f)
 
 }  // namespace
 
-bool vec_applies(int nz) { return nz % VW == 0 && nz >= VW; }
+bool vec_applies(int nt, int nz) { return nz % VW == 0 && nz >= VW && (uint64_t)nt * nz * 4 < (1ull << 32); }
 
 hipError_t launch_velocity_vec(const StepArgs &a, int storage, hipStream_t stream)
 {
   const int nbx = (a.nz / VW + 255) / 256;
   const long g = (long)nbx * ((a.nt + kRows - 1) / kRows) * a.nr;
-  if (g > 0x7fffffff || !vec_applies(a.nz)) return hipErrorInvalidConfiguration;
+  if (g > 0x7fffffff || !vec_applies(a.nt, a.nz)) return hipErrorInvalidConfiguration;
   return dispatch(storage, [&](auto s) {
     hipLaunchKernelGGL(k_velocity_vec<decltype(s)>, dim3((unsigned)g), dim3(256), 0, stream, a, nbx);
     return hipGetLastError();
@@ -390,7 +390,7 @@ hipError_t launch_stress_vec(const StepArgs &a, int storage, hipStream_t stream)
 {
   const int nbx = (a.nz / VW + 255) / 256;
   const long g = (long)nbx * ((a.nt + kRows - 1) / kRows) * a.nr;
-  if (g > 0x7fffffff || !vec_applies(a.nz)) return hipErrorInvalidConfiguration;
+  if (g > 0x7fffffff || !vec_applies(a.nt, a.nz)) return hipErrorInvalidConfiguration;
   return dispatch(storage, [&](auto s) {
     hipLaunchKernelGGL(k_stress_vec<decltype(s)>, dim3((unsigned)g), dim3(256), 0, stream, a, nbx);
     return hipGetLastError();

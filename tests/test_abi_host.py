@@ -175,9 +175,11 @@ def _refined(zones, nr=16, nz=64, ntheta=None):
 def test_refined_zone_validation():
     """cw_refined_create refuses zones that do not start at ring 0, do not
     double, are out of order or beyond the grid, a grid ntheta other than
-    the outermost zone's, and depths that are not a multiple of 4."""
+    the outermost zone's, depths that are not a multiple of 4, and rings of
+    4 GiB or more (their kernels address a ring with 32-bit offsets)."""
     for zones, kw in (([(1, 4), (4, 8)], {}), ([(0, 4), (4, 12)], {}), ([(0, 4), (4, 8), (4, 16)], {}),
-                      ([(0, 4), (20, 8)], {}), ([(0, 4), (4, 8)], {"ntheta": 16}), ([(0, 4), (4, 8)], {"nz": 62})):
+                      ([(0, 4), (20, 8)], {}), ([(0, 4), (4, 8)], {"ntheta": 16}), ([(0, 4), (4, 8)], {"nz": 62}),
+                      ([(0, 64), (4, 128)], {"nz": 1 << 23})):
         lib, rc, h = _refined(zones, **kw)
         assert rc == -2, (zones, kw, rc)
     lib, rc, h = _refined([(0, 4), (4, 8), (9, 16)])
