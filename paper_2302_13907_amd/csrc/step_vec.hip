@@ -120,9 +120,9 @@ __device__ __forceinline__ void velocity_column(const StepArgs &a, int i, int j,
   }
   const rsrc_t R_vr = L.field(a.in[VR], i), R_vt = L.field(a.in[VT], i), R_vz = L.field(a.in[VZ], i);
   float vr[VW], vt[VW], vz[VW];
-  S::ldb(vr, R_vr, L.v0, L.sj, c[VR]);
-  S::ldb(vt, R_vt, L.v0, L.sj, c[VT]);
-  S::ldb(vz, R_vz, L.v0, L.sj, c[VZ]);
+  S::ldbu(vr, R_vr, L.v0, L.sj, c[VR]);
+  S::ldbu(vt, R_vt, L.v0, L.sj, c[VT]);
+  S::ldbu(vz, R_vz, L.v0, L.sj, c[VZ]);
 #pragma unroll
   for (int e = 0; e < VW; e++) {
     const float rho_kp = e == VW - 1 ? rho_a : rho0[e + 1];
@@ -247,12 +247,12 @@ __device__ __forceinline__ void stress_column(const StepArgs &a, int i, int j, i
   const rsrc_t R_srr = L.field(a.in[SRR], i), R_stt = L.field(a.in[STT], i), R_szz = L.field(a.in[SZZ], i);
   const rsrc_t R_srt = L.field(a.in[SRT], i), R_srz = L.field(a.in[SRZ], i), R_stz = L.field(a.in[STZ], i);
   float srr[VW], stt[VW], szz[VW], srt[VW], srz[VW], stz[VW];
-  S::ldb(srr, R_srr, L.v0, L.sj, c[SRR]);
-  S::ldb(stt, R_stt, L.v0, L.sj, c[STT]);
-  S::ldb(szz, R_szz, L.v0, L.sj, c[SZZ]);
-  S::ldb(srt, R_srt, L.v0, L.sj, c[SRT]);
-  S::ldb(srz, R_srz, L.v0, L.sj, c[SRZ]);
-  S::ldb(stz, R_stz, L.v0, L.sj, c[STZ]);
+  S::ldbu(srr, R_srr, L.v0, L.sj, c[SRR]);
+  S::ldbu(stt, R_stt, L.v0, L.sj, c[STT]);
+  S::ldbu(szz, R_szz, L.v0, L.sj, c[SZZ]);
+  S::ldbu(srt, R_srt, L.v0, L.sj, c[SRT]);
+  S::ldbu(srz, R_srz, L.v0, L.sj, c[SRZ]);
+  S::ldbu(stz, R_stz, L.v0, L.sj, c[STZ]);
 #pragma unroll
   for (int e = 0; e < VW; e++) {
     const float ik = e == VW - 1 ? ia : im[e + 1];            // 1/mu at k+1

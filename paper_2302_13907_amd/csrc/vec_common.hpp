@@ -153,7 +153,7 @@ __device__ __forceinline__ void ldf(float (&o)[VW], const Lanes<S> &L, const Ste
 __device__ __forceinline__ void cpml_b(rsrc_t r, unsigned voff, unsigned soff, float ca, float cb, float (&X)[VW])
 {
   float p[VW];
-  ldb4(p, r, voff, soff);
+  ldb4<kOwnLoadAux>(p, r, voff, soff);
 #pragma unroll
   for (int e = 0; e < VW; e++) {
     p[e] = cb * p[e] + ca * X[e];
