@@ -319,12 +319,20 @@ __device__ __forceinline__ void st4(float *f, size_t q, const float (&v)[AW])
 {
   *reinterpret_cast<float4 *>(f + q) = make_float4(v[0], v[1], v[2], v[3]);
 }
+#ifndef CW_ADJ_NT
+#define CW_ADJ_NT 1
+#endif
+typedef float f4v __attribute__((ext_vector_type(4)));
+// f[q..q+3] += v: the gathers' own updates, which no other lane of the
+// launch reads, load and store non-temporally (the caches stay with the
+// arrays that neighbouring columns re-read)
 __device__ __forceinline__ void add4(float *f, size_t q, const float (&v)[AW])
 {
-  float o[AW];
-  ld4(o, f, q);
-  for (int e = 0; e < AW; e++) o[e] += v[e];
-  st4(f, q, o);
+  f4v *p = reinterpret_cast<f4v *>(f + q);
+  f4v o = CW_ADJ_NT ? __builtin_nontemporal_load(p) : *p;
+  o.x += v[0]; o.y += v[1]; o.z += v[2]; o.w += v[3];
+  if (CW_ADJ_NT) __builtin_nontemporal_store(o, p);
+  else *p = o;
 }
 // ---- fused gathers (nz a multiple of 4).  Outside the layer slabs a
 // term is a pointwise function of the field adjoints and the medium, so
