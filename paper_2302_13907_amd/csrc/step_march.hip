@@ -109,9 +109,9 @@ k_velocity_march(StepArgs a, int nzb, int njt, int rseg)
     const float rho_a = ldb1(L.med(a.rho, i), L.ma, L.mj);
     const rsrc_t R_vr = L.field(a.in[VR], i), R_vt = L.field(a.in[VT], i), R_vz = L.field(a.in[VZ], i);
     float vr[VW], vt[VW], vz[VW];
-    S::ldb(vr, R_vr, L.v0, L.sj, c[VR]);
-    S::ldb(vt, R_vt, L.v0, L.sj, c[VT]);
-    S::ldb(vz, R_vz, L.v0, L.sj, c[VZ]);
+    S::ldbu(vr, R_vr, L.v0, L.sj, c[VR]);
+    S::ldbu(vt, R_vt, L.v0, L.sj, c[VT]);
+    S::ldbu(vz, R_vz, L.v0, L.sj, c[VZ]);
 
     const float irc = a.inv_rc[i], irf = a.inv_rf[i];
     float r_dr[VW], r_b[VW], r_dz[VW], t_dr[VW], t_b[VW], t_dz[VW], z_dr[VW], z_b[VW], z_dz[VW];
@@ -231,12 +231,12 @@ k_stress_march(StepArgs a, int nzb, int njt, int rseg)
     const float ia1 = rcp(ldb1(R_mu1, L.ma, L.mj)), ia1_jp = rcp(ldb1(R_mu1, L.ma, L.mjp));
     const float *c = a.scl_in;
     float srr[VW], stt[VW], szz[VW], srt[VW], srz[VW], stz[VW];
-    S::ldb(srr, L.field(a.in[SRR], i), L.v0, L.sj, c[SRR]);
-    S::ldb(stt, L.field(a.in[STT], i), L.v0, L.sj, c[STT]);
-    S::ldb(szz, L.field(a.in[SZZ], i), L.v0, L.sj, c[SZZ]);
-    S::ldb(srt, L.field(a.in[SRT], i), L.v0, L.sj, c[SRT]);
-    S::ldb(srz, L.field(a.in[SRZ], i), L.v0, L.sj, c[SRZ]);
-    S::ldb(stz, L.field(a.in[STZ], i), L.v0, L.sj, c[STZ]);
+    S::ldbu(srr, L.field(a.in[SRR], i), L.v0, L.sj, c[SRR]);
+    S::ldbu(stt, L.field(a.in[STT], i), L.v0, L.sj, c[STT]);
+    S::ldbu(szz, L.field(a.in[SZZ], i), L.v0, L.sj, c[SZZ]);
+    S::ldbu(srt, L.field(a.in[SRT], i), L.v0, L.sj, c[SRT]);
+    S::ldbu(srz, L.field(a.in[SRZ], i), L.v0, L.sj, c[SRZ]);
+    S::ldbu(stz, L.field(a.in[STZ], i), L.v0, L.sj, c[STZ]);
 
     const float irc = a.inv_rc[i], irf = a.inv_rf[i];
     float err[VW], ett[VW], ezz[VW], rt_dr[VW], rt_b[VW], rz_dr[VW], rz_dz[VW], tz_b[VW], tz_dz[VW];
