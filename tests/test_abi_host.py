@@ -225,4 +225,17 @@ def test_refined_configuration_on_the_host():
     nb = ctypes.c_uint64()
     assert lib.cw_refined_workspace_bytes(h, ctypes.byref(nb)) == 0
     assert nb.value > 2 * 9 * 4 * (4 * 4 + 5 * 8 + 7 * 16) * 64
+    # nothing runs or reads back before cw_refined_bind
+    assert lib.cw_refined_step(h, 1) == -5
+    done = ctypes.c_int64()
+    out = np.zeros(2 * 10)
+    assert lib.cw_refined_get_traces(h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 10,
+                                     ctypes.byref(done)) == -5
+    assert lib.cw_refined_energy(h, ctypes.byref(ctypes.c_double())) == -5
+    fld = np.zeros((4 * 4 + 5 * 8 + 7 * 16) * 64, dtype=np.float32)
+    assert lib.cw_refined_get_field(h, 0, fld.ctypes.data_as(ctypes.POINTER(ctypes.c_float))) == -5
+    assert b"bind" in lib.cw_last_error()
+    # null handles are refused, not dereferenced
+    assert lib.cw_refined_step(None, 1) == -1
+    assert lib.cw_refined_bind(h, None, 0, None) == -1
     lib.cw_refined_destroy(h)
