@@ -89,6 +89,7 @@ def measured_traffic(variant: str, kernel: str, workload: str):
 # run ends with a 1 GiB device-to-device copy whose counter readings calibrate the counters
 # (bytes the copy must move / what the counter reports for it).
 PROFILE_VARIANTS = {
+    "auto_f32": "--path auto --storage f32",
     "two_pass_f32": "--path two-pass --storage f32",
     "two_pass_f16": "--path two-pass --storage f16",
     "two_pass_bf16": "--path two-pass --storage bf16",
@@ -397,19 +398,22 @@ def run_steps(w, storage: str, path: str, warmup: int, steps: int, graph: int = 
 STREAM_MIX = {"velocity": ((10, 3), (9, 3)), "stress": ((11, 6), (9, 6)), "fused": ((12, 9), (9, 9))}
 
 
-def stream_ceiling(kernel: str, axisym: bool, roofline: dict):
+def stream_ceiling(kernel: str, axisym: bool, roofline: dict, lane_bytes: int = 16):
     """What HBM delivers to a kernel that only streams the dominant kernel's
-    read/write mix (1 GiB per array; 16 bytes per thread and array as the
-    step kernels read, and 4), and a plain 1 + 1 copy; the dominant kernel's
-    algorithmic rate as a fraction of the 16-byte figure."""
+    read/write mix (1 GiB per array; 16 bytes per thread and array, and 4),
+    and a plain 1 + 1 copy; the dominant kernel's algorithmic rate as a
+    fraction of the figure for its own access width (lane_bytes: 16 for the
+    four-cell kernels, 4 for the one-cell ones)."""
     from paper_2302_13907_amd import cwell
     r, w = STREAM_MIX[kernel][1 if axisym else 0]
     log("stream ceiling: %d reads + %d writes" % (r, w))
     mix = cwell.stream_probe(r, w) / 1e9
     mix4 = cwell.stream_probe(r, w, lane_bytes=4) / 1e9
     copy = cwell.stream_probe(1, 1) / 1e9
+    ref = mix4 if lane_bytes == 4 else mix
     return {"kernel": kernel, "reads": r, "writes": w, "GBps": round(mix, 1), "GBps_4B_lanes": round(mix4, 1),
-            "copy_GBps": round(copy, 1), "frac_of_ceiling": round(roofline["achieved"] / mix, 4)}
+            "copy_GBps": round(copy, 1), "kernel_lane_bytes": lane_bytes,
+            "frac_of_ceiling": round(roofline["achieved"] / ref, 4)}
 
 
 def graph_replay(path: str, graph: int = 20, steps: int = 300):
@@ -675,7 +679,9 @@ def main():
     axisym = w.rock_jitter == 0          # the medium is then stored once per (ring, depth)
     alg = algorithmic_bytes(dom, w, n_r, n_z, fb, axisym)
     achieved = alg / avg_s / 1e9
-    form = "fused" if dom == "fused" else ("march" if args.path == "march" else "two_pass")
+    # the default path differs from the column two-pass step only in the float32 stress kernel
+    form = ("fused" if dom == "fused" else "march" if args.path == "march"
+            else "auto" if args.path == "auto" and args.storage == "f32" else "two_pass")
     variant = "%s_%s" % (form, args.storage)
     traffic = measured_traffic(variant, dom, w.name)
     # the whole step against the single-pass floor: every field read and written once,
@@ -719,7 +725,8 @@ def main():
         del src, dst
         torch.cuda.empty_cache()
     if not args.no_stream_ceiling:
-        out["stream_ceiling"] = stream_ceiling(dom, axisym, out["roofline"])
+        one_cell = form == "auto" and dom == "stress"     # the default float32 stress kernel: one cell per thread
+        out["stream_ceiling"] = stream_ceiling(dom, axisym, out["roofline"], 4 if one_cell else 16)
     if not args.no_storage_forms:
         out["storage_forms"] = storage_forms(args.path)
     if not args.no_graph_replay:

@@ -712,6 +712,22 @@ cw_status cw_bind(cw_sim *s, void *workspace, uint64_t bytes, void *stream)
   return CW_OK;
 }
 
+// Stress kernel form of the default (CW_PATH_AUTO) two-pass step per storage
+// (bit 0 float32, bit 1 float16, bit 2 bfloat16 set: one cell per thread
+// instead of four).
+// Measured on MI355X at 256 x 128 x 8192 with non-temporal own-update
+// accesses in both forms: float32 one cell per thread 3.32 ms against 3.41
+// (four times as many threads keep more loads in flight); 16-bit storage
+// four cells per thread, 2.17 / 2.31 ms against 4.92 / 6.05 (2-byte accesses).
+#ifndef CW_STRESS_ONE_CELL
+#define CW_STRESS_ONE_CELL 1
+#endif
+static bool stress_one_cell(int storage)
+{
+  const int bit = storage == ST_F32 ? 1 : storage == ST_F16 ? 2 : 4;
+  return (CW_STRESS_ONE_CELL & bit) != 0;
+}
+
 cw_status cw_step(cw_sim *s, int64_t nsteps)
 {
   if (!s) return fail(CW_ERR_ARG, "null simulation");
@@ -743,9 +759,13 @@ cw_status cw_step(cw_sim *s, int64_t nsteps)
     return march ? launch_velocity_march(a, s->storage, s->stream)
                  : vec ? launch_velocity_vec(a, s->storage, s->stream) : launch_velocity_basic(a, s->storage, s->stream);
   };
+  // the default path takes the faster stress form; CW_PATH_TWO_PASS keeps the
+  // four-cell column kernels (the form the batched kernels reproduce bitwise)
+  const bool vec_stress = vec && !(s->path == CW_PATH_AUTO && stress_one_cell(s->storage));
   auto stress = [&](const StepArgs &a) {
     return march ? launch_stress_march(a, s->storage, s->stream)
-                 : vec ? launch_stress_vec(a, s->storage, s->stream) : launch_stress_basic(a, s->storage, s->stream);
+                 : vec_stress ? launch_stress_vec(a, s->storage, s->stream)
+                              : launch_stress_basic(a, s->storage, s->stream);
   };
   // One step's launches.  Nothing in them depends on the host's step count
   // (the injection and receiver kernels read the device counter, which the

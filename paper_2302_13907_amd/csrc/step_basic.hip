@@ -65,8 +65,10 @@ __device__ __forceinline__ int zrow(const StepArgs &a, int k)
 // psi <- b psi + a X; returns X + psi
 __device__ __forceinline__ float cpml(float *psi, size_t p, float ca, float cb, float X)
 {
-  float v = cb * psi[p] + ca * X;
-  psi[p] = v;
+  // the layer memory is read and written only by its own cell: non-temporal
+  const float v = cb * (CW_NT_OWN ? __builtin_nontemporal_load(psi + p) : psi[p]) + ca * X;
+  if (CW_NT_STORE) __builtin_nontemporal_store(v, psi + p);
+  else psi[p] = v;
   return X + v;
 }
 
@@ -151,14 +153,14 @@ __global__ void __launch_bounds__(256) k_velocity_basic(StepArgs a, int nbx)
   const float b_t = 2.0f * rcp(rho0 + a.rho[mat(a, i, jp, kk)]);
   const float b_z = 2.0f * rcp(rho0 + a.rho[mat(a, i, j, k1)]);
 
-  const float vr = S::ld(a.in[VR], p, c[VR]) + a.dt * b_r * (r_dr + r_b + r_dz);
-  const float vt = S::ld(a.in[VT], p, c[VT]) + a.dt * b_t * (t_dr + t_b + t_dz);
-  const float vz = S::ld(a.in[VZ], p, c[VZ]) + a.dt * b_z * (z_dr + z_b + z_dz);
+  const float vr = S::ldn(a.in[VR], p, c[VR]) + a.dt * b_r * (r_dr + r_b + r_dz);
+  const float vt = S::ldn(a.in[VT], p, c[VT]) + a.dt * b_t * (t_dr + t_b + t_dz);
+  const float vz = S::ldn(a.in[VZ], p, c[VZ]) + a.dt * b_z * (z_dr + z_b + z_dz);
   if (live) {
     const float *o = a.scl_out;
-    S::st(a.out[VR], p, vr, 1.0f / o[VR]);
-    S::st(a.out[VT], p, vt, 1.0f / o[VT]);
-    S::st(a.out[VZ], p, vz, 1.0f / o[VZ]);
+    S::stn(a.out[VR], p, vr, 1.0f / o[VR]);
+    S::stn(a.out[VT], p, vt, 1.0f / o[VT]);
+    S::stn(a.out[VZ], p, vz, 1.0f / o[VZ]);
   }
   if (S::scaled) {
     track_max(a.maxabs + VR * kMaxSlots, live ? vr : 0.0f);
@@ -235,19 +237,19 @@ __global__ void __launch_bounds__(256) k_stress_basic(StepArgs a, int nbx)
   const float *c = a.scl_in;
   const float tr = err + ett + ezz;
   const float lt = lam * tr, m2 = 2.0f * mu;
-  const float s_rr = S::ld(a.in[SRR], p, c[SRR]) + a.dt * (lt + m2 * err);
-  const float s_tt = S::ld(a.in[STT], p, c[STT]) + a.dt * (lt + m2 * ett);
-  const float s_zz = S::ld(a.in[SZZ], p, c[SZZ]) + a.dt * (lt + m2 * ezz);
-  const float s_rt = S::ld(a.in[SRT], p, c[SRT]) + a.dt * mu_rt * (rt_dr + rt_b);
-  const float s_rz = S::ld(a.in[SRZ], p, c[SRZ]) + a.dt * mu_rz * (rz_dr + rz_dz);
-  const float s_tz = S::ld(a.in[STZ], p, c[STZ]) + a.dt * mu_tz * (tz_b + tz_dz);
+  const float s_rr = S::ldn(a.in[SRR], p, c[SRR]) + a.dt * (lt + m2 * err);
+  const float s_tt = S::ldn(a.in[STT], p, c[STT]) + a.dt * (lt + m2 * ett);
+  const float s_zz = S::ldn(a.in[SZZ], p, c[SZZ]) + a.dt * (lt + m2 * ezz);
+  const float s_rt = S::ldn(a.in[SRT], p, c[SRT]) + a.dt * mu_rt * (rt_dr + rt_b);
+  const float s_rz = S::ldn(a.in[SRZ], p, c[SRZ]) + a.dt * mu_rz * (rz_dr + rz_dz);
+  const float s_tz = S::ldn(a.in[STZ], p, c[STZ]) + a.dt * mu_tz * (tz_b + tz_dz);
   if (live) {
-    S::st(a.out[SRR], p, s_rr, 1.0f / o[SRR]);
-    S::st(a.out[STT], p, s_tt, 1.0f / o[STT]);
-    S::st(a.out[SZZ], p, s_zz, 1.0f / o[SZZ]);
-    S::st(a.out[SRT], p, s_rt, 1.0f / o[SRT]);
-    S::st(a.out[SRZ], p, s_rz, 1.0f / o[SRZ]);
-    S::st(a.out[STZ], p, s_tz, 1.0f / o[STZ]);
+    S::stn(a.out[SRR], p, s_rr, 1.0f / o[SRR]);
+    S::stn(a.out[STT], p, s_tt, 1.0f / o[STT]);
+    S::stn(a.out[SZZ], p, s_zz, 1.0f / o[SZZ]);
+    S::stn(a.out[SRT], p, s_rt, 1.0f / o[SRT]);
+    S::stn(a.out[SRZ], p, s_rz, 1.0f / o[SRZ]);
+    S::stn(a.out[STZ], p, s_tz, 1.0f / o[STZ]);
   }
   if (S::scaled) {
     track_max(a.maxabs + SRR * kMaxSlots, live ? s_rr : 0.0f);

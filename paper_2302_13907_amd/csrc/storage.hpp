@@ -86,6 +86,16 @@ struct StF32 {
     stb4<kFieldStoreAux>(r, voff, soff, v);
   }
   __device__ static void st(float *f, size_t p, float v, float) { f[p] = v; }
+  // one value that only the thread's own update reads / one field value written
+  __device__ static float ldn(const float *f, size_t p, float)
+  {
+    return CW_NT_OWN ? __builtin_nontemporal_load(f + p) : f[p];
+  }
+  __device__ static void stn(float *f, size_t p, float v, float)
+  {
+    if (CW_NT_STORE) __builtin_nontemporal_store(v, f + p);
+    else f[p] = v;
+  }
   template <int V>
   __device__ static void ldv(float (&o)[V], const float *f, size_t p, float)
   {
@@ -142,6 +152,18 @@ struct StF16 {
   __device__ static void st(float *f, size_t p, float v, float is)
   {
     reinterpret_cast<_Float16 *>(f)[p] = (_Float16)(v * is);
+  }
+  __device__ static float ldn(const float *f, size_t p, float s)
+  {
+    const _Float16 *h = reinterpret_cast<const _Float16 *>(f) + p;
+    return (float)(CW_NT_OWN ? __builtin_nontemporal_load(h) : *h) * s;
+  }
+  __device__ static void stn(float *f, size_t p, float v, float is)
+  {
+    _Float16 *h = reinterpret_cast<_Float16 *>(f) + p;
+    const _Float16 x = (_Float16)(v * is);
+    if (CW_NT_STORE) __builtin_nontemporal_store(x, h);
+    else *h = x;
   }
   template <int V>
   __device__ static void ldv(float (&o)[V], const float *f, size_t p, float s)
@@ -213,6 +235,18 @@ struct StBF16 {
   __device__ static void st(float *f, size_t p, float v, float)
   {
     reinterpret_cast<unsigned short *>(f)[p] = pack(v);
+  }
+  __device__ static float ldn(const float *f, size_t p, float)
+  {
+    const unsigned short *h = reinterpret_cast<const unsigned short *>(f) + p;
+    return unpack(CW_NT_OWN ? __builtin_nontemporal_load(h) : *h);
+  }
+  __device__ static void stn(float *f, size_t p, float v, float)
+  {
+    unsigned short *h = reinterpret_cast<unsigned short *>(f) + p;
+    const unsigned short x = pack(v);
+    if (CW_NT_STORE) __builtin_nontemporal_store(x, h);
+    else *h = x;
   }
   template <int V>
   __device__ static void ldv(float (&o)[V], const float *f, size_t p, float)

@@ -21,7 +21,7 @@ TRACE_TOL = 1e-5
 FIELD_TOL = 1e-5
 
 
-PATHS = ["fused", "two-pass", "march"]
+PATHS = ["auto", "fused", "two-pass", "march"]
 
 
 @pytest.mark.parametrize("path", PATHS)
