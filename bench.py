@@ -606,6 +606,9 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", choices=("production", "parity"), default="production")
+    ap.add_argument("--medium", choices=("axisymmetric", "3d"), default="axisymmetric",
+                    help="production medium as specified (theta-invariant, stored once per ring and depth), "
+                         "or with the rock moduli jittered +-2 %% cell by cell (a 3-D medium)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--path", choices=("auto", "fused", "two-pass", "march"), default="auto",
@@ -664,6 +667,9 @@ def main():
         print("no HIP device visible", file=sys.stderr)
         sys.exit(1)
     w = inputs.production_case() if args.workload == "production" else inputs.parity_case()
+    if args.medium == "3d" and w.rock_jitter == 0:
+        import dataclasses
+        w = dataclasses.replace(w, rock_jitter=0.02, name=w.name + ", 3-D medium")
     log("workload %s" % w.name)
     try:
         el, times, _ = run_steps(w, args.storage, args.path, args.warmup, args.steps)
@@ -704,7 +710,9 @@ def main():
         "config": {"workload": w.name, "cells": w.cells, "grid": [w.nr, w.nt, w.nz],
                    "medium": "axisymmetric" if axisym else "3-D",
                    "cell_m": w.dr, "layer_cells": w.npml, "receivers": len(w.rec_k),
-                   "kernel_path": "two-pass" if dom != "fused" else "fused"},
+                   "kernel_path": {"fused": "fused", "march": "two-pass, radial march",
+                                   "auto": "two-pass, four-cell velocity and one-cell stress kernels"}.get(
+                                       form, "two-pass, four-cell kernels")},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "alg_bytes_per_launch": alg,
