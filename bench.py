@@ -711,7 +711,7 @@ def main():
                    "medium": "axisymmetric" if axisym else "3-D",
                    "cell_m": w.dr, "layer_cells": w.npml, "receivers": len(w.rec_k),
                    "kernel_path": {"fused": "fused", "march": "two-pass, radial march",
-                                   "auto": "two-pass, four-cell velocity and one-cell stress kernels"}.get(
+                                   "auto": "two-pass, one-cell velocity and stress kernels"}.get(
                                        form, "two-pass, four-cell kernels")},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),

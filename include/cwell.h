@@ -205,10 +205,11 @@ cw_status cw_set_storage(cw_sim *s, int32_t storage);
    memory once (float32 storage only, at most 12 source injections -- 3 per
    volume source, 2 per torsion source, 1 per force -- and nr <= 2048).
    CW_PATH_AUTO (default): the path measured fastest on MI355X: the
-   two-pass step, with the stress update one cell per thread for float32
-   storage (3 % faster per stress launch at the production size than four
-   cells per thread); otherwise exactly CW_PATH_TWO_PASS.  Results of the
-   two stress forms agree to float32 rounding. */
+   two-pass step, with the velocity and the stress update one cell per
+   thread for float32 storage (1 % and 3 % faster per launch at the
+   production size than four cells per thread); otherwise exactly
+   CW_PATH_TWO_PASS.  Results of the two kernel forms agree to float32
+   rounding. */
 enum { CW_PATH_AUTO = 0, CW_PATH_TWO_PASS, CW_PATH_FUSED, CW_PATH_MARCH };
 cw_status cw_set_path(cw_sim *s, int32_t path);
 

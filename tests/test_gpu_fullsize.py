@@ -1,6 +1,6 @@
 """Parity at the production size (256 x 128 x 8192 cells, 268 M), in the
 launch configuration the benchmark times (the default path, float32 storage:
-the four-cell velocity kernel and the one-cell stress kernel).
+the one-cell velocity and stress kernels).
 
 The oracle cannot run the whole grid, so the checks are (1) one step from
 a seeded random state, compared on whole 256 x 128 planes at sampled
