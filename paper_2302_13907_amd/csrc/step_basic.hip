@@ -74,10 +74,10 @@ __device__ __forceinline__ Cols cols(const StepArgs &a, int i, int j)
 }
 
 // Value at (i, j, k) read with bounds checks: zero beyond the axis, the
-// outer face and the top and bottom faces.  The stress update keeps this
-// form for its velocity loads: measured on MI355X at 256 x 128 x 8192
-// (float32) it runs 3.21 ms per launch against 3.27 with the column offsets
-// below, although it issues more scalar instructions.
+// outer face and the top and bottom faces.  The stress update reads its
+// depth neighbours this way: measured on MI355X at 256 x 128 x 8192
+// (float32), 3.19 ms per launch against 3.27 with the clamped loads of ldz
+// below and 3.20 with a branch on k over the column offset.
 template <class S>
 __device__ __forceinline__ float ld(const float *f, float s, const StepArgs &a, int i, int j, int k)
 {
@@ -238,19 +238,17 @@ __device__ __forceinline__ void stress_cell(const StepArgs &a, int i, int j, int
 {
   const bool live = k < a.nz;
   const int kk = live ? k : a.nz - 1;              // dead lanes compute on a valid cell, store nothing
-  const int jm = j == 0 ? a.nt - 1 : j - 1;
-  const int jp = j == a.nt - 1 ? 0 : j + 1;
   const Cols col = cols(a, i, j);
   // velocities at level n+1/2 are in the output buffer
   const float *vR = a.out[VR], *vT = a.out[VT], *vZ = a.out[VZ];
   const float *o = a.scl_out;
 
-  const float vr0 = ld<S>(vR, o[VR], a, i, j, kk), vr_im = ld<S>(vR, o[VR], a, i - 1, j, kk);
-  const float vr_jp = ld<S>(vR, o[VR], a, i, jp, kk), vr_kp = ld<S>(vR, o[VR], a, i, j, kk + 1);
-  const float vt0 = ld<S>(vT, o[VT], a, i, j, kk), vt_jm = ld<S>(vT, o[VT], a, i, jm, kk);
-  const float vt_ip = ld<S>(vT, o[VT], a, i + 1, j, kk), vt_kp = ld<S>(vT, o[VT], a, i, j, kk + 1);
-  const float vz0 = ld<S>(vZ, o[VZ], a, i, j, kk), vz_km = ld<S>(vZ, o[VZ], a, i, j, kk - 1);
-  const float vz_ip = ld<S>(vZ, o[VZ], a, i + 1, j, kk), vz_jp = ld<S>(vZ, o[VZ], a, i, jp, kk);
+  const float vr0 = ldc<S>(vR, o[VR], col.c, kk), vr_im = ldr<S>(vR, o[VR], col.im_in, col.im, kk);
+  const float vr_jp = ldc<S>(vR, o[VR], col.jp, kk), vr_kp = ld<S>(vR, o[VR], a, i, j, kk + 1);
+  const float vt0 = ldc<S>(vT, o[VT], col.c, kk), vt_jm = ldc<S>(vT, o[VT], col.jm, kk);
+  const float vt_ip = ldr<S>(vT, o[VT], col.ip_in, col.ip, kk), vt_kp = ld<S>(vT, o[VT], a, i, j, kk + 1);
+  const float vz0 = ldc<S>(vZ, o[VZ], col.c, kk), vz_km = ld<S>(vZ, o[VZ], a, i, j, kk - 1);
+  const float vz_ip = ldr<S>(vZ, o[VZ], col.ip_in, col.ip, kk), vz_jp = ldc<S>(vZ, o[VZ], col.jp, kk);
 
   const float irc = a.inv_rc[i], irf = a.inv_rf[i];
   float err = (vr0 - vr_im) * a.inv_dr;
