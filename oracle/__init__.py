@@ -34,6 +34,10 @@ ORACLE_PINS = {
         "tests/test_oracle_pins.py::test_operators_skew_adjoint",
     "leapfrog ordering + material averaging: energy conservation":
         "tests/test_oracle_pins.py::test_energy_conserved",
+    "staggered material averages (face buoyancy, harmonic edge shear modulus, clamp and wrap): hand-derived values":
+        "tests/test_oracle_averages.py::test_coefficient_tables_match_hand_values",
+    "the step applies those averages: one-step impulse responses against the hand-derived values":
+        "tests/test_oracle_averages.py::test_step_applies_hand_values",
     "theta stencils and periodic wrap: axisymmetric invariance":
         "tests/test_oracle_pins.py::test_theta_invariance_bitwise",
     "P-SV / SH decoupling of axisymmetric sources":

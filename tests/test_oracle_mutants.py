@@ -6,14 +6,12 @@ normalisation), built with gcc in a temporary directory.  The oracle's pins
 test modules) run against the mutant, cheapest first, and at least one of
 them must reject it.  The oracle itself is untouched.
 
-Two choices on which the paper is silent have no pin that tells them from a
-plausible alternative, and are listed in NO_PIN instead: the face density as
-the mean of the two adjacent cells and the shear modulus of an edge node as
-the harmonic mean of its four cells (the standard staggered-grid rules).
-Either alternative keeps the scheme symmetric (energy, reciprocity,
-skew-adjointness and the transposed step all still hold) and changes results
-only where the medium jumps, at second order in the cell size; the GPU
-parity tests hold the HIP path to the rule the oracle takes."""
+The staggered material averages (the face density as the mean of the two
+adjacent cells, the shear modulus of an edge node as the harmonic mean of its
+four cells) keep the scheme symmetric under the plausible alternatives
+written here (energy, reciprocity, skew-adjointness and the transposed step
+all still hold), so the physics pins cannot see them; the hand-derived
+coefficient values of ``test_oracle_averages`` reject them."""
 import concurrent.futures
 import gc
 import os
@@ -93,16 +91,15 @@ MUTANTS = {
     "Ricker pulse delayed by 1/f0 instead of 2/f0": (
         "double tau = t - 2.0 / f0;",
         "double tau = t - 1.0 / f0;"),
-}
-
-# readings that no pin separates from the alternative written here (see above)
-NO_PIN = {
     "face density from the theta neighbour instead of the depth neighbour": (
         "s->b_z[p] = 2.0 / (rho[p] + rho[IDX(s, i, j, k1)]);",
         "s->b_z[p] = 2.0 / (rho[p] + rho[IDX(s, i, j1, k)]);"),
     "edge shear modulus as the arithmetic mean of the four cells": (
         "  return 4.0 / (1.0 / a + 1.0 / b + 1.0 / c + 1.0 / d);",
         "  return 0.25 * (a + b + c + d);"),
+    "azimuthal neighbour of the averages clamped instead of wrapped": (
+        "int j1 = (j + 1) % s->nt;",
+        "int j1 = j + 1 < s->nt ? j + 1 : s->nt - 1;"),
 }
 
 # The pin that rejected each mutant when this table was written, for the
@@ -127,10 +124,14 @@ FIRST_PIN = {
 def _pins():
     """(name, callable) of the oracle pins, cheapest first."""
     import test_oracle_adjoint as ta
+    import test_oracle_averages as tav
     import test_oracle_physics as tph
     import test_oracle_pins as tp
     pins = [("Ricker zeros and extrema", tp.test_ricker_properties),
-            ("energy conservation", tp.test_energy_conserved)]
+            ("hand-derived staggered averages", tav.test_coefficient_tables_match_hand_values)]
+    pins += [("impulse response applies the averages, %s" % c, (lambda cc=c: tav.test_step_applies_hand_values(cc)))
+             for c in sorted(tav.IMPULSE)]
+    pins += [("energy conservation", tp.test_energy_conserved)]
     pins += [("skew-adjointness %s" % (shape,), (lambda sh=shape: tp.test_operators_skew_adjoint(sh)))
              for shape in [(6, 8, 7), (5, 1, 9), (3, 2, 4)]]
     pins += [("transposed step, layer %s" % layer, (lambda ly=layer: ta.test_adjoint_step_is_the_transpose(ly)))
@@ -169,7 +170,7 @@ def _build(tmpdir, name, mutation):
 @pytest.fixture(scope="module")
 def mutant_libs(tmp_path_factory):
     d = str(tmp_path_factory.mktemp("oracle_mutants"))
-    todo = dict(MUTANTS, **NO_PIN)
+    todo = dict(MUTANTS)
     with concurrent.futures.ThreadPoolExecutor(max_workers=4) as ex:
         futs = {n: ex.submit(_build, d, n, m) for n, m in todo.items()}
         return {n: f.result() for n, f in futs.items()}
@@ -204,7 +205,7 @@ def test_sources_are_unique_and_the_original_passes():
     """Every planted text occurs exactly once, and the unmutated source
     passes the cheap pins (so a rejection is the mutation's doing)."""
     src = open(SRC).read()
-    for name, m in dict(MUTANTS, **NO_PIN).items():
+    for name, m in MUTANTS.items():
         for orig, repl in _edits(m):
             assert src.count(orig) == 1 and orig != repl, name
     pin_names = {n for n, _ in _pins()}

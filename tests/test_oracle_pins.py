@@ -430,4 +430,4 @@ def test_ricker_properties():
     freqs = np.fft.rfftfreq(1 << 22, dt)
     assert abs(freqs[np.argmax(spec)] - f0) < 0.002 * f0
     # t = 0 is (almost) at rest: the printed delay puts the onset before the peak
-    assert abs(oracle.ricker(f0, 0.0)[0]) < 1e-15 * 1e20
+    assert abs(oracle.ricker(f0, 0.0)[0]) < 1e-15
