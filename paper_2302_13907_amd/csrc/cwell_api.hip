@@ -101,6 +101,7 @@ struct cw_sim {
   int path = CW_PATH_AUTO;
   int storage = ST_F32;
   float *d_scl = nullptr;       // [3][NF]: scale of buffer 0, buffer 1, next write
+  float scl_init[3 * NF] = {};  // host copy of the scales zero_state starts from
   unsigned *d_maxabs = nullptr; // [NF][kMaxSlots]
   Inject *d_inject = nullptr;
   int ninject = 0;
@@ -387,10 +388,24 @@ cw_status zero_state(cw_sim *s)
 {
   const Layout L = layout(s);
   HIPCHK(hipMemsetAsync(s->ws + L.fields, 0, 2 * NF * s->n_alloc() * field_bytes(s), s->stream));
-  // every scale 1, no maxima yet (pageable source: the caller synchronizes)
-  static const float ones[3 * NF] = {1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1,
-                                     1, 1, 1, 1, 1, 1, 1, 1, 1};
-  HIPCHK(hipMemcpyAsync(s->d_scl, ones, sizeof ones, hipMemcpyHostToDevice, s->stream));
+  // Every buffer scale 1, no maxima yet.  The first write of a field a source
+  // injects into takes the scale its largest injected value needs (the rule
+  // of the per-step rescale), so a large or abrupt pulse cannot overflow
+  // float16 before the scale has adapted; other fields start at 1 and adapt
+  // from the values they first receive.  (Kept in the simulation: the copy
+  // source must outlive the asynchronous copy.)
+  float peak[NF] = {};
+  for (size_t e = 0; e < s->inject_host.size(); e++)
+    for (float a : s->inject_amp[e])
+      peak[s->inject_host[e].field] = std::max(peak[s->inject_host[e].field], std::fabs(s->inject_host[e].scale * a));
+  for (int q = 0; q < 3 * NF; q++) s->scl_init[q] = 1.0f;
+  for (int q = 0; q < NF; q++)
+    if (peak[q] > 0.0f) {
+      int ex;
+      std::frexp(peak[q], &ex);
+      s->scl_init[2 * NF + q] = std::ldexp(1.0f, ex - kF16TargetExp);
+    }
+  HIPCHK(hipMemcpyAsync(s->d_scl, s->scl_init, sizeof s->scl_init, hipMemcpyHostToDevice, s->stream));
   HIPCHK(hipMemsetAsync(s->d_maxabs, 0, NF * kMaxSlots * sizeof(unsigned), s->stream));
   const size_t psir = 2 * (size_t)NPSI_R * s->npr * s->nt * s->nz * sizeof(float);
   const size_t psiz = 2 * (size_t)NPSI_Z * s->nr * s->nt * nzs_of(s) * sizeof(float);

@@ -1,33 +1,67 @@
-"""The thin-well gradient case shared by the oracle and GPU adjoint tests:
-a hole of 20 mm, casing to 30 mm and cement to 50 mm (so the wave reaches
-the cement within a short run), 20 x 8 x 96 cells of 5 mm, a 40 kHz volume
-source on the axis above a cement top with a 0.1 m shear ramp, 12 axis
-pressure receivers, 400 steps, loss over steps [150, 400), parameters on 8
-bins of 2 rows of the annulus below the cement top."""
+"""Gradient cases shared by the oracle and GPU adjoint tests.
+
+THIN: a hole of 20 mm, casing to 30 mm and cement to 50 mm (so the wave
+reaches the cement within a short run), 20 x 8 x 96 cells of 5 mm, a 40 kHz
+volume source on the axis above a cement top with a 0.1 m shear ramp, 12
+axis pressure receivers, 400 steps, loss over steps [150, 400), parameters
+on 8 bins of 2 rows of the annulus below the cement top.
+
+CROP: the adjoint workload's correctness crop, with the standard well radii
+(hole 0.10 m, casing 0.11 m, cement 0.15 m): 48 x 32 x 256 cells of 5 mm,
+4000 steps at half the Courant limit (648 us), a 10-cell layer, a 15 kHz
+volume source on the axis at z = 0.30 m, the cement top at z = 0.60 m with a
+0.32 m (64-row) shear ramp, 32 axis pressure receivers every 10 mm from
+z = 0.35 m, loss over steps [2000, 4000) (after the two-way time from the
+source to the cement top and back), parameters on the 64 one-row bins of
+the annulus (rings 22..29) from the first row below the top."""
 import math
+from dataclasses import dataclass, field
+from typing import List, Optional, Tuple
 
 import numpy as np
 
 import oracle
 from paper_2302_13907_amd import inputs
 
-H = 5e-3
-SHAPE = (20, 8, 96)
-RADII = (0.02, 0.03, 0.05)
-KTOP = 48
-STEPS = 400
-WINDOW = (150, 400)
-REGION = (6, 10, KTOP + 1, 8, 2)      # annulus rings 6..9, 8 bins of 2 rows below the cement top
-NPML = 6
-F0 = 40e3
-SRC_K = 40
-REC_K = list(range(20, 44, 2))
+
+@dataclass(frozen=True)
+class Case:
+    shape: Tuple[int, int, int]
+    h: float
+    radii: Tuple[float, float, float]
+    ktop: int
+    ramp: float
+    steps: int
+    window: Tuple[int, int]
+    region: Tuple[int, int, int, int, int]   # (i0, i1, k0, bins, rows per bin)
+    npml: int
+    f0: float
+    src_k: int
+    rec_k: Tuple[int, ...]
 
 
-def medium(dmu=None, dK=None, shape=SHAPE, rock_jitter=0.0):
-    rho, lam, mu = inputs.cased_well(*shape, H, H, z_top=KTOP * H, ramp=0.1, radii=RADII, rock_jitter=rock_jitter)
+THIN = Case(shape=(20, 8, 96), h=5e-3, radii=(0.02, 0.03, 0.05), ktop=48, ramp=0.1, steps=400,
+            window=(150, 400), region=(6, 10, 49, 8, 2), npml=6, f0=40e3, src_k=40,
+            rec_k=tuple(range(20, 44, 2)))
+
+CROP = Case(shape=(48, 32, 256), h=5e-3, radii=(inputs.R_HOLE, inputs.R_CASING, inputs.R_CEMENT), ktop=120,
+            ramp=0.32, steps=4000, window=(2000, 4000), region=(22, 30, 121, 64, 1), npml=10, f0=15e3,
+            src_k=60, rec_k=tuple(70 + 2 * m for m in range(32)))
+
+# the thin-well case's names, as the tests first used them
+H, SHAPE, RADII, KTOP = THIN.h, THIN.shape, THIN.radii, THIN.ktop
+STEPS, WINDOW, REGION, NPML, F0, SRC_K, REC_K = (THIN.steps, THIN.window, THIN.region, THIN.npml, THIN.f0,
+                                                  THIN.src_k, list(THIN.rec_k))
+
+
+def medium(dmu=None, dK=None, shape=None, rock_jitter=0.0, case: Case = THIN):
+    """rho, lambda, mu of the case, with the region's bins shifted by dmu and
+    dK (mu and K = lambda + 2 mu / 3 of every cell of a bin)."""
+    shape = shape or case.shape
+    rho, lam, mu = inputs.cased_well(*shape, case.h, case.h, z_top=case.ktop * case.h, ramp=case.ramp,
+                                     radii=case.radii, rock_jitter=rock_jitter)
     if dmu is not None:
-        i0, i1, k0, nb, br = REGION
+        i0, i1, k0, nb, br = case.region
         K = lam + 2.0 * mu / 3.0
         for b in range(nb):
             sl = (slice(i0, i1), slice(None), slice(k0 + b * br, k0 + (b + 1) * br))
@@ -37,13 +71,23 @@ def medium(dmu=None, dK=None, shape=SHAPE, rock_jitter=0.0):
     return rho, lam, mu
 
 
-def oracle_sim(med, dt=None, shape=SHAPE):
-    o = oracle.OracleSim(*shape, H, H)
+def oracle_sim(med, dt=None, shape=None, case: Case = THIN):
+    shape = shape or case.shape
+    o = oracle.OracleSim(*shape, case.h, case.h)
     o.set_material(*med)
-    o.set_pml(NPML, NPML, 1e-3, math.pi * F0)
+    o.set_pml(case.npml, case.npml, 1e-3, math.pi * case.f0)
     dt = dt or 0.5 * o.cfl_dt()
     o.set_dt(dt)
-    o.add_source("volume", 0, -1, SRC_K, oracle.ricker(F0, (np.arange(STEPS) + 0.5) * dt))
-    for k in REC_K:
+    o.add_source("volume", 0, -1, case.src_k, oracle.ricker(case.f0, (np.arange(case.steps) + 0.5) * dt))
+    for k in case.rec_k:
         o.add_receiver("pressure", 0, -1, k)
     return o, dt
+
+
+def bin_moduli(case: Case):
+    """(mu, K) of each bin of the case's region (the bins are uniform)."""
+    rho, lam, mu = medium(case=case)
+    i0, i1, k0, nb, br = case.region
+    m = np.array([mu[i0, 0, k0 + b * br] for b in range(nb)])
+    K = np.array([lam[i0, 0, k0 + b * br] + 2.0 * mu[i0, 0, k0 + b * br] / 3.0 for b in range(nb)])
+    return m, K

@@ -114,6 +114,33 @@ def field_errors(got: dict, ref: dict) -> dict:
     return out
 
 
+def field_max_errors(got: dict, ref: dict) -> dict:
+    """Per-field largest |gpu - oracle| over every cell, divided by the
+    largest |value| of the field's group (velocities, stresses) in the
+    oracle.  A group the oracle holds at exactly zero everywhere gives inf
+    unless the device holds it at exactly zero too (then 0)."""
+    out = {}
+    for group in (VEL, STRESS):
+        scale = max(float(np.abs(ref[n]).max()) for n in group)
+        for n in group:
+            d = float(np.abs(got[n].astype(np.float64) - ref[n]).max())
+            out[n] = d / scale if scale > 0 else (0.0 if d == 0 else math.inf)
+    return out
+
+
+def check_fields(got: dict, ref: dict, tol: float, tag: str = ""):
+    """Fields within tol of the oracle twice over: the per-field RMS error
+    over the group's RMS (field_errors), and cell by cell against the group's
+    largest magnitude (field_max_errors), so a wrong value in one corner of
+    the layer or one axis cell cannot hide in a norm."""
+    fe = field_errors(got, ref)
+    fm = field_max_errors(got, ref)
+    announce("  %sfield errors: rms worst %.2e (%s), per cell worst %.2e (%s)"
+             % (tag, max(fe.values()), max(fe, key=fe.get), max(fm.values()), max(fm, key=fm.get)))
+    assert max(fe.values()) <= tol, fe
+    assert max(fm.values()) <= tol, fm
+
+
 def parity_scenario() -> Scenario:
     w = inputs.parity_case()
     return Scenario(shape=(w.nr, w.nt, w.nz), h=(w.dr, w.dz), medium=w.medium(), steps=w.steps,

@@ -1,10 +1,14 @@
 """GPU adjoint gradient (float32 arithmetic, float64 accumulation of the
-gradient) against the FP64 oracle's adjoint gradient on the thin-well case;
-independence of the checkpoint spacing; the torch.autograd wrapper.
+gradient) against the FP64 oracle's adjoint gradient on the thin-well case
+and on the adjoint workload's correctness crop; independence of the
+checkpoint spacing; the torch.autograd wrapper.
 
-Measured on MI355X: loss relative error 1.1e-7, per-bin gradient relative
-error (bins above 1e-3 of the largest) 4.6e-6; the bound asserted is 1e-4."""
+Measured on MI355X (thin well): loss relative error 1.1e-7, per-bin gradient
+relative error (bins above 1e-3 of the largest) 4.6e-6; the bound asserted
+is 1e-4."""
+import json
 import math
+import os
 
 import numpy as np
 import pytest
@@ -19,15 +23,16 @@ pytestmark = pytest.mark.gpu
 GRAD_TOL = 1e-4
 
 
-def _gpu_sim(dt, every, shape=C.SHAPE, rock_jitter=0.0):
-    s = cwell.Sim(*shape, C.H, C.H)
-    s.set_material(*C.medium(shape=shape, rock_jitter=rock_jitter))
-    s.set_pml(C.NPML, C.NPML, 1e-3, math.pi * C.F0)
+def _gpu_sim(dt, every, shape=None, rock_jitter=0.0, case=C.THIN):
+    shape = shape or case.shape
+    s = cwell.Sim(*shape, case.h, case.h)
+    s.set_material(*C.medium(shape=shape, rock_jitter=rock_jitter, case=case))
+    s.set_pml(case.npml, case.npml, 1e-3, math.pi * case.f0)
     s.set_dt(dt)
-    s.add_source("volume", 0, -1, C.SRC_K, cwell.ricker(C.F0, (np.arange(C.STEPS) + 0.5) * dt))
-    for k in C.REC_K:
+    s.add_source("volume", 0, -1, case.src_k, cwell.ricker(case.f0, (np.arange(case.steps) + 0.5) * dt))
+    for k in case.rec_k:
         s.add_receiver("pressure", 0, -1, k)
-    s.set_adjoint(C.STEPS, every, C.REGION)
+    s.set_adjoint(case.steps, every, case.region)
     s.bind()
     return s
 
@@ -104,3 +109,34 @@ def test_autograd_wrapper():
     s.set_region_moduli(np.zeros(nb), np.zeros(nb))
     assert s.gradient(C.WINDOW)[0] == L0
     s.close()
+
+
+CROP_GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "adjoint_crop_48x32x256.json")
+CROP_TOL = 1e-4
+
+
+def test_crop_gradient_matches_oracle():
+    """The adjoint workload's correctness crop (48 x 32 x 256 cells of 5 mm,
+    4000 steps, checkpoints every 100, 128 parameters on the 64 one-row bins
+    of the cement ramp): the GPU loss and gradient against the FP64 oracle's,
+    stored by tests/golden/make_adjoint_crop.py (which calls only the
+    oracle).  Bins whose oracle gradient is above 1e-3 of the largest are
+    held to CROP_TOL relative error; every bin to CROP_TOL of the largest."""
+    g = json.load(open(CROP_GOLDEN))
+    case = C.CROP
+    assert g["case"]["shape"] == list(case.shape) and g["case"]["region"] == list(case.region)
+    assert g["case"]["window"] == list(case.window) and g["case"]["steps"] == case.steps
+    announce("adjoint crop 48x32x256, 4000 steps, checkpoints every 100")
+    s = _gpu_sim(g["dt"], 100, case=case)
+    Lg, gmg, gkg = s.gradient(case.window)
+    s.close()
+    L = g["loss"]
+    announce("  loss gpu %.9g oracle %.9g (rel %.2e)" % (Lg, L, abs(Lg - L) / L))
+    assert abs(Lg - L) <= CROP_TOL * L
+    for name, a, b in (("mu", gmg, np.array(g["dL_dmu"])), ("K", gkg, np.array(g["dL_dK"]))):
+        big = np.abs(b) > 1e-3 * np.abs(b).max()
+        err = np.abs(a - b)[big] / np.abs(b)[big]
+        announce("  dL/d%s: worst relative error %.2e over %d bins; worst against the largest %.2e"
+                 % (name, err.max(), big.sum(), np.abs(a - b).max() / np.abs(b).max()))
+        assert err.max() <= CROP_TOL, (name, err.max())
+        assert np.all(np.abs(a - b) <= CROP_TOL * np.abs(b).max()), name

@@ -1,7 +1,8 @@
 """Batched steps: simulations of different sizes, media, sources and
 receivers advanced by one velocity and one stress launch per step give
 bitwise the results of stepping each alone (two-pass path), with every tile
-shape, in several calls, and under graph replay."""
+shape, in several calls, and under graph replay; instances stepped in a
+batch match the FP64 oracle run on the same inputs."""
 import math
 
 import numpy as np
@@ -9,7 +10,7 @@ import pytest
 
 from paper_2302_13907_amd import cwell, inputs
 
-from gpu_common import FIELDS, announce
+from gpu_common import FIELDS, Scenario, announce, check_fields, make_sim, rel_l2, run_oracle
 
 pytestmark = pytest.mark.gpu
 
@@ -133,3 +134,45 @@ def test_autotuner_caches_its_choice(tmp_path, monkeypatch):
     # a second request is answered from the cache, without measuring
     monkeypatch.setattr(autotune, "measure", lambda *a, **k: (_ for _ in ()).throw(AssertionError("measured")))
     assert autotune.best_tile(12, 4, 200, cache=cache) == tz
+
+
+def test_batch_instances_match_oracle():
+    """Two instances of one batch against the FP64 oracle on the same inputs:
+    traces within 1e-5 relative L2, fields within 1e-5 (RMS and cell by
+    cell).  One has a ragged depth (100 cells: the last 256-cell wavefront
+    group of each column ends after 25 of its 64 lanes) and an axisymmetric
+    medium; the other a 3-D medium (rock moduli jittered cell by cell) and
+    a theta count that is not a multiple of the tile's rows."""
+    h = 5e-3
+    specs = []
+    for shape, jitter, tile in (((30, 8, 100), 0.0, 4), ((36, 6, 136), 0.02, 1)):
+        nr, nt, nz = shape
+        med = inputs.cased_well(*shape, h, h, z_top=nz * h / 2, ramp=0.05, rock_jitter=jitter)
+        srcs = [("volume", 0, -1, nz // 3, 1.0), ("force_z", 3, nt - 1, nz // 2, 1e-3),
+                ("torsion", 21, -1, nz // 3 + 4, 1.0)]
+        recs = [("pressure", 0, -1, k, None) for k in range(4, nz - 4, nz // 8)]
+        recs += [("field", 2, 1, nz // 3 + 2, f) for f in FIELDS]
+        specs.append((Scenario(shape=shape, h=(h, h), medium=med, steps=160, npml=(6, 6), f0=20e3,
+                               sources=srcs, receivers=recs, path="two-pass"), tile))
+    sims = [make_sim(sc) for sc, _ in specs]
+    b = cwell.Batch(sims)
+    for q, (_, tile) in enumerate(specs):
+        b.set_tile(q, tile)
+    b.bind()
+    b.step(70)
+    b.step(90)
+    for q, ((sc, _), s) in enumerate(zip(specs, sims)):
+        announce("batched instance %d %s against the oracle" % (q, sc.shape))
+        s.sync()
+        tr_g = s.traces()
+        f_g = {n: s.field(n) for n in FIELDS}
+        tr_o, f_o = run_oracle(sc)
+        press = [m for m, r in enumerate(sc.receivers) if r[0] == "pressure"]
+        assert np.abs(tr_o[press]).max() > 0
+        e = rel_l2(tr_g[press], tr_o[press])
+        announce("  pressure traces relL2 %.2e" % e)
+        assert e <= 1e-5, e
+        check_fields(f_g, f_o, 1e-5)
+    b.close()
+    for s in sims:
+        s.close()

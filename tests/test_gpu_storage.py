@@ -133,3 +133,34 @@ def test_f16_refuses_fused_path():
     s.step(2)
     assert s.steps_done == 2
     s.close()
+
+
+def test_f16_abrupt_large_source_stays_finite():
+    """A step-onset volume source of strength 3e9: its first injected stress
+    (about 1e10) is far above float16's largest finite value at the initial
+    scale 1.  The first write of each field a source injects into takes the
+    scale its largest injected value needs, so the float16 run stays finite
+    and follows the float32 run."""
+    shape, h, steps = (24, 8, 64), 5e-3, 80
+    med = inputs.cased_well(*shape, h, h, z_top=0.16, rock_jitter=0.02)
+    out = {}
+    for storage in ("f16", "f32"):
+        s = cwell.Sim(*shape, h, h)
+        s.set_material(*med)
+        s.set_pml(5, 5, 1e-3, math.pi * 20e3)
+        s.set_dt(0.5 * s.cfl_dt())
+        s.add_source("volume", 0, -1, 20, np.full(steps, 3e9))
+        for k in (21, 24, 30, 40):
+            s.add_receiver("pressure", 0, -1, k)
+        s.set_trace_capacity(steps)
+        s.set_storage(storage)
+        s.bind()
+        s.step(steps)
+        s.sync()
+        out[storage] = (s.traces(), s.field("szz"))
+        s.close()
+    tr16, tr32 = out["f16"][0], out["f32"][0]
+    announce("abrupt 3e9 source: max |p| %.3e, float16 vs float32 %.2e" % (np.abs(tr32).max(), rel_l2(tr16, tr32)))
+    assert np.all(np.isfinite(tr16)) and np.all(np.isfinite(out["f16"][1]))
+    assert np.abs(tr32).max() > 1e9
+    assert rel_l2(tr16, tr32) <= 1e-2

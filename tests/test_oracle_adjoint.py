@@ -89,3 +89,80 @@ def _well_conditioned(fd, h, L):
     magnitude above the float64 rounding of the loss itself, so the check
     measures the gradient, not rounding noise."""
     assert abs(fd) * 2 * h >= 1e6 * np.finfo(np.float64).eps * L, (fd, h, L)
+
+
+# ---- the adjoint workload's correctness crop (48 x 32 x 256, 4000 steps)
+import json
+import os
+
+import adjoint_case as AC
+
+CROP_GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "adjoint_crop_48x32x256.json")
+
+
+def _crop_golden():
+    with open(CROP_GOLDEN) as f:
+        return json.load(f)
+
+
+def test_crop_golden_is_for_the_crop_case():
+    """The stored oracle gradient of the crop belongs to the crop as
+    tests/adjoint_case.py defines it, at half the oracle's Courant limit."""
+    g = _crop_golden()
+    c = AC.CROP
+    want = {"shape": list(c.shape), "h": c.h, "radii": list(c.radii), "ktop": c.ktop, "ramp": c.ramp,
+            "steps": c.steps, "window": list(c.window), "region": list(c.region), "npml": c.npml,
+            "f0": c.f0, "src_k": c.src_k, "rec_k": list(c.rec_k)}
+    assert g["case"] == want
+    o = oracle.OracleSim(*c.shape, c.h, c.h)
+    o.set_material(*AC.medium(case=c))
+    assert g["dt"] == 0.5 * o.cfl_dt()
+    nb = c.region[3]
+    assert len(g["dL_dmu"]) == nb and len(g["dL_dK"]) == nb and g["loss"] > 0
+
+
+def test_crop_gradient_agrees_with_finite_differences():
+    """On the crop, the oracle's adjoint gradient agrees with central finite
+    differences of the oracle's forward loss (step 1e-4 of the bin's own
+    modulus) for two shear and two bulk parameters, each difference well
+    above the float64 rounding of the loss; the relative sensitivities
+    |dL/dtheta| |theta| / L of those bins exceed 1e-4, so the check is well
+    conditioned.  Both sides were computed by tests/golden/make_adjoint_crop.py
+    (about 15 minutes of oracle time); CWELL_LONG_ORACLE=1 repeats the
+    computation in test_crop_oracle_reproduces_golden."""
+    g = _crop_golden()
+    L = g["loss"]
+    assert len(g["finite_differences"]) == 4
+    for e in g["finite_differences"]:
+        b = e["bin"]
+        adj = (g["dL_dmu"] if e["modulus"] == "mu" else g["dL_dK"])[b]
+        theta = (g["bin_mu"] if e["modulus"] == "mu" else g["bin_K"])[b]
+        assert abs(e["step"] / theta - 1e-4) < 1e-12
+        assert math.isclose(e["fd"], (e["loss_plus"] - e["loss_minus"]) / (2 * e["step"]), rel_tol=1e-15)
+        assert abs(adj - e["fd"]) <= 1e-5 * abs(e["fd"]), (e, adj)
+        _well_conditioned(e["fd"], e["step"], L)
+        assert abs(adj) * theta / L > 1e-4, (e, adj * theta / L)
+
+
+@pytest.mark.skipif(not os.environ.get("CWELL_LONG_ORACLE"),
+                    reason="about 15 minutes of oracle time; set CWELL_LONG_ORACLE=1")
+def test_crop_oracle_reproduces_golden():
+    """The oracle recomputes the stored crop gradient and one of the stored
+    finite differences."""
+    g = _crop_golden()
+    c = AC.CROP
+    o, dt = AC.oracle_sim(AC.medium(case=c), case=c)
+    L, gm, gk = o.gradient(c.steps, c.window, c.region)
+    assert math.isclose(L, g["loss"], rel_tol=1e-12)
+    assert np.allclose(gm, g["dL_dmu"], rtol=1e-10, atol=1e-10 * np.abs(gm).max())
+    assert np.allclose(gk, g["dL_dK"], rtol=1e-10, atol=1e-10 * np.abs(gk).max())
+    e = g["finite_differences"][0]
+    nb = c.region[3]
+    d = np.zeros(nb)
+    d[e["bin"]] = e["step"]
+    z = np.zeros(nb)
+    args = (d, z) if e["modulus"] == "mu" else (z, d)
+    o2, _ = AC.oracle_sim(AC.medium(*args, case=c), dt, case=c)
+    tr = o2.run(c.steps)
+    lp = float((tr[:, c.window[0]:c.window[1]] ** 2).sum())
+    assert math.isclose(lp, e["loss_plus"], rel_tol=1e-12)
