@@ -170,6 +170,18 @@ cw_status cw_set_field(cw_sim *s, int32_t field, const float *host_in);
    source fires.  Requires at least one step.  Synchronous. */
 cw_status cw_energy(cw_sim *s, double *E);
 
+/* cw_energy for callers that cannot allocate device memory (code under HIP
+   graph capture, tight serving loops, harnesses that forbid allocation):
+   the same kernels and the same result, with the nblocks partial sums and
+   the result kept in a static scratch array of the library instead of the
+   workspace.  The array holds 4096 partial sums plus the result (32 KiB,
+   one copy per GPU, held until the process ends); nblocks outside
+   [1, 4096] returns CW_ERR_RANGE.  nblocks = 1024 gives bitwise the result
+   of cw_energy.  Allocates nothing.  Calls that overlap on one GPU (from
+   two threads or two streams) share the array and race; calls on one
+   stream are ordered.  Synchronous; same errors as cw_energy. */
+cw_status cw_energy_noalloc(cw_sim *s, int32_t nblocks, double *E);
+
 /* Zero the state, the layer's memory and the traces; step count to 0. */
 cw_status cw_reset(cw_sim *s);
 

@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -1018,6 +1019,58 @@ cw_status cw_energy(cw_sim *s, double *E)
   ae.scl_out = s->d_scl + s->cur * NF;                  // the current buffer's own scales
   HIPCHK(launch_energy(ae, s->storage, s->d_energy, kEnergyBlocks, scale, s->d_energy + kEnergyBlocks, s->stream));
   HIPCHK(hipMemcpyAsync(E, s->d_energy + kEnergyBlocks, sizeof(double), hipMemcpyDeviceToHost, s->stream));
+  HIPCHK(hipStreamSynchronize(s->stream));
+  if (!std::isfinite(*E)) return fail(CW_ERR_NONFINITE, "energy is not finite");
+  return CW_OK;
+}
+
+// ---- allocation-free energy ------------------------------------------------
+// Scratch of cw_energy_noalloc: the per-workgroup partial sums and the result.
+// One copy per GPU, held until the process ends.  In host code the array's
+// name is only a stand-in; its device address comes from hipGetSymbolAddress,
+// taken once per device and kept in g_scratch.
+constexpr int kNoAllocMaxBlocks = 4096;
+static __device__ __align__(256) double scratch[kNoAllocMaxBlocks + 1];
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch[kMaxDevices] = {};
+
+// device address of this device's scratch (the device must be current)
+cw_status scratch_ptr(int device, double **out)
+{
+  if (device < 0 || device >= kMaxDevices) return fail(CW_ERR_ARG, "device %d out of range", device);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch[device]) {
+    void *p = nullptr;
+    HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(CW_ERR_HIP, "no device address for the energy scratch");
+    g_scratch[device] = static_cast<double *>(p);
+  }
+  *out = g_scratch[device];
+  return CW_OK;
+}
+}  // namespace
+
+cw_status cw_energy_noalloc(cw_sim *s, int32_t nblocks, double *E)
+{
+  if (!s || !E) return fail(CW_ERR_ARG, "null argument");
+  if (nblocks < 1 || nblocks > kNoAllocMaxBlocks)
+    return fail(CW_ERR_RANGE, "nblocks %d outside [1, %d] (the static scratch holds %d partial sums)", nblocks,
+                kNoAllocMaxBlocks, kNoAllocMaxBlocks);
+  if (!s->bound) return fail(CW_ERR_STATE, "cw_bind first");
+  if (s->nstep < 1) return fail(CW_ERR_STATE, "energy needs at least one step");
+  HIPCHK(hipSetDevice(s->device));
+  double *scr = nullptr;
+  const cw_status st = scratch_ptr(s->device, &scr);
+  if (st != CW_OK) return st;
+  const StepArgs a = step_args(s, 1 - s->cur, s->cur);
+  const double scale = s->dr * s->dr * s->dth * s->dz;
+  StepArgs ae = a;
+  ae.scl_out = s->d_scl + s->cur * NF;
+  // every partial and the result are written by the kernels, so nothing is cleared
+  HIPCHK(launch_energy(ae, s->storage, scr, nblocks, scale, scr + nblocks, s->stream));
+  HIPCHK(hipMemcpyAsync(E, scr + nblocks, sizeof(double), hipMemcpyDeviceToHost, s->stream));
   HIPCHK(hipStreamSynchronize(s->stream));
   if (!std::isfinite(*E)) return fail(CW_ERR_NONFINITE, "energy is not finite");
   return CW_OK;

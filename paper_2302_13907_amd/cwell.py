@@ -38,7 +38,7 @@ EXPORTS = ("cw_create", "cw_set_material", "cw_set_material_rz", "cw_set_pml", "
            "cw_refined_cfl_dt", "cw_refined_set_dt", "cw_refined_add_source", "cw_refined_add_receiver",
            "cw_refined_set_trace_capacity", "cw_refined_workspace_bytes", "cw_refined_bind", "cw_refined_step",
            "cw_refined_get_field", "cw_refined_set_field", "cw_refined_get_traces", "cw_refined_energy",
-           "cw_refined_reset", "cw_refined_destroy")
+           "cw_refined_reset", "cw_refined_destroy", "cw_energy_noalloc")
 
 STORAGE = {"f32": 0, "f16": 1, "bf16": 2}
 
@@ -91,6 +91,7 @@ def load():
         "cw_get_field": [P, I32, FP],
         "cw_set_field": [P, I32, FP],
         "cw_energy": [P, DP],
+        "cw_energy_noalloc": [P, I32, DP],
         "cw_reset": [P],
         "cw_steps_done": [P, ctypes.POINTER(I64)],
         "cw_ricker": [D, DP, I64, DP],
@@ -301,6 +302,13 @@ class Sim:
     def energy(self) -> float:
         e = ctypes.c_double()
         _check(self.lib.cw_energy(self.h, ctypes.byref(e)))
+        return e.value
+
+    def energy_noalloc(self, nblocks: int = 1024) -> float:
+        """cw_energy_noalloc: the energy with its partial sums in the
+        library's static scratch (no device memory allocated)."""
+        e = ctypes.c_double()
+        _check(self.lib.cw_energy_noalloc(self.h, int(nblocks), ctypes.byref(e)))
         return e.value
 
     def reset(self):
