@@ -57,9 +57,9 @@ def algorithmic_bytes(kernel: str, w, n_r: int, n_z: int, fb: int = 4, axisym: b
     raise ValueError(kernel)
 
 
-# the sources the profiled step kernels (two-pass, fused, march, sources, receivers) are built from
+# the sources the profiled step kernels (two-pass, fused, sources, receivers) are built from
 PROFILED_SOURCES = ("cwell_internal.hpp", "storage.hpp", "vec_common.hpp", "step_basic.hip", "step_vec.hip",
-                    "step_fused.hip", "step_march.hip")
+                    "step_fused.hip")
 
 
 def kernel_source_hash() -> str:
@@ -95,7 +95,6 @@ PROFILE_VARIANTS = {
     "two_pass_f16": "--path two-pass --storage f16",
     "two_pass_bf16": "--path two-pass --storage bf16",
     "fused_f32": "--path fused --storage f32",
-    "march_f32": "--path march --storage f32",
 }
 PROFILE_RUN = ("python3 -u bench.py --steps 20 --warmup 5 --no-cpu-baseline --no-storage-forms --no-stream-ceiling "
                "--no-graph-replay --no-adjoint --no-batched --no-refined --copy-gib 1")
@@ -106,8 +105,7 @@ PROFILE_PASSES = (
     ("rdreq", "--pmc TCC_EA0_RDREQ_32B_sum TCC_EA0_RDREQ_64B_sum TCC_EA0_RDREQ_128B_sum"),
 )
 KERNEL_PATTERNS = (("velocity", "k_velocity_"), ("stress", "k_stress_"), ("fused", "k_step_fused"),
-                   ("inject", "k_inject"), ("record", "k_record"), ("rescale", "k_rescale"),
-                   ("copy", "copyBuffer"))
+                   ("tail", "k_step_tail"), ("copy", "copyBuffer"))
 
 
 def profile_commands(variant: str, outdir: str):
@@ -200,7 +198,7 @@ def ingest_profiles(variant: str, outdir: str):
     lines += ["", "%-10s %6s %12s %12s %12s %14s %14s %14s %10s"
               % ("kernel", "calls", "avg_us", "min_us", "max_us", "alg_B/launch", "fetch_B", "write_B",
                  "L2miss_TB/s")]
-    for k in ("velocity", "stress", "fused", "inject", "record", "rescale"):
+    for k in ("velocity", "stress", "fused", "tail"):
         if k not in stats:
             continue
         st = stats[k]
@@ -612,7 +610,7 @@ def main():
                          "or with the rock moduli jittered +-2 %% cell by cell (a 3-D medium)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--path", choices=("auto", "fused", "two-pass", "march"), default="auto",
+    ap.add_argument("--path", choices=("auto", "fused", "two-pass"), default="auto",
                     help="kernel path of the step")
     ap.add_argument("--storage", choices=("f32", "f16", "bf16"), default="f32",
                     help="field storage (arithmetic is float32 in every case)")
@@ -683,8 +681,7 @@ def main():
     axisym = w.rock_jitter == 0          # the medium is then stored once per (ring, depth)
     # the default path differs from the column two-pass step only in the float32 kernels
     fused = times["fused"][1] > 0
-    form = ("fused" if fused else "march" if args.path == "march"
-            else "auto" if args.path == "auto" and args.storage == "f32" else "two_pass")
+    form = ("fused" if fused else "auto" if args.path == "auto" and args.storage == "f32" else "two_pass")
     variant = "%s_%s" % (form, args.storage)
     # Roofline of the step: the method's bytes per cell-update (every field read
     # and written once, the moduli read once, each layer memory variable read and
@@ -722,7 +719,7 @@ def main():
         "config": {"workload": w.name, "cells": w.cells, "grid": [w.nr, w.nt, w.nz],
                    "medium": "axisymmetric" if axisym else "3-D",
                    "cell_m": w.dr, "layer_cells": w.npml, "receivers": len(w.rec_k),
-                   "kernel_path": {"fused": "fused", "march": "two-pass, radial march",
+                   "kernel_path": {"fused": "fused",
                                    "auto": "two-pass, one-cell velocity and stress kernels"}.get(
                                        form, "two-pass, four-cell kernels")},
         "roofline": {"bound": "hbm", "kernel": "+".join(step_kernels), "achieved": round(achieved, 1),

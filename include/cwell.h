@@ -201,28 +201,26 @@ cw_status cw_set_storage(cw_sim *s, int32_t storage);
 
 /* Kernel path of cw_step.  All paths compute the same scheme; results
    agree to float32 rounding.
-   CW_PATH_TWO_PASS: a velocity launch and a stress launch per step (plus
-   source launches), any number of sources and any storage; one workgroup
+   CW_PATH_TWO_PASS: a velocity launch and a stress launch per step, small
+   launches that add the force and the stress sources (in the order they
+   were added) after them when there are any, then one launch that samples
+   the receivers, sets the float16 scales and advances the step counter;
+   any number of sources and any storage; one workgroup
    per (ring, theta row) depth segment, 4 depth cells per thread when nz is
    a multiple of 4 and a ring of one float32 array is under 4 GiB, one cell
    per thread otherwise.
-   CW_PATH_MARCH: the same two launches in radial-march form (when nz is a
-   multiple of 4 and a ring of one array is under 2 GiB; otherwise as
-   CW_PATH_TWO_PASS): each wavefront owns one theta row and 256 depth cells
-   and walks outward through a range of rings, keeping the radial
-   neighbours in registers.  Measured slower than CW_PATH_TWO_PASS on
-   MI355X; kept for comparison.
-   CW_PATH_FUSED: one launch per step that marches each theta x depth tile
-   outward through the rings and reads the state, the medium and the layer
-   memory once (float32 storage only, at most 12 source injections -- 3 per
+   CW_PATH_FUSED: one launch per step (and the receiver launch) that
+   marches each theta x depth tile outward through the rings and reads the
+   state, the medium and the layer memory once (float32 storage only, at most 12 source injections -- 3 per
    volume source, 2 per torsion source, 1 per force -- and nr <= 2048).
    CW_PATH_AUTO (default): the path measured fastest on MI355X: the
    two-pass step, with the velocity and the stress update one cell per
    thread for float32 storage (1 % and 3 % faster per launch at the
-   production size than four cells per thread); otherwise exactly
-   CW_PATH_TWO_PASS.  Results of the two kernel forms agree to float32
+   production size than four cells per thread; the one-cell stress update
+   adds the stress sources itself, so that a step with only stress sources
+   is three launches); otherwise exactly CW_PATH_TWO_PASS.  Results of the two kernel forms agree to float32
    rounding. */
-enum { CW_PATH_AUTO = 0, CW_PATH_TWO_PASS, CW_PATH_FUSED, CW_PATH_MARCH };
+enum { CW_PATH_AUTO = 0, CW_PATH_TWO_PASS, CW_PATH_FUSED };
 cw_status cw_set_path(cw_sim *s, int32_t path);
 
 /* Graph replay of the two-pass step.  With steps > 0 (even, at most 4096),
@@ -243,7 +241,9 @@ cw_status cw_set_graph(cw_sim *s, int32_t steps);
    microseconds of overhead per launch); enable = 0 stops recording and
    clears the records.  cw_profile_read waits for the recorded work and
    returns, for kernel `kernel` (CW_K_*), the summed device time in
-   milliseconds and the number of launches recorded. */
+   milliseconds and the number of launches recorded.  CW_K_RECORD is the
+   step's last launch (receivers, scales, step counter); CW_K_INJECT the
+   source launches. */
 enum { CW_K_VELOCITY = 0, CW_K_STRESS, CW_K_FUSED, CW_K_INJECT, CW_K_RECORD, CW_K_COUNT };
 cw_status cw_profile(cw_sim *s, int32_t enable);
 cw_status cw_profile_read(cw_sim *s, int32_t kernel, double *total_ms, int64_t *launches);

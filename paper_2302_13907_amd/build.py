@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcwell.so")
-SOURCES = ["cwell_api.hip", "step_basic.hip", "step_fused.hip", "step_vec.hip", "step_march.hip", "stream_probe.hip", "adjoint.hip", "refine.hip"]
+SOURCES = ["cwell_api.hip", "step_basic.hip", "step_fused.hip", "step_vec.hip", "stream_probe.hip", "adjoint.hip", "refine.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -112,6 +112,10 @@ struct cw_sim {
   double *d_traces = nullptr;
   double *d_energy = nullptr;   // kEnergyBlocks partials + 1 result
   int64_t *d_step = nullptr;    // steps done, as the injection and receiver kernels read it
+  bool force_src = false;       // a source injects into a velocity (phase 0)
+  bool stress_src = false;      // a source injects into a stress (phase 1)
+  int inj_i0 = 0, inj_i1 = -1;  // rings the sources touch
+  unsigned *d_done = nullptr;   // workgroups of the step's last launch that have finished (zero between steps)
   // adjoint gradient (cw_set_adjoint): configuration and buffers in the workspace
   bool adj = false;
   int64_t adj_steps = 0;
@@ -239,7 +243,7 @@ Layout layout(const cw_sim *s)
   L.traces = take(s->receivers.size() * (size_t)s->trace_cap * sizeof(double));
   L.energy = take((kEnergyBlocks + 1) * sizeof(double));
   L.scales = take(3 * NF * sizeof(float) + NF * kMaxSlots * sizeof(unsigned));
-  L.step = take(sizeof(int64_t));
+  L.step = take(2 * sizeof(int64_t));   // the step counter, then the finish counter of the step's last launch
   L.adj = take(adj_bytes(s));
   L.total = off;
   return L;
@@ -414,7 +418,7 @@ cw_status zero_state(cw_sim *s)
   if (psiz) HIPCHK(hipMemsetAsync(s->ws + L.psiz, 0, psiz, s->stream));
   const size_t tb = s->receivers.size() * (size_t)s->trace_cap * sizeof(double);
   if (tb) HIPCHK(hipMemsetAsync(s->ws + L.traces, 0, tb, s->stream));
-  HIPCHK(hipMemsetAsync(s->d_step, 0, sizeof(int64_t), s->stream));
+  HIPCHK(hipMemsetAsync(s->d_step, 0, 2 * sizeof(int64_t), s->stream));
   s->cur = 0;
   s->psi_cur = 0;
   s->nstep = 0;
@@ -646,6 +650,7 @@ cw_status cw_bind(cw_sim *s, void *workspace, uint64_t bytes, void *stream)
   s->d_traces = (double *)(w + L.traces);
   s->d_energy = (double *)(w + L.energy);
   s->d_step = (int64_t *)(w + L.step);
+  s->d_done = (unsigned *)(s->d_step + 1);
   if (s->adj) {
     float *p = (float *)(w + L.adj);
     for (int q = 0; q < NF; q++) { s->adj_fb[q] = p; p += s->n; }
@@ -707,6 +712,15 @@ cw_status cw_bind(cw_sim *s, void *workspace, uint64_t bytes, void *stream)
     }
   }
   s->ninject = (int)s->inject_host.size();
+  s->force_src = s->stress_src = false;
+  s->inj_i0 = s->nr;
+  s->inj_i1 = -1;
+  for (const Inject &e : s->inject_host) {
+    s->force_src = s->force_src || e.phase == 0;
+    s->stress_src = s->stress_src || e.phase == 1;
+    s->inj_i0 = std::min(s->inj_i0, e.i);
+    s->inj_i1 = std::max(s->inj_i1, e.i);
+  }
 
   HIPCHK(hipMemcpyAsync(s->d_rho, s->rho.data(), s->nm * sizeof(float), hipMemcpyHostToDevice, s->stream));
   HIPCHK(hipMemcpyAsync(s->d_lam, s->lam.data(), s->nm * sizeof(float), hipMemcpyHostToDevice, s->stream));
@@ -777,50 +791,55 @@ cw_status cw_step(cw_sim *s, int64_t nsteps)
                 s->ninject, s->nr);
   FusedArgs f{};
   if (fused) fused_tiles(s->nt, s->nz, &f.own_rows, &f.ntile_z);
-  // two-pass kernel form: one workgroup per column segment (default) or the
-  // radial march, both with 4 depth cells per thread; one thread per cell
-  // when nz is not a multiple of 4
+  // two-pass kernel form: one workgroup per column segment with 4 depth cells
+  // per thread; one thread per cell when nz is not a multiple of 4
   const bool vec = kUseVec && vec_applies(s->nt, s->nz);
-  const bool march = vec && s->path == CW_PATH_MARCH && march_applies(s->nt, s->nz);
   // the default path takes the faster form of each update; CW_PATH_TWO_PASS
   // keeps the four-cell column kernels (the form the batched kernels
   // reproduce bitwise)
   const bool vec_velocity = vec && !(s->path == CW_PATH_AUTO && velocity_one_cell(s->storage));
   const bool vec_stress = vec && !(s->path == CW_PATH_AUTO && stress_one_cell(s->storage));
   auto velocity = [&](const StepArgs &a) {
-    return march ? launch_velocity_march(a, s->storage, s->stream)
-                 : vec_velocity ? launch_velocity_vec(a, s->storage, s->stream)
-                                : launch_velocity_basic(a, s->storage, s->stream);
+    return vec_velocity ? launch_velocity_vec(a, s->storage, s->stream)
+                        : launch_velocity_basic(a, s->storage, s->stream);
   };
   auto stress = [&](const StepArgs &a) {
-    return march ? launch_stress_march(a, s->storage, s->stream)
-                 : vec_stress ? launch_stress_vec(a, s->storage, s->stream)
-                              : launch_stress_basic(a, s->storage, s->stream);
+    return vec_stress ? launch_stress_vec(a, s->storage, s->stream)
+                      : launch_stress_basic(a, s->storage, s->stream);
   };
   // One step's launches.  Nothing in them depends on the host's step count
   // (the injection and receiver kernels read the device counter, which the
   // last launch advances), so the launches of an even number of two-pass
   // steps can be captured once and replayed.
+  // the step's last launch: receivers, float16 rescale, step counter
   auto finish_step = [&](const StepArgs &a) -> cw_status {
-    if (nrec && (st = timed(s, CW_K_RECORD, [&] {
-          return launch_record(s->d_rec, nrec, s->d_step, s->trace_cap, a, s->storage, s->d_traces, s->stream);
+    if ((st = timed(s, CW_K_RECORD, [&] {
+          return launch_step_tail(s->d_rec, nrec, s->d_step, s->trace_cap, a, s->storage, s->d_traces, s->d_done,
+                                  s->d_scl + (1 - s->cur) * NF, s->d_scl + 2 * NF, s->d_maxabs, s->stream);
         })) != CW_OK)
       return st;
-    if (s->storage == ST_F16)
-      HIPCHK(launch_rescale(s->d_scl + (1 - s->cur) * NF, s->d_scl + 2 * NF, s->d_maxabs, s->stream));
-    HIPCHK(launch_step_done(s->d_step, s->stream));
     s->cur = 1 - s->cur;
     return CW_OK;
   };
+  // velocity update, force sources (if any), stress update (the one-cell form
+  // adds the stress sources itself, the four-cell one takes a source launch),
+  // the tail: three launches for the default float32 path
   auto two_pass_step = [&]() -> cw_status {
-    const StepArgs a = step_args(s, s->cur, 1 - s->cur);
+    StepArgs a = step_args(s, s->cur, 1 - s->cur);
+    if (s->ninject) {
+      a.inj = s->d_inject;
+      a.ninj = s->ninject;
+      a.inj_i0 = s->inj_i0;
+      a.inj_i1 = s->inj_i1;
+      a.step = s->d_step;
+    }
     if ((st = timed(s, CW_K_VELOCITY, [&] { return velocity(a); })) != CW_OK) return st;
-    if (s->ninject && (st = timed(s, CW_K_INJECT, [&] {
-          return launch_inject(s->d_inject, s->ninject, 0, s->d_step, a, s->storage, s->stream); })) != CW_OK)
+    if (s->force_src &&
+        (st = timed(s, CW_K_INJECT, [&] { return launch_sources(a, 0, s->storage, s->stream); })) != CW_OK)
       return st;
     if ((st = timed(s, CW_K_STRESS, [&] { return stress(a); })) != CW_OK) return st;
-    if (s->ninject && (st = timed(s, CW_K_INJECT, [&] {
-          return launch_inject(s->d_inject, s->ninject, 1, s->d_step, a, s->storage, s->stream); })) != CW_OK)
+    if (s->stress_src && vec_stress &&
+        (st = timed(s, CW_K_INJECT, [&] { return launch_sources(a, 1, s->storage, s->stream); })) != CW_OK)
       return st;
     return finish_step(a);
   };
@@ -1096,7 +1115,7 @@ cw_status cw_set_storage(cw_sim *s, int32_t storage)
 cw_status cw_set_path(cw_sim *s, int32_t path)
 {
   if (!s) return fail(CW_ERR_ARG, "null simulation");
-  if (path < CW_PATH_AUTO || path > CW_PATH_MARCH) return fail(CW_ERR_ARG, "bad path %d", path);
+  if (path < CW_PATH_AUTO || path > CW_PATH_FUSED) return fail(CW_ERR_ARG, "bad path %d", path);
   if (path != s->path) s->drop_graph();
   s->path = path;
   return CW_OK;

@@ -28,6 +28,15 @@ enum TabR { AR_C = 0, BR_C, AR_F, BR_F, AT_C, BT_C, AT_F, BT_F, NTAB_R };
 // Rows of the packed z table (each row nz floats): at z_k and z_{k+1/2}.
 enum TabZ { AZ_C = 0, BZ_C, AZ_H, BZ_H, NTAB_Z };
 
+// One point (or ring) injection: field[(i, j or all j, k)] += scale * amp[n].
+struct Inject {
+  int field, i, j, k;       // j = -1: the whole ring
+  int phase;                // 0: after the velocity update, 1: after the stress update
+  int nsamp;                // amp has nsamp entries
+  float scale;              // 1, or the node buoyancy for force sources
+  const float *amp;         // dt * w[n] / V, float32
+};
+
 // Everything one time step reads and writes, by value as a kernel argument.
 struct StepArgs {
   int nr, nt, nz;
@@ -60,16 +69,15 @@ struct StepArgs {
   // float32 storage.
   const float *scl_in, *scl_out;
   unsigned *maxabs;
+  // Source injections of a solo two-pass step: the list, its length, the
+  // rings it touches and the device step counter that indexes the
+  // amplitudes.  The one-cell stress update adds the stress sources itself.
+  // inj == nullptr: none.
+  const Inject *inj;
+  int ninj, inj_i0, inj_i1;   // inj_i0..inj_i1: the rings the sources touch
+  const int64_t *step;
 };
 
-// One point (or ring) injection: field[(i, j or all j, k)] += scale * amp[n].
-struct Inject {
-  int field, i, j, k;       // j = -1: the whole ring
-  int phase;                // 0: after the velocity update, 1: after the stress update
-  int nsamp;                // amp has nsamp entries
-  float scale;              // 1, or the node buoyancy for force sources
-  const float *amp;         // dt * w[n] / V, float32
-};
 
 // One receiver: trace[id][n] = ring mean or point value.
 struct Receiver {
@@ -161,10 +169,16 @@ constexpr int kMaxFusedRings = 2048;            // nr limit of the fused step (L
 hipError_t launch_fused(const FusedArgs &f, hipStream_t stream);
 hipError_t launch_velocity_basic(const StepArgs &a, int storage, hipStream_t stream);
 hipError_t launch_stress_basic(const StepArgs &a, int storage, hipStream_t stream);
-hipError_t launch_inject(const Inject *dev_list, int ninj, int phase, const int64_t *step,
-                         const StepArgs &a, int storage, hipStream_t stream);
-hipError_t launch_record(const Receiver *dev_rec, int nrec, const int64_t *step, int64_t cap,
-                         const StepArgs &a, int storage, double *traces, hipStream_t stream);
+// The sources of one phase of a.inj in a solo step (0: forces, after the
+// velocity update; 1: stresses, after a stress update that does not add
+// them itself), in list order.
+hipError_t launch_sources(const StepArgs &a, int phase, int storage, hipStream_t stream);
+// The last launch of a solo step: the receivers, then (in whichever
+// workgroup finishes last) the float16 rescale and the step counter.
+// done: a zeroed counter of finished workgroups, left at zero.
+hipError_t launch_step_tail(const Receiver *dev_rec, int nrec, int64_t *step, int64_t cap, const StepArgs &a,
+                            int storage, double *traces, unsigned *done, float *scl_written, float *scl_next,
+                            unsigned *maxabs, hipStream_t stream);
 // One ghost-ring fill of an azimuthally refined grid: dst[r][k] =
 // sum_j M[r][j] src[j][k], rings of nz depth cells.
 struct Transfer {
@@ -178,10 +192,6 @@ hipError_t launch_interp(const Transfer *dev, int count, int nz, int max_ns, hip
 
 hipError_t launch_energy(const StepArgs &a, int storage, double *partials, int nblocks, double scale,
                          double *result, hipStream_t stream);
-// After a float16 step: record the scale the level-n+1 buffer was written
-// with (scl_written = scl_next), derive the next scale from maxabs, clear it.
-hipError_t launch_step_done(int64_t *step, hipStream_t stream);
-hipError_t launch_rescale(float *scl_written, float *scl_next, unsigned *maxabs, hipStream_t stream);
 constexpr int kF16TargetExp = 11;   // scaled float16 maxima land in [2^10, 2^11)
 // depth-vectorized two-pass kernels (4 cells per thread), when nz % 4 == 0
 // the depth-vectorized kernels apply: nz a multiple of 4, and one ring of a
@@ -248,11 +258,8 @@ hipError_t launch_adjoint_coefs(const AdjArgs &a, hipStream_t stream);
 hipError_t launch_adjoint_capture(const AdjArgs &a, const AdjRegion &g, const float *vr, const float *vt,
                                   const float *vz, float *Z, hipStream_t stream);
 hipError_t launch_set_step(int64_t *step, int64_t value, hipStream_t stream);
-bool march_applies(int nt, int nz);
 bool stream_mix_supported(int r, int w);
 hipError_t launch_stream(const void *base, size_t bytes_per_array, int lane_bytes, int r, int w, hipStream_t stream);
-hipError_t launch_velocity_march(const StepArgs &a, int storage, hipStream_t stream);
-hipError_t launch_stress_march(const StepArgs &a, int storage, hipStream_t stream);
 hipError_t launch_velocity_vec(const StepArgs &a, int storage, hipStream_t stream);
 hipError_t launch_stress_vec(const StepArgs &a, int storage, hipStream_t stream);
 

@@ -1,7 +1,10 @@
 // Two-pass time step: one thread per cell, k (depth) across the lanes so
 // every load of a wavefront is one contiguous run.  The velocity and stress
-// updates are separate launches; they carry the source, receiver, energy
-// and rescale kernels too.  The fields may be stored in float32, float16
+// updates are separate launches; the one-cell stress update adds the step's
+// stress sources itself (the other forms take a small source launch, as do
+// force sources after the velocity update); a last launch samples the
+// receivers, sets the float16 scales and advances the step counter.  The energy and the batched source and receiver
+// kernels live here too.  The fields may be stored in float32, float16
 // (with a power-of-two scale per field, chosen on the device from the
 // largest magnitude written in the previous step) or bfloat16; every
 // arithmetic operation is float32.
@@ -294,12 +297,32 @@ __device__ __forceinline__ void stress_cell(const StepArgs &a, int i, int j, int
   const float *c = a.scl_in;
   const float tr = err + ett + ezz;
   const float lt = lam * tr, m2 = 2.0f * mu;
-  const float s_rr = S::ldn(a.in[SRR], p, c[SRR]) + a.dt * (lt + m2 * err);
-  const float s_tt = S::ldn(a.in[STT], p, c[STT]) + a.dt * (lt + m2 * ett);
-  const float s_zz = S::ldn(a.in[SZZ], p, c[SZZ]) + a.dt * (lt + m2 * ezz);
-  const float s_rt = S::ldn(a.in[SRT], p, c[SRT]) + a.dt * mu_rt * (rt_dr + rt_b);
-  const float s_rz = S::ldn(a.in[SRZ], p, c[SRZ]) + a.dt * mu_rz * (rz_dr + rz_dz);
-  const float s_tz = S::ldn(a.in[STZ], p, c[STZ]) + a.dt * mu_tz * (tz_b + tz_dz);
+  float s_rr = S::ldn(a.in[SRR], p, c[SRR]) + a.dt * (lt + m2 * err);
+  float s_tt = S::ldn(a.in[STT], p, c[STT]) + a.dt * (lt + m2 * ett);
+  float s_zz = S::ldn(a.in[SZZ], p, c[SZZ]) + a.dt * (lt + m2 * ezz);
+  float s_rt = S::ldn(a.in[SRT], p, c[SRT]) + a.dt * mu_rt * (rt_dr + rt_b);
+  float s_rz = S::ldn(a.in[SRZ], p, c[SRZ]) + a.dt * mu_rz * (rz_dr + rz_dz);
+  float s_tz = S::ldn(a.in[STZ], p, c[STZ]) + a.dt * mu_tz * (tz_b + tz_dz);
+  // this step's stress sources at the cell, in the order they were added
+  // (only workgroups of the rings the sources touch look at the list: the
+  // scalar unit is this kernel's busiest)
+  if (a.inj && live && i >= a.inj_i0 && i <= a.inj_i1) {
+    const int64_t n = *a.step;
+    for (int m = 0; m < a.ninj; m++) {
+      const Inject s = a.inj[m];
+      if (s.phase != 1 || s.i != i || (s.j >= 0 && s.j != j) || s.k != k || n >= s.nsamp) continue;
+      const float amp = s.scale * s.amp[n];
+      switch (s.field) {
+      case SRR: s_rr += amp; break;
+      case STT: s_tt += amp; break;
+      case SZZ: s_zz += amp; break;
+      case SRT: s_rt += amp; break;
+      case SRZ: s_rz += amp; break;
+      case STZ: s_tz += amp; break;
+      default: break;
+      }
+    }
+  }
   if (live) {
     S::stn(a.out[SRR], p, s_rr, 1.0f / o[SRR]);
     S::stn(a.out[STT], p, s_tt, 1.0f / o[STT]);
@@ -364,11 +387,12 @@ __device__ void inject_all(const Inject *list, int ninj, int phase, int64_t step
   }
 }
 
+// the sources of one phase of a solo step: forces (phase 0) after the
+// velocity update, stresses (phase 1) after the four-cell stress update
 template <class S>
-__global__ void __launch_bounds__(256) k_inject(const Inject *list, int ninj, int phase,
-                                                const int64_t *stepp, StepArgs a)
+__global__ void __launch_bounds__(256) k_inject(StepArgs a, int phase)
 {
-  inject_all<S>(list, ninj, phase, *stepp, a);      // step: steps done (device counter)
+  inject_all<S>(a.inj, a.ninj, phase, *a.step, a);
 }
 
 __global__ void __launch_bounds__(256) k_inject_batch(const BatchInst *B, int phase, int parity)
@@ -381,10 +405,11 @@ __global__ void __launch_bounds__(256) k_inject_batch(const BatchInst *B, int ph
 template <class S>
 __device__ void record_one(const Receiver &r, int m, int64_t step, int64_t cap, const StepArgs &a, double *traces)
 {
+  const int lane = threadIdx.x & 63;
   const int j0 = r.j < 0 ? 0 : r.j, j1 = r.j < 0 ? a.nt : r.j + 1;
   const float *o = a.scl_out;
   double acc = 0.0;
-  for (int j = j0 + (int)threadIdx.x; j < j1; j += 64) {
+  for (int j = j0 + lane; j < j1; j += 64) {
     const size_t p = at(a, r.i, j, r.k);
     if (r.kind == 0)
       acc += (double)S::ld(a.out[SRR], p, o[SRR]) + (double)S::ld(a.out[STT], p, o[STT]) +
@@ -393,17 +418,55 @@ __device__ void record_one(const Receiver &r, int m, int64_t step, int64_t cap, 
       acc += (double)S::ld(a.out[r.field], p, o[r.field]);
   }
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-  if (threadIdx.x == 0) {
+  if (lane == 0) {
     const double cnt = (double)(j1 - j0);
     traces[(size_t)m * cap + step] = r.kind == 0 ? -acc / (3.0 * cnt) : acc / cnt;
   }
 }
 
-template <class S>
-__global__ void __launch_bounds__(64) k_record(const Receiver *rec, const int64_t *stepp, int64_t cap,
-                                               StepArgs a, double *traces)
+// New float16 scale of field q: 2^(e - target) with max|v| = f 2^e,
+// f in [0.5, 1); unchanged while the field is still identically zero.  The
+// maxima slots are cleared for the next step.
+__device__ void rescale_field(int q, float *scl_written, float *scl_next, unsigned *maxabs)
 {
-  record_one<S>(rec[blockIdx.x], blockIdx.x, *stepp, cap, a, traces);
+  scl_written[q] = scl_next[q];
+  unsigned mb = 0u;
+  for (int c = 0; c < kMaxSlots; c++) {
+    mb = max(mb, maxabs[q * kMaxSlots + c]);
+    maxabs[q * kMaxSlots + c] = 0u;
+  }
+  const float m = __builtin_bit_cast(float, mb);
+  if (m > 0.0f) {
+    int e;
+    frexpf(m, &e);
+    scl_next[q] = ldexpf(1.0f, e - kF16TargetExp);
+  }
+}
+
+// The last launch of a solo step: one workgroup per receiver, then -- in the
+// workgroup that finishes last, once every other one has read the step
+// counter and the scales -- the float16 scales and the step counter.  The
+// finish counter is left at zero for the next step.
+template <class S>
+__global__ void __launch_bounds__(64) k_step_tail(const Receiver *rec, int nrec, int64_t *stepp, int64_t cap,
+                                                  StepArgs a, double *traces, unsigned *done, float *scl_written,
+                                                  float *scl_next, unsigned *maxabs)
+{
+  if ((int)blockIdx.x < nrec) record_one<S>(rec[blockIdx.x], blockIdx.x, *stepp, cap, a, traces);
+  __shared__ unsigned ticket;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    ticket = atomicAdd(done, 1u);
+  }
+  __syncthreads();
+  if (ticket != gridDim.x - 1) return;
+  __threadfence();
+  if (S::scaled && threadIdx.x < NF) rescale_field(threadIdx.x, scl_written, scl_next, maxabs);
+  if (threadIdx.x == 0) {
+    *done = 0u;
+    *stepp += 1;
+  }
 }
 
 // grid (receivers of the largest instance, instances)
@@ -498,25 +561,6 @@ __global__ void __launch_bounds__(256) k_energy_final(const double *partials, in
   if (threadIdx.x == 0) *result = red[0] * scale;
 }
 
-// New float16 scale per field: 2^(e - target) with max|v| = f 2^e,
-// f in [0.5, 1); unchanged while a field is still identically zero.
-__global__ void k_rescale(float *scl_written, float *scl_next, unsigned *maxabs)
-{
-  const int q = threadIdx.x;
-  if (q >= NF) return;
-  scl_written[q] = scl_next[q];
-  unsigned mb = 0u;
-  for (int c = 0; c < kMaxSlots; c++) {
-    mb = max(mb, maxabs[q * kMaxSlots + c]);
-    maxabs[q * kMaxSlots + c] = 0u;
-  }
-  const float m = __builtin_bit_cast(float, mb);
-  if (m > 0.0f) {
-    int e;
-    frexpf(m, &e);
-    scl_next[q] = ldexpf(1.0f, e - kF16TargetExp);
-  }
-}
 
 template <class F>
 hipError_t dispatch(int storage, F &&f)
@@ -553,22 +597,22 @@ hipError_t launch_stress_basic(const StepArgs &a, int storage, hipStream_t strea
   });
 }
 
-hipError_t launch_inject(const Inject *dev_list, int ninj, int phase, const int64_t *step,
-                         const StepArgs &a, int storage, hipStream_t stream)
+hipError_t launch_sources(const StepArgs &a, int phase, int storage, hipStream_t stream)
 {
-  if (ninj == 0) return hipSuccess;
   return dispatch(storage, [&](auto s) {
-    hipLaunchKernelGGL(k_inject<decltype(s)>, dim3(1), dim3(256), 0, stream, dev_list, ninj, phase, step, a);
+    hipLaunchKernelGGL(k_inject<decltype(s)>, dim3(1), dim3(256), 0, stream, a, phase);
     return hipGetLastError();
   });
 }
 
-hipError_t launch_record(const Receiver *dev_rec, int nrec, const int64_t *step, int64_t cap,
-                         const StepArgs &a, int storage, double *traces, hipStream_t stream)
+hipError_t launch_step_tail(const Receiver *dev_rec, int nrec, int64_t *step, int64_t cap, const StepArgs &a,
+                            int storage, double *traces, unsigned *done, float *scl_written, float *scl_next,
+                            unsigned *maxabs, hipStream_t stream)
 {
-  if (nrec == 0) return hipSuccess;
+  const unsigned g = nrec > 0 ? (unsigned)nrec : 1u;
   return dispatch(storage, [&](auto s) {
-    hipLaunchKernelGGL(k_record<decltype(s)>, dim3(nrec), dim3(64), 0, stream, dev_rec, step, cap, a, traces);
+    hipLaunchKernelGGL(k_step_tail<decltype(s)>, dim3(g), dim3(64), 0, stream, dev_rec, nrec, step, cap, a, traces,
+                       done, scl_written, scl_next, maxabs);
     return hipGetLastError();
   });
 }
@@ -604,22 +648,5 @@ hipError_t launch_step_done_batch(const BatchInst *dev, int count, hipStream_t s
   return hipGetLastError();
 }
 
-// the step counter the injection and receiver kernels read, advanced once per step
-__global__ void k_step_done(int64_t *step)
-{
-  if (threadIdx.x == 0) *step += 1;
-}
-
-hipError_t launch_step_done(int64_t *step, hipStream_t stream)
-{
-  hipLaunchKernelGGL(k_step_done, dim3(1), dim3(64), 0, stream, step);
-  return hipGetLastError();
-}
-
-hipError_t launch_rescale(float *scl_written, float *scl_next, unsigned *maxabs, hipStream_t stream)
-{
-  hipLaunchKernelGGL(k_rescale, dim3(1), dim3(64), 0, stream, scl_written, scl_next, maxabs);
-  return hipGetLastError();
-}
 
 }  // namespace cw

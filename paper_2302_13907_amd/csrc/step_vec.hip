@@ -132,6 +132,9 @@ __device__ __forceinline__ void velocity_column(const StepArgs &a, int i, int j,
     vr[e] += a.dt * b_r * (r_dr[e] + r_b[e] + r_dz[e]);
     vt[e] += a.dt * b_t * (t_dr[e] + t_b[e] + t_dz[e]);
     vz[e] += a.dt * b_z * (z_dr[e] + z_b[e] + z_dz[e]);
+  }
+#pragma unroll
+  for (int e = 0; e < VW; e++) {
     mr = fmaxf(mr, fabsf(vr[e])); mt = fmaxf(mt, fabsf(vt[e])); mz = fmaxf(mz, fabsf(vz[e]));
   }
   if (live) {
@@ -270,6 +273,9 @@ __device__ __forceinline__ void stress_column(const StepArgs &a, int i, int j, i
     srt[e] += a.dt * mu_rt * (rt_dr[e] + rt_b[e]);
     srz[e] += a.dt * mu_rz * (rz_dr[e] + rz_dz[e]);
     stz[e] += a.dt * mu_tz * (tz_b[e] + tz_dz[e]);
+  }
+#pragma unroll
+  for (int e = 0; e < VW; e++) {
     mx[0] = fmaxf(mx[0], fabsf(srr[e])); mx[1] = fmaxf(mx[1], fabsf(stt[e]));
     mx[2] = fmaxf(mx[2], fabsf(szz[e])); mx[3] = fmaxf(mx[3], fabsf(srt[e]));
     mx[4] = fmaxf(mx[4], fabsf(srz[e])); mx[5] = fmaxf(mx[5], fabsf(stz[e]));

@@ -1,5 +1,5 @@
-// Device helpers shared by the depth-vectorized step kernels (column and
-// radial-march forms): VW consecutive depth cells per thread, zero ghosts
+// Device helpers shared by the depth-vectorized step kernels (solo and
+// batched column forms): VW consecutive depth cells per thread, zero ghosts
 // outside the grid, layer memory updates, float16 scale tracking.
 #pragma once
 #include "cwell_internal.hpp"

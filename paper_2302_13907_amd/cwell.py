@@ -42,7 +42,7 @@ EXPORTS = ("cw_create", "cw_set_material", "cw_set_material_rz", "cw_set_pml", "
 
 STORAGE = {"f32": 0, "f16": 1, "bf16": 2}
 
-PATHS = {"auto": 0, "two-pass": 1, "fused": 2, "march": 3}
+PATHS = {"auto": 0, "two-pass": 1, "fused": 2}
 
 KERNELS = {"velocity": 0, "stress": 1, "fused": 2, "inject": 3, "record": 4}
 
@@ -319,7 +319,7 @@ class Sim:
         _check(self.lib.cw_set_storage(self.h, STORAGE[storage]))
 
     def set_path(self, path: str):
-        """Kernel path of step(): "auto", "two-pass", "fused" or "march"."""
+        """Kernel path of step(): "auto", "two-pass" or "fused"."""
         _check(self.lib.cw_set_path(self.h, PATHS[path]))
 
     def set_adjoint(self, nsteps: int, checkpoint_every: int, region):

@@ -22,7 +22,7 @@ TRACE_TOL = 1e-5
 FIELD_TOL = 1e-5
 
 
-PATHS = ["auto", "fused", "two-pass", "march"]
+PATHS = ["auto", "fused", "two-pass"]
 
 
 @pytest.mark.parametrize("path", PATHS)
@@ -92,7 +92,7 @@ CASES = {
     # layer in r only, long z
     "layer_r_only": dict(shape=(30, 8, 300), npml=(8, 0), steps=80, sources=[
         ("volume", 0, -1, 150, 1.0)]),
-    # a single azimuthal cell with depth groups of 4 (radial-march kernels)
+    # a single azimuthal cell with depth groups of 4 (four-cell kernels)
     "ntheta_1_depth_64": dict(shape=(31, 1, 64), npml=(5, 6), steps=150, sources=[
         ("volume", 0, -1, 25, 1.0), ("torsion", 20, -1, 30, 1.0)]),
     # a medium that does not vary along theta (stored once per ring and depth)
@@ -285,40 +285,6 @@ def test_fused_matches_two_pass():
     fe = field_errors({k: v.astype(np.float64) for k, v in fa.items()},
                       {k: v.astype(np.float64) for k, v in fb.items()})
     assert max(fe.values()) < 1e-6, fe
-
-
-@pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
-@pytest.mark.parametrize("shape", [(48, 32, 192), (19, 6, 200), (40, 1, 64), (9, 5, 1032)])
-def test_march_matches_column(shape, storage):
-    """The radial-march and column forms (CW_PATH_MARCH, CW_PATH_TWO_PASS) of the two-pass step evaluate the
-    same expressions (the compiler may contract them into fused multiply-adds
-    differently), so they agree to float32 rounding: layer on in r and z,
-    ring and point sources of every kind, theta rows not a multiple of a
-    workgroup's rows, ring counts not a multiple of the radial segment,
-    depth groups that end inside a wavefront."""
-    announce("march vs column form %s %s" % (shape, storage))
-    h = 5e-3
-    med = _cased(shape, h, z_top=shape[2] * h / 2, ramp=0.05)
-    nr, nt, nz = shape
-    srcs = [("volume", 0, -1, nz // 3, 1.0), ("force_r", nr // 2, nt - 1, nz // 2, 1e-3),
-            ("force_z", 1, 0, nz // 4, 1e-3), ("torsion", min(21, nr - 1), -1, nz // 3 + 2, 1.0)]
-    recs = [("pressure", 0, -1, k, None) for k in range(2, nz - 2, max(1, nz // 6))]
-    steps = 90
-    res = {}
-    for path in ("march", "two-pass"):
-        sc = Scenario(shape=shape, h=(h, h), medium=med, steps=steps, npml=(min(6, nr // 3), 6),
-                      sources=srcs, receivers=recs, path=path, storage=storage)
-        res[path] = run_gpu(sc)
-    (ta, fa), (tb, fb) = res["march"], res["two-pass"]
-    assert np.abs(fa["szz"]).max() > 0
-    # float16 / bfloat16 storage: one rounding of a stored value either way
-    tol = {"f32": 1e-6, "f16": 2e-3, "bf16": 2e-2}[storage]
-    e = rel_l2(ta, tb)
-    fe = field_errors({k: v.astype(np.float64) for k, v in fa.items()},
-                      {k: v.astype(np.float64) for k, v in fb.items()})
-    announce("  traces %.2e, worst field %.2e" % (e, max(fe.values())))
-    assert e <= tol, e
-    assert max(fe.values()) <= tol, fe
 
 
 @pytest.mark.parametrize("storage", ["f32", "f16"])
