@@ -8,7 +8,9 @@ oracle): 48 x 32 x 192 parity case (300 steps) float16 4.1e-4, bfloat16
 float16 8.5e-3, bfloat16 1.2e-1 (float32 storage 1.6e-6).  The asserted
 bounds below add margin to those numbers.  bfloat16's 8-bit mantissa
 loses every per-step increment below half a unit of the stored value, so
-its error grows with the step count much faster than float16's."""
+its error grows with the step count much faster than float16's: on the
+crop it passes 1e-2 after 550 steps (89 us of simulated time), while
+float16 stays below 1e-2 for all 3000."""
 import math
 
 import numpy as np
@@ -23,6 +25,10 @@ pytestmark = pytest.mark.gpu
 
 PARITY_BOUND = {"f16": 1e-3, "bf16": 1e-2}
 CROP_BOUND = {"f16": 1.5e-2, "bf16": 2e-1}
+# step counts below which the crop's trace error stays under 1e-2: measured on
+# MI355X, float16 never passes it in 3000 steps; bfloat16 passes it at 550
+# steps (the error over steps [0, n) checked every 50 steps)
+CROSS_MIN = {"f16": 3000, "bf16": 400}
 
 
 def _run(sc, storage):
@@ -88,10 +94,17 @@ def test_crop_3000_steps_16bit(storage):
     e_or = rel_l2(tr16, tro)
     e_32 = rel_l2(tr16, tr32)
     e_32o = rel_l2(tr32, tro)
-    announce("  %s: traces vs oracle %.3e, vs float32 %.3e (float32 vs oracle %.3e)" % (
-        storage, e_or, e_32, e_32o))
+    # the first step count n at which the error of the traces over steps [0, n)
+    # passes 1e-2 (none: it stays below over the whole run)
+    cross = next((n for n in range(100, sc.steps + 1, 50) if rel_l2(tr16[:, :n], tro[:, :n]) > 1e-2), None)
+    announce("  %s: traces vs oracle %.3e, vs float32 %.3e (float32 vs oracle %.3e); error passes 1e-2 at %s steps" % (
+        storage, e_or, e_32, e_32o, cross))
     assert e_32o <= 1e-5, e_32o
     assert e_or <= CROP_BOUND[storage], e_or
+    if storage == "f16":
+        assert cross is None or cross >= CROSS_MIN["f16"], cross
+    else:
+        assert cross is not None and CROSS_MIN["bf16"] <= cross, cross
 
 
 def test_f16_field_roundtrip_and_scale():
