@@ -510,7 +510,8 @@ def batched_form(small: bool = False, steps: int = 40, graph: int = 20):
         s.step(2)
     t_seq = timed(lambda: [s.step(steps) for s in sims])
     b = cwell.Batch(sims)
-    tiles = autotune.tune_batch(b, sims)
+    tuned = autotune.tune_batch(b, sims)
+    tiles = tuned["tiles"]
     b.bind()
     b.step(2)
     t_bat = timed(lambda: b.step(steps))
@@ -523,13 +524,19 @@ def batched_form(small: bool = False, steps: int = 40, graph: int = 20):
     del sims
     torch.cuda.empty_cache()
     gc = lambda t: round(cells * steps / t / 1e9, 3)
+    # the method's bytes of one step of every instance (axisymmetric media;
+    # the layer is a larger share of these smaller grids than of the production one)
+    alg = sum(algorithmic_bytes("fused", w, *w.layer_cells, axisym=True) for w in ws)
     depths = sorted({w.nz for w in ws})
     return {"workload": "%d instances of %dx%dxNz, Nz in {%d..%d} (5 mm)" % (len(ws), ws[0].nr, ws[0].nt,
                                                                            depths[0], depths[-1]),
             "cells_per_step": cells, "steps": steps, "unit": "Gcell-updates/s",
             "sequential": gc(t_seq), "batched": gc(t_bat), "batched_graph": gc(t_gr),
             "speedup_batched": round(t_seq / t_bat, 3), "speedup_batched_graph": round(t_seq / t_gr, 3),
-            "tiles": {str(ws[q].nz): tz for q, tz in sorted(tiles.items())}}
+            "bytes_per_cell_update": round(alg / cells, 2),
+            "roofline_frac_batched": round(alg * steps / t_bat / 1e9 / HBM_PEAK_GBS, 4),
+            "tiles": {str(ws[q].nz): tz for q, tz in sorted(tiles.items())},
+            "waves_per_simd": tuned["waves_per_simd"]}
 
 
 def refined_form(uniform_ms: float, warmup: int = 10, steps: int = 100):

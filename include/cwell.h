@@ -301,11 +301,18 @@ cw_status cw_gradient(cw_sim *s, int64_t n0, int64_t n1, double *loss, double *g
    (cw_batch_set_tile, before cw_batch_bind): a workgroup covers tz_waves x
    256 depth cells of 4 / tz_waves theta rows, tz_waves in {1, 2, 4}
    (default 4); shallow or ragged columns waste fewer lanes with shorter
-   tiles.  cw_batch_set_graph: as cw_set_graph, for the batch.  The batch
-   must be destroyed before its simulations. */
+   tiles.  cw_batch_set_occupancy: the minimum wavefronts per SIMD the
+   batched kernels' registers are sized for, 0 (the compiler's choice,
+   default: 79 registers, 6 waves), 7 or 8 (fewer registers, some values
+   spilled; CW_ERR_RANGE otherwise); one compiled variant each, same
+   results; callable at any time.  The tile shapes and the occupancy
+   are what the package's autotuner searches.  cw_batch_set_graph: as
+   cw_set_graph, for the batch.  The batch must be destroyed before its
+   simulations. */
 typedef struct cw_batch cw_batch;
 cw_status cw_batch_create(cw_sim *const *sims, int32_t count, cw_batch **out);
 cw_status cw_batch_set_tile(cw_batch *b, int32_t index, int32_t tz_waves);
+cw_status cw_batch_set_occupancy(cw_batch *b, int32_t waves_per_simd);
 cw_status cw_batch_workspace_bytes(const cw_batch *b, uint64_t *bytes);
 cw_status cw_batch_bind(cw_batch *b, void *workspace, uint64_t bytes);
 cw_status cw_batch_set_graph(cw_batch *b, int32_t steps);

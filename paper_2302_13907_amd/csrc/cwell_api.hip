@@ -1416,6 +1416,7 @@ cw_status cw_gradient(cw_sim *s, int64_t n0, int64_t n1, double *loss, double *g
 struct cw_batch {
   std::vector<cw_sim *> sims;
   std::vector<int> tz;                 // tile shape per instance (wavefronts along depth)
+  int wpe = 0;                         // minimum wavefronts per SIMD of the batched kernels (0: none)
   bool bound = false;
   int device = 0;
   hipStream_t stream = nullptr;
@@ -1490,6 +1491,16 @@ cw_status cw_batch_set_tile(cw_batch *b, int32_t index, int32_t tz_waves)
   return CW_OK;
 }
 
+cw_status cw_batch_set_occupancy(cw_batch *b, int32_t waves_per_simd)
+{
+  if (!b) return fail(CW_ERR_ARG, "null batch");
+  if (!batch_occupancy_supported(waves_per_simd))
+    return fail(CW_ERR_RANGE, "waves per SIMD must be 0 (no constraint), 7 or 8 (have %d)", waves_per_simd);
+  if (waves_per_simd != b->wpe) b->drop_graph();
+  b->wpe = waves_per_simd;
+  return CW_OK;
+}
+
 static size_t batch_bytes(const cw_batch *b)
 {
   return align256(b->sims.size() * sizeof(BatchInst)) + align256(b->sims.size() * sizeof(long));
@@ -1557,9 +1568,9 @@ cw_status cw_batch_set_graph(cw_batch *b, int32_t steps)
 static cw_status batch_launches(cw_batch *b, int parity, hipStream_t stream)
 {
   const int n = (int)b->sims.size();
-  HIPCHK(launch_velocity_batch(b->d_inst, b->d_tile0, n, b->tiles, parity, stream));
+  HIPCHK(launch_velocity_batch(b->d_inst, b->d_tile0, n, b->tiles, parity, b->wpe, stream));
   if (b->any_inject) HIPCHK(launch_inject_batch(b->d_inst, n, 0, parity, stream));
-  HIPCHK(launch_stress_batch(b->d_inst, b->d_tile0, n, b->tiles, parity, stream));
+  HIPCHK(launch_stress_batch(b->d_inst, b->d_tile0, n, b->tiles, parity, b->wpe, stream));
   if (b->any_inject) HIPCHK(launch_inject_batch(b->d_inst, n, 1, parity, stream));
   HIPCHK(launch_record_batch(b->d_inst, n, b->max_rec, parity, stream));
   HIPCHK(launch_step_done_batch(b->d_inst, n, stream));
@@ -1967,10 +1978,10 @@ cw_status cw_refined_step(cw_refined *r, int64_t nsteps)
   for (int64_t t = 0; t < nsteps; t++) {
     const int p = r->zones[0]->cur;
     HIPCHK(launch_interp(r->d_tr[p][0], r->ntr[p][0], r->nz, r->max_ns, r->stream));
-    HIPCHK(launch_velocity_batch(b->d_inst, b->d_tile0, n, b->tiles, p, r->stream));
+    HIPCHK(launch_velocity_batch(b->d_inst, b->d_tile0, n, b->tiles, p, b->wpe, r->stream));
     if (b->any_inject) HIPCHK(launch_inject_batch(b->d_inst, n, 0, p, r->stream));
     HIPCHK(launch_interp(r->d_tr[p][1], r->ntr[p][1], r->nz, r->max_ns, r->stream));
-    HIPCHK(launch_stress_batch(b->d_inst, b->d_tile0, n, b->tiles, p, r->stream));
+    HIPCHK(launch_stress_batch(b->d_inst, b->d_tile0, n, b->tiles, p, b->wpe, r->stream));
     if (b->any_inject) HIPCHK(launch_inject_batch(b->d_inst, n, 1, p, r->stream));
     HIPCHK(launch_record_batch(b->d_inst, n, b->max_rec, p, r->stream));
     HIPCHK(launch_step_done_batch(b->d_inst, n, r->stream));

@@ -216,9 +216,12 @@ struct BatchInst {
   double *traces;
   int64_t *step;
 };
-hipError_t launch_velocity_batch(const BatchInst *dev, const long *tile0, int count, long tiles, int parity,
+// wpe: minimum wavefronts per SIMD of the batched kernels' registers, one of
+// 0 (no constraint), 7, 8 (batch_occupancy_supported)
+bool batch_occupancy_supported(int wpe);
+hipError_t launch_velocity_batch(const BatchInst *dev, const long *tile0, int count, long tiles, int parity, int wpe,
                                  hipStream_t stream);
-hipError_t launch_stress_batch(const BatchInst *dev, const long *tile0, int count, long tiles, int parity,
+hipError_t launch_stress_batch(const BatchInst *dev, const long *tile0, int count, long tiles, int parity, int wpe,
                                hipStream_t stream);
 hipError_t launch_inject_batch(const BatchInst *dev, int count, int phase, int parity, hipStream_t stream);
 hipError_t launch_record_batch(const BatchInst *dev, int count, int max_rec, int parity, hipStream_t stream);

@@ -342,8 +342,11 @@ __device__ __forceinline__ bool batch_cell(const BatchInst &I, const StepArgs &a
   return true;
 }
 
-__global__ void __launch_bounds__(256) k_velocity_batch(const BatchInst *__restrict__ B,
-                                                        const long *__restrict__ tile0, int count, int parity)
+// WPE: the minimum wavefronts per SIMD the registers are sized for (1: no
+// constraint); the batch's tuner picks it with the tile shapes.
+template <int WPE>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE)))
+k_velocity_batch(const BatchInst *__restrict__ B, const long *__restrict__ tile0, int count, int parity)
 {
   const BatchInst &I = B[batch_instance(tile0, count, blockIdx.x)];
   const StepArgs a = I.a[parity];     // a private copy: the field stores cannot alias it
@@ -354,8 +357,9 @@ __global__ void __launch_bounds__(256) k_velocity_batch(const BatchInst *__restr
   velocity_column<StF32>(a, i, j, kb, live, mr, mt, mz);
 }
 
-__global__ void __launch_bounds__(256) k_stress_batch(const BatchInst *__restrict__ B,
-                                                      const long *__restrict__ tile0, int count, int parity)
+template <int WPE>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE)))
+k_stress_batch(const BatchInst *__restrict__ B, const long *__restrict__ tile0, int count, int parity)
 {
   const BatchInst &I = B[batch_instance(tile0, count, blockIdx.x)];
   const StepArgs a = I.a[parity];
@@ -403,20 +407,35 @@ hipError_t launch_stress_vec(const StepArgs &a, int storage, hipStream_t stream)
   });
 }
 
-hipError_t launch_velocity_batch(const BatchInst *dev, const long *tile0, int count, long tiles, int parity,
-                                 hipStream_t stream)
-{
-  if (tiles < 1 || tiles > 0x7fffffff) return hipErrorInvalidConfiguration;
-  hipLaunchKernelGGL(k_velocity_batch, dim3((unsigned)tiles), dim3(256), 0, stream, dev, tile0, count, parity);
-  return hipGetLastError();
-}
+bool batch_occupancy_supported(int wpe) { return wpe == 0 || wpe == 7 || wpe == 8; }
 
-hipError_t launch_stress_batch(const BatchInst *dev, const long *tile0, int count, long tiles, int parity,
+template <template <int> class K>
+static hipError_t launch_batch(int wpe, const BatchInst *dev, const long *tile0, int count, long tiles, int parity,
                                hipStream_t stream)
 {
   if (tiles < 1 || tiles > 0x7fffffff) return hipErrorInvalidConfiguration;
-  hipLaunchKernelGGL(k_stress_batch, dim3((unsigned)tiles), dim3(256), 0, stream, dev, tile0, count, parity);
+  const dim3 g((unsigned)tiles), b(256);
+  switch (wpe) {
+  case 0: hipLaunchKernelGGL(K<1>::f, g, b, 0, stream, dev, tile0, count, parity); break;
+  case 7: hipLaunchKernelGGL(K<7>::f, g, b, 0, stream, dev, tile0, count, parity); break;
+  case 8: hipLaunchKernelGGL(K<8>::f, g, b, 0, stream, dev, tile0, count, parity); break;
+  default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
+}
+template <int W> struct VelBatch { static constexpr auto f = k_velocity_batch<W>; };
+template <int W> struct StrBatch { static constexpr auto f = k_stress_batch<W>; };
+
+hipError_t launch_velocity_batch(const BatchInst *dev, const long *tile0, int count, long tiles, int parity, int wpe,
+                                 hipStream_t stream)
+{
+  return launch_batch<VelBatch>(wpe, dev, tile0, count, tiles, parity, stream);
+}
+
+hipError_t launch_stress_batch(const BatchInst *dev, const long *tile0, int count, long tiles, int parity, int wpe,
+                               hipStream_t stream)
+{
+  return launch_batch<StrBatch>(wpe, dev, tile0, count, tiles, parity, stream);
 }
 
 }  // namespace cw

@@ -33,7 +33,7 @@ EXPORTS = ("cw_create", "cw_set_material", "cw_set_material_rz", "cw_set_pml", "
            "cw_ricker", "cw_destroy", "cw_last_error", "cw_profile", "cw_profile_read",
            "cw_set_path", "cw_set_storage", "cw_stream_probe", "cw_set_graph", "cw_set_adjoint",
            "cw_set_region_moduli", "cw_gradient", "cw_batch_create", "cw_batch_set_tile",
-           "cw_batch_workspace_bytes", "cw_batch_bind", "cw_batch_set_graph", "cw_batch_step", "cw_batch_destroy",
+           "cw_batch_workspace_bytes", "cw_batch_bind", "cw_batch_set_occupancy", "cw_batch_set_graph", "cw_batch_step", "cw_batch_destroy",
            "cw_refined_create", "cw_refined_cells", "cw_refined_set_material_rz", "cw_refined_set_pml",
            "cw_refined_cfl_dt", "cw_refined_set_dt", "cw_refined_add_source", "cw_refined_add_receiver",
            "cw_refined_set_trace_capacity", "cw_refined_workspace_bytes", "cw_refined_bind", "cw_refined_step",
@@ -106,6 +106,7 @@ def load():
         "cw_gradient": [P, I64, I64, DP, DP, DP],
         "cw_batch_create": [ctypes.POINTER(P), I32, ctypes.POINTER(P)],
         "cw_batch_set_tile": [P, I32, I32],
+        "cw_batch_set_occupancy": [P, I32],
         "cw_batch_workspace_bytes": [P, ctypes.POINTER(ctypes.c_uint64)],
         "cw_batch_bind": [P, P, ctypes.c_uint64],
         "cw_batch_set_graph": [P, I32],
@@ -379,6 +380,10 @@ class Batch:
 
     def set_tile(self, index: int, tz_waves: int):
         _check(self.lib.cw_batch_set_tile(self.h, int(index), int(tz_waves)))
+
+    def set_occupancy(self, waves_per_simd: int):
+        """Minimum wavefronts per SIMD of the batched kernels: 0 (none), 7 or 8."""
+        _check(self.lib.cw_batch_set_occupancy(self.h, int(waves_per_simd)))
 
     def bind(self):
         import torch

@@ -126,14 +126,46 @@ def test_batch_refuses_mismatched_instances():
 def test_autotuner_caches_its_choice(tmp_path, monkeypatch):
     from paper_2302_13907_amd import autotune
     cache = str(tmp_path / "tiles.json")
-    tz = autotune.best_tile(12, 4, 200, cache=cache, steps=2)
-    assert tz in (1, 2, 4)
+    tz, w = autotune.best_config(12, 4, 200, cache=cache, steps=2)
+    assert tz in autotune.SHAPES and w in autotune.OCCUPANCY
     import json
     db = json.load(open(cache))
-    assert len(db) == 1 and list(db.values())[0]["tz_waves"] == tz
+    assert len(db) == 1
+    e = list(db.values())[0]
+    assert (e["tz_waves"], e["waves_per_simd"]) == (tz, w)
+    assert len(e["seconds_per_step"]) == len(autotune.SHAPES) * len(autotune.OCCUPANCY)
     # a second request is answered from the cache, without measuring
     monkeypatch.setattr(autotune, "measure", lambda *a, **k: (_ for _ in ()).throw(AssertionError("measured")))
+    assert autotune.best_config(12, 4, 200, cache=cache) == (tz, w)
     assert autotune.best_tile(12, 4, 200, cache=cache) == tz
+
+
+def test_batch_occupancy_variants_are_bitwise_equal():
+    """The batched kernels compiled for each register budget give bitwise
+    the same results (same operations, other register allocation)."""
+    from paper_2302_13907_amd import autotune
+    runs = []
+    for w in autotune.OCCUPANCY:
+        sims = [_sim(spec, STEPS) for spec in SPECS]
+        b = cwell.Batch(sims)
+        b.set_occupancy(w)
+        b.bind()
+        b.step(STEPS)
+        runs.append([_state(s) for s in sims])
+        b.close()
+        for s in sims:
+            s.close()
+    for other in runs[1:]:
+        for (ta, fa), (tb, fb) in zip(runs[0], other):
+            assert np.array_equal(ta, tb)
+            for n in FIELDS:
+                assert np.array_equal(fa[n], fb[n]), n
+    s = _sim(SPECS[0], STEPS)
+    b = cwell.Batch([s])
+    with pytest.raises(cwell.CwellError):
+        b.set_occupancy(5)
+    b.close()
+    s.close()
 
 
 def test_batch_instances_match_oracle():
