@@ -204,7 +204,10 @@ cw_status cw_set_storage(cw_sim *s, int32_t storage);
    CW_PATH_TWO_PASS: a velocity launch and a stress launch per step, small
    launches that add the force and the stress sources (in the order they
    were added) after them when there are any, then one launch that samples
-   the receivers, sets the float16 scales and advances the step counter;
+   the receivers, sets the float16 scales and advances the step counter
+   (with float32 storage and the one-cell velocity update, the next step's
+   velocity launch does that work for the step before it, and only the last
+   step of a cw_step call or of a captured graph has this launch);
    any number of sources and any storage; one workgroup
    per (ring, theta row) depth segment, 4 depth cells per thread when nz is
    a multiple of 4 and a ring of one float32 array is under 4 GiB, one cell
@@ -217,8 +220,11 @@ cw_status cw_set_storage(cw_sim *s, int32_t storage);
    two-pass step, with the velocity and the stress update one cell per
    thread for float32 storage (1 % and 3 % faster per launch at the
    production size than four cells per thread; the one-cell stress update
-   adds the stress sources itself, so that a step with only stress sources
-   is three launches); otherwise exactly CW_PATH_TWO_PASS.  Results of the two kernel forms agree to float32
+   adds the stress sources itself, and a step's receivers and step counter
+   are taken by the next step's velocity launch, so that a step with only
+   stress sources is two launches, plus one receiver launch after the last
+   step of a cw_step call or of a captured graph); otherwise exactly
+   CW_PATH_TWO_PASS.  Results of the two kernel forms agree to float32
    rounding. */
 enum { CW_PATH_AUTO = 0, CW_PATH_TWO_PASS, CW_PATH_FUSED };
 cw_status cw_set_path(cw_sim *s, int32_t path);
@@ -242,7 +248,8 @@ cw_status cw_set_graph(cw_sim *s, int32_t steps);
    clears the records.  cw_profile_read waits for the recorded work and
    returns, for kernel `kernel` (CW_K_*), the summed device time in
    milliseconds and the number of launches recorded.  CW_K_RECORD is the
-   step's last launch (receivers, scales, step counter); CW_K_INJECT the
+   receiver launch (receivers, scales, step counter; with the default
+   float32 path once per call, the velocity launches time the rest); CW_K_INJECT the
    source launches. */
 enum { CW_K_VELOCITY = 0, CW_K_STRESS, CW_K_FUSED, CW_K_INJECT, CW_K_RECORD, CW_K_COUNT };
 cw_status cw_profile(cw_sim *s, int32_t enable);

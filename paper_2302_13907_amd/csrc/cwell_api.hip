@@ -799,10 +799,18 @@ cw_status cw_step(cw_sim *s, int64_t nsteps)
   // reproduce bitwise)
   const bool vec_velocity = vec && !(s->path == CW_PATH_AUTO && velocity_one_cell(s->storage));
   const bool vec_stress = vec && !(s->path == CW_PATH_AUTO && stress_one_cell(s->storage));
-  auto velocity = [&](const StepArgs &a) {
+  auto velocity = [&](const StepArgs &a, const TailArgs *tail) {
     return vec_velocity ? launch_velocity_vec(a, s->storage, s->stream)
-                        : launch_velocity_basic(a, s->storage, s->stream);
+                        : launch_velocity_basic(a, s->storage, s->stream, tail);
   };
+  // With the one-cell float32 velocity update, a step's receivers and step
+  // counter are taken by the first workgroups of the next step's velocity
+  // launch (it reads only the buffer they sample and does not read the
+  // counter), so that only the last step of a run of steps -- a call, or a
+  // captured graph -- has a launch of its own for them.  The 16-bit storages
+  // keep the tail launch, which also sets the float16 scales.
+  const bool fold_tail = !vec_velocity && s->storage == ST_F32;
+  TailArgs tail{s->d_rec, nrec, std::max(1, (nrec + 3) / 4), s->d_step, s->trace_cap, s->d_traces, s->d_done};
   auto stress = [&](const StepArgs &a) {
     return vec_stress ? launch_stress_vec(a, s->storage, s->stream)
                       : launch_stress_basic(a, s->storage, s->stream);
@@ -824,7 +832,10 @@ cw_status cw_step(cw_sim *s, int64_t nsteps)
   // velocity update, force sources (if any), stress update (the one-cell form
   // adds the stress sources itself, the four-cell one takes a source launch),
   // the tail: three launches for the default float32 path
-  auto two_pass_step = [&]() -> cw_status {
+  // prev_tail: fold the previous step's tail into this step's velocity
+  // launch; own_tail: end the step with the tail launch (otherwise the next
+  // step's velocity launch takes it)
+  auto two_pass_step = [&](bool prev_tail, bool own_tail) -> cw_status {
     StepArgs a = step_args(s, s->cur, 1 - s->cur);
     if (s->ninject) {
       a.inj = s->d_inject;
@@ -833,7 +844,7 @@ cw_status cw_step(cw_sim *s, int64_t nsteps)
       a.inj_i1 = s->inj_i1;
       a.step = s->d_step;
     }
-    if ((st = timed(s, CW_K_VELOCITY, [&] { return velocity(a); })) != CW_OK) return st;
+    if ((st = timed(s, CW_K_VELOCITY, [&] { return velocity(a, prev_tail ? &tail : nullptr); })) != CW_OK) return st;
     if (s->force_src &&
         (st = timed(s, CW_K_INJECT, [&] { return launch_sources(a, 0, s->storage, s->stream); })) != CW_OK)
       return st;
@@ -841,7 +852,9 @@ cw_status cw_step(cw_sim *s, int64_t nsteps)
     if (s->stress_src && vec_stress &&
         (st = timed(s, CW_K_INJECT, [&] { return launch_sources(a, 1, s->storage, s->stream); })) != CW_OK)
       return st;
-    return finish_step(a);
+    if (own_tail) return finish_step(a);
+    s->cur = 1 - s->cur;
+    return CW_OK;
   };
   auto fused_step = [&](int64_t n) -> cw_status {   // source amplitudes of step n go in as arguments
     const StepArgs a = step_args(s, s->cur, 1 - s->cur);
@@ -881,6 +894,7 @@ cw_status cw_step(cw_sim *s, int64_t nsteps)
   }
   const bool use_graph = s->graph_steps > 0 && !s->profiling;
   int64_t done = 0;
+  bool pending = false;                        // the previous ordinary step left its tail to this one
   while (done < nsteps) {
     if (use_graph && s->cur == 0 && nsteps - done >= s->graph_steps) {
       if (!s->graph_exec) {
@@ -892,7 +906,8 @@ cw_status cw_step(cw_sim *s, int64_t nsteps)
         s->stream = s->capture_stream;
         const hipError_t eb = hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal);
         cw_status cst = eb == hipSuccess ? CW_OK : fail(CW_ERR_HIP, "graph capture: %s", hipGetErrorString(eb));
-        for (int g = 0; g < s->graph_steps && cst == CW_OK; g++) cst = two_pass_step();
+        for (int g = 0; g < s->graph_steps && cst == CW_OK; g++)
+          cst = two_pass_step(fold_tail && g > 0, !fold_tail || g == s->graph_steps - 1);
         hipGraph_t gr = nullptr;
         const hipError_t ee = eb == hipSuccess ? hipStreamEndCapture(s->stream, &gr) : hipSuccess;
         s->stream = user;
@@ -913,7 +928,11 @@ cw_status cw_step(cw_sim *s, int64_t nsteps)
       s->nstep += s->graph_steps;
       continue;
     }
-    if ((st = two_pass_step()) != CW_OK) return st;
+    // the last step of the call, or one a graph replay follows, runs its own tail
+    const bool graph_next = use_graph && s->cur == 1 && nsteps - done - 1 >= s->graph_steps;
+    const bool own = !fold_tail || done + 1 == nsteps || graph_next;
+    if ((st = two_pass_step(pending, own)) != CW_OK) return st;
+    pending = !own;
     done++;
     s->nstep++;
   }

@@ -167,7 +167,19 @@ int fused_tiles(int nt, int nz, int *own_rows, int *ntile_z);
 size_t fused_lds_bytes(int nr);                 // dynamic LDS of the fused step
 constexpr int kMaxFusedRings = 2048;            // nr limit of the fused step (LDS tables)
 hipError_t launch_fused(const FusedArgs &f, hipStream_t stream);
-hipError_t launch_velocity_basic(const StepArgs &a, int storage, hipStream_t stream);
+// The previous step's receivers and step counter, folded into the next
+// velocity launch (float32 storage): blocks = ceil(max(nrec, 1) / 4)
+// workgroups take them; done is a zeroed finish counter, left at zero.
+struct TailArgs {
+  const Receiver *rec;
+  int nrec, blocks;
+  int64_t *step;
+  int64_t cap;
+  double *traces;
+  unsigned *done;
+};
+// tail: nullptr, or the previous step's tail to fold in (float32 only)
+hipError_t launch_velocity_basic(const StepArgs &a, int storage, hipStream_t stream, const TailArgs *tail = nullptr);
 hipError_t launch_stress_basic(const StepArgs &a, int storage, hipStream_t stream);
 // The sources of one phase of a.inj in a solo step (0: forces, after the
 // velocity update; 1: stresses, after a stress update that does not add

@@ -3,8 +3,10 @@
 // updates are separate launches; the one-cell stress update adds the step's
 // stress sources itself (the other forms take a small source launch, as do
 // force sources after the velocity update); a last launch samples the
-// receivers, sets the float16 scales and advances the step counter.  The energy and the batched source and receiver
-// kernels live here too.  The fields may be stored in float32, float16
+// receivers, sets the float16 scales and advances the step counter (with
+// float32 storage only after the last step of a run of steps: the velocity
+// launch of the next step does that work for the step before it).  The
+// energy and the batched source and receiver kernels live here too.  The fields may be stored in float32, float16
 // (with a power-of-two scale per field, chosen on the device from the
 // largest magnitude written in the previous step) or bfloat16; every
 // arithmetic operation is float32.
@@ -151,9 +153,66 @@ __device__ __forceinline__ void track_max(unsigned *slots, float x)
     atomicMax(&slots[(blockIdx.x + (threadIdx.x >> 6)) & (kMaxSlots - 1)], __builtin_bit_cast(unsigned, m));
 }
 
-template <class S>
-__global__ void __launch_bounds__(256) k_velocity_basic(StepArgs a, int nbx)
+// One wavefront per receiver; float64 sum over the ring in a fixed order.
+// Samples the level-(n+1) buffer a.out, or with kIn the level-n buffer a.in
+// (the previous step's result).
+template <class S, bool kIn = false>
+__device__ void record_one(const Receiver &r, int m, int64_t step, int64_t cap, const StepArgs &a, double *traces)
 {
+  const int lane = threadIdx.x & 63;
+  const int j0 = r.j < 0 ? 0 : r.j, j1 = r.j < 0 ? a.nt : r.j + 1;
+  const float *o = kIn ? a.scl_in : a.scl_out;
+  const float *const *F = kIn ? a.in : a.out;
+  double acc = 0.0;
+  for (int j = j0 + lane; j < j1; j += 64) {
+    const size_t p = at(a, r.i, j, r.k);
+    if (r.kind == 0)
+      acc += (double)S::ld(F[SRR], p, o[SRR]) + (double)S::ld(F[STT], p, o[STT]) +
+             (double)S::ld(F[SZZ], p, o[SZZ]);
+    else
+      acc += (double)S::ld(F[r.field], p, o[r.field]);
+  }
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if (lane == 0) {
+    const double cnt = (double)(j1 - j0);
+    traces[(size_t)m * cap + step] = r.kind == 0 ? -acc / (3.0 * cnt) : acc / cnt;
+  }
+}
+
+
+// The receivers and the step counter of the previous step, done by the
+// first T.blocks workgroups of the velocity launch that follows it instead
+// of by a launch of their own: workgroup b samples receivers 4b .. 4b+3 (one
+// wavefront each) from the buffer this step reads (the previous step's
+// result, which no launch of this step writes); the last of these
+// workgroups to finish, once every one of them has read the counter,
+// advances it.  T.done is a zeroed counter of finished workgroups, left at
+// zero.  No other workgroup of the launch reads the step counter.
+template <class S>
+__device__ void previous_step_tail(const TailArgs &T, const StepArgs &a)
+{
+  const int m = (int)blockIdx.x * 4 + (int)(threadIdx.x >> 6);
+  if (m < T.nrec) record_one<S, true>(T.rec[m], m, *T.step, T.cap, a, T.traces);
+  __shared__ unsigned ticket;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    ticket = atomicAdd(T.done, 1u);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0 && ticket == (unsigned)T.blocks - 1) {
+    __threadfence();
+    *T.done = 0u;
+    *T.step += 1;
+  }
+}
+
+// kTail: the first T.blocks workgroups first finish the previous step
+// (previous_step_tail)
+template <class S, bool kTail>
+__global__ void __launch_bounds__(256) k_velocity_basic(StepArgs a, int nbx, TailArgs T)
+{
+  if (kTail && (int)blockIdx.x < T.blocks) previous_step_tail<S>(T, a);
   const int t = xcd_tile(blockIdx.x, gridDim.x);
   const int bx = t % nbx;
   const int k = bx * 256 + threadIdx.x;
@@ -401,29 +460,6 @@ __global__ void __launch_bounds__(256) k_inject_batch(const BatchInst *B, int ph
   inject_all<StF32>(I.inject, I.ninj, phase, *I.step, I.a[parity]);
 }
 
-// One wavefront per receiver; float64 sum over the ring in a fixed order.
-template <class S>
-__device__ void record_one(const Receiver &r, int m, int64_t step, int64_t cap, const StepArgs &a, double *traces)
-{
-  const int lane = threadIdx.x & 63;
-  const int j0 = r.j < 0 ? 0 : r.j, j1 = r.j < 0 ? a.nt : r.j + 1;
-  const float *o = a.scl_out;
-  double acc = 0.0;
-  for (int j = j0 + lane; j < j1; j += 64) {
-    const size_t p = at(a, r.i, j, r.k);
-    if (r.kind == 0)
-      acc += (double)S::ld(a.out[SRR], p, o[SRR]) + (double)S::ld(a.out[STT], p, o[STT]) +
-             (double)S::ld(a.out[SZZ], p, o[SZZ]);
-    else
-      acc += (double)S::ld(a.out[r.field], p, o[r.field]);
-  }
-  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-  if (lane == 0) {
-    const double cnt = (double)(j1 - j0);
-    traces[(size_t)m * cap + step] = r.kind == 0 ? -acc / (3.0 * cnt) : acc / cnt;
-  }
-}
-
 // New float16 scale of field q: 2^(e - target) with max|v| = f 2^e,
 // f in [0.5, 1); unchanged while the field is still identically zero.  The
 // maxima slots are cleared for the next step.
@@ -575,13 +611,19 @@ hipError_t dispatch(int storage, F &&f)
 
 }  // namespace
 
-hipError_t launch_velocity_basic(const StepArgs &a, int storage, hipStream_t stream)
+hipError_t launch_velocity_basic(const StepArgs &a, int storage, hipStream_t stream, const TailArgs *tail)
 {
   const int nbx = (a.nz + 255) / 256;
   const long g = (long)nbx * a.nt * a.nr;
   if (g > 0x7fffffff) return hipErrorInvalidConfiguration;
+  if (tail) {
+    if (storage != ST_F32 || tail->blocks < 1 || tail->blocks > g) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_velocity_basic<StF32, true>), dim3((unsigned)g), dim3(256), 0, stream, a, nbx, *tail);
+    return hipGetLastError();
+  }
   return dispatch(storage, [&](auto s) {
-    hipLaunchKernelGGL(k_velocity_basic<decltype(s)>, dim3((unsigned)g), dim3(256), 0, stream, a, nbx);
+    hipLaunchKernelGGL((k_velocity_basic<decltype(s), false>), dim3((unsigned)g), dim3(256), 0, stream, a, nbx,
+                       TailArgs{});
     return hipGetLastError();
   });
 }

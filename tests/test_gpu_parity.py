@@ -320,6 +320,41 @@ def test_graph_replay_matches_ordinary_launches(storage):
     graph.close()
 
 
+def test_folded_step_tail_matches_per_step_tails():
+    """With float32 storage a step's receivers and step counter are taken by
+    the next step's velocity launch, and only the last step of a call (or of
+    a captured graph) has a tail launch of its own.  Stepping one step per
+    call (every step its own tail) must give bitwise the same traces and
+    fields as long calls, split calls and graph replay, with force sources
+    (whose launch reads the counter the velocity launch advanced), stress
+    sources, and receivers of every field."""
+    c = CASES["ragged_all_sources"]
+    shape, h, steps = c["shape"], 5e-3, 120
+    med = _cased(shape, h, z_top=shape[2] * h / 2)
+    recs = [("pressure", 0, -1, k, None) for k in range(3, shape[2] - 3, 9)]
+    recs += [("field", 2, 0, 42, f) for f in FIELDS] + [("field", 5, 7, 22, f) for f in FIELDS]
+    sc = Scenario(shape=shape, h=(h, h), medium=med, steps=steps, npml=c["npml"], sources=c["sources"],
+                  receivers=recs)
+    announce("folded step tail: per-step calls vs long, split and graph-replayed calls")
+    runs = {}
+    for name, chunks, graph in (("per_step", [1] * steps, 0), ("long", [steps], 0),
+                                ("split", [1, 7, 40, 1, 71], 0), ("graph", [3, 50, 67], 8)):
+        s = make_sim(sc)
+        s.set_graph(graph)
+        for n in chunks:
+            s.step(n)
+        s.sync()
+        assert s.steps_done == steps
+        runs[name] = (s.traces(), {f: s.field(f) for f in FIELDS})
+        s.close()
+    ref_tr, ref_f = runs["per_step"]
+    assert np.abs(ref_tr).max() > 0
+    for name, (tr, f) in runs.items():
+        assert np.array_equal(tr, ref_tr), name
+        for n in FIELDS:
+            assert np.array_equal(f[n], ref_f[n]), (name, n)
+
+
 def test_many_sources_fall_back_to_two_pass():
     """More injections than the fused step takes: auto uses the two-pass
     kernels, an explicit fused request is refused."""
