@@ -46,6 +46,10 @@ ORACLE_PINS = {
         "tests/test_oracle_pins.py::test_reciprocity",
     "point source in a homogeneous fluid: closed form, 2nd order":
         "tests/test_oracle_pins.py::test_point_source_closed_form",
+    "z stencils, leapfrog order, ring-source volume, pressure receiver: rigid pipe against the 1-D staggered scheme":
+        "tests/test_oracle_rigid_pipe.py::test_rigid_pipe_plane_wave_matches_1d_scheme",
+    "plane wave in a rigid pipe travels at the fluid speed":
+        "tests/test_oracle_rigid_pipe.py::test_rigid_pipe_plane_wave_travels_at_the_fluid_speed",
     "fluid-solid coupling: low-frequency tube-wave speed":
         "tests/test_oracle_physics.py::test_tube_wave_speed",
     "shear stencils, zero shear at fluid contacts: torsional casing wave":

@@ -127,6 +127,7 @@ def _pins():
     import test_oracle_averages as tav
     import test_oracle_physics as tph
     import test_oracle_pins as tp
+    import test_oracle_rigid_pipe as trp
     pins = [("Ricker zeros and extrema", tp.test_ricker_properties),
             ("hand-derived staggered averages", tav.test_coefficient_tables_match_hand_values)]
     pins += [("impulse response applies the averages, %s" % c, (lambda cc=c: tav.test_step_applies_hand_values(cc)))
@@ -143,6 +144,7 @@ def _pins():
              ("Courant margin", tp.test_cfl_margin),
              ("Courant margin next to the axis", tp.test_cfl_margin_near_axis),
              ("operators against the paper's matrices", tp.test_operators_match_paper_matrices),
+             ("rigid pipe: plane wave against the 1-D scheme", trp.test_rigid_pipe_plane_wave_matches_1d_scheme),
              ("torsional casing wave", tph.test_torsion_wave_in_casing),
              ("layer reflection bound", tph.test_pml_reflection_bound)]
     return pins
