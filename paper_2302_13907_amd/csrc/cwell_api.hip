@@ -1360,12 +1360,10 @@ cw_status cw_gradient(cw_sim *s, int64_t n0, int64_t n1, double *loss, double *g
   };
   // forward from rest, a checkpoint at the start of every segment
   if ((st = zero_state(s)) != CW_OK) return st;
-  for (int64_t t = 0; t < N; t++) {
-    if (t % C == 0) {
-      ck_cur[t / C] = s->cur;
-      if ((st = state_copy(s->adj_ckpt + (size_t)(t / C) * nst, s->cur, true)) != CW_OK) return st;
-    }
-    if ((st = cw_step(s, 1)) != CW_OK) return st;
+  for (int64_t t = 0; t < N; t += C) {
+    ck_cur[t / C] = s->cur;
+    if ((st = state_copy(s->adj_ckpt + (size_t)(t / C) * nst, s->cur, true)) != CW_OK) return st;
+    if ((st = cw_step(s, std::min<int64_t>(C, N - t))) != CW_OK) return st;
   }
   // loss and the receivers' adjoint weights
   std::vector<double> tr((size_t)nrec * s->trace_cap);

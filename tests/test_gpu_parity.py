@@ -320,6 +320,33 @@ def test_graph_replay_matches_ordinary_launches(storage):
     graph.close()
 
 
+def test_rigid_pipe_plane_wave_gpu():
+    """The oracle's rigid-pipe pin on the device: a fluid column walled by a
+    ring of density 1e30, the same stress injected on every fluid ring; the
+    float32 traces follow the oracle within the trace tolerance and stay the
+    same on every ring (a plane wave)."""
+    import test_oracle_rigid_pipe as rp
+    nr, nt, nz, h = rp.NR, rp.NT, rp.NZ, rp.H
+    rho = np.full((nr, nt, nz), rp.RHO)
+    rho[nr - 1] = 1e30
+    med = (rho, np.full((nr, nt, nz), rp.K), np.zeros((nr, nt, nz)))
+    steps = 700
+    srcs = [("volume", i, -1, rp.KS, 2.0 * math.pi * (i + 0.5) * h ** 3) for i in range(nr - 1)]
+    recs = [("pressure", i, -1, k, None) for k in rp.KR for i in (0, 2, nr - 2)]
+    sc = Scenario(shape=(nr, nt, nz), h=(h, h), medium=med, steps=steps, f0=rp.F0, sources=srcs,
+                  receivers=recs)
+    announce("rigid pipe plane wave, %s, %d steps" % ((nr, nt, nz), steps))
+    tr_g, f_g = run_gpu(sc)
+    tr_o, _ = run_oracle(sc)
+    e = rel_l2(tr_g, tr_o)
+    announce("  trace relL2 %.2e" % e)
+    assert e <= TRACE_TOL, e
+    for q in range(0, len(recs), 3):
+        ring0 = tr_g[q]
+        for d in (1, 2):
+            assert np.abs(tr_g[q + d] - ring0).max() <= 1e-5 * np.abs(ring0).max(), (q, d)
+
+
 def test_folded_step_tail_matches_per_step_tails():
     """With float32 storage a step's receivers and step counter are taken by
     the next step's velocity launch, and only the last step of a call (or of
