@@ -432,23 +432,29 @@ def graph_replay(path: str, graph: int = 20, steps: int = 300):
 def adjoint_gradient():
     """Seconds per adjoint gradient on the adjoint workload (forward with
     checkpoints, segment recomputation, adjoint steps), next to one plain
-    forward run of the same steps."""
+    forward run of the same steps; and the same gradient with one segment
+    (the strain rates of all steps kept on the device, nothing recomputed)."""
     import numpy as np
     import torch
     from paper_2302_13907_amd import cwell, inputs
     w = inputs.adjoint_case()
     x = w.extra
     log("adjoint gradient on %s" % w.name)
-    s = cwell.Sim(w.nr, w.nt, w.nz, w.dr, w.dz)
-    s.set_material(*w.medium_rz())
-    s.set_pml(w.npml, w.npml, w.pml_rc, math.pi * w.f0)
-    dt = w.cfl_fraction * s.cfl_dt()
-    s.set_dt(dt)
-    s.add_source("volume", 0, -1, w.src_k, cwell.ricker(w.f0, (np.arange(w.steps) + 0.5) * dt))
-    for k in w.rec_k:
-        s.add_receiver("pressure", 0, -1, k)
-    s.set_adjoint(w.steps, x["checkpoint_every"], x["region"])
-    s.bind("cuda:0")
+
+    def make(every):
+        s = cwell.Sim(w.nr, w.nt, w.nz, w.dr, w.dz)
+        s.set_material(*w.medium_rz())
+        s.set_pml(w.npml, w.npml, w.pml_rc, math.pi * w.f0)
+        dt = w.cfl_fraction * s.cfl_dt()
+        s.set_dt(dt)
+        s.add_source("volume", 0, -1, w.src_k, cwell.ricker(w.f0, (np.arange(w.steps) + 0.5) * dt))
+        for k in w.rec_k:
+            s.add_receiver("pressure", 0, -1, k)
+        s.set_adjoint(w.steps, every, x["region"])
+        s.bind("cuda:0")
+        return s
+
+    s = make(x["checkpoint_every"])
     s.step(10)                                    # warm-up of the forward kernels
     s.sync()
     s.reset()
@@ -467,9 +473,21 @@ def adjoint_gradient():
     torch.cuda.empty_cache()
     if not (np.all(np.isfinite(gm)) and np.all(np.isfinite(gk))):
         raise RuntimeError("non-finite gradient")
+    s = make(w.steps)
+    t0 = time.perf_counter()
+    loss1, gm1, gk1 = s.gradient(x["window"])
+    grad1 = time.perf_counter() - t0
+    ws1 = s.workspace_bytes()
+    s.close()
+    del s
+    torch.cuda.empty_cache()
+    if loss1 != loss or not (np.array_equal(gm1, gm) and np.array_equal(gk1, gk)):
+        raise RuntimeError("the one-segment gradient differs from the checkpointed one")
     return {"workload": w.name, "parameters": 2 * x["region"][3], "checkpoint_every": x["checkpoint_every"],
             "s_per_gradient": round(grad, 3), "forward_s": round(fwd, 3), "ratio_to_forward": round(grad / fwd, 2),
-            "workspace_GB": round(ws / 1e9, 2), "loss": loss}
+            "workspace_GB": round(ws / 1e9, 2), "loss": loss,
+            "one_segment": {"s_per_gradient": round(grad1, 3), "ratio_to_forward": round(grad1 / fwd, 2),
+                            "workspace_GB": round(ws1 / 1e9, 2)}}
 
 
 def batched_form(small: bool = False, steps: int = 40, graph: int = 20):

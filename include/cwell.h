@@ -268,7 +268,10 @@ cw_status cw_ricker(double f0, const double *t, int64_t n, double *out);
    keeping a checkpoint of the whole state every checkpoint_every steps,
    then the discrete adjoint of the step backwards: segment by segment it
    recomputes the forward steps from the segment's checkpoint (storing the
-   region's strain rates) and then takes their adjoint steps, adding each
+   region's strain rates; those of the last segment are stored by the
+   forward run itself, so checkpoint_every >= nsteps recomputes nothing, at
+   the price of a strain-rate buffer for all nsteps steps) and then takes
+   their adjoint steps, adding each
    step's contribution to the gradient (Eq. (1): the stress update is linear
    in lambda, mu and, through the harmonic means of the shear nodes, in the
    cells' mu).  Outputs: *loss, grad_mu[nbins] = dL/dmu_b (K fixed),
@@ -277,7 +280,7 @@ cw_status cw_ricker(double f0, const double *t, int64_t n, double *out);
    the two-pass kernels only.
 
    cw_set_adjoint: before cw_bind, after cw_set_pml (its buffers -- the
-   adjoint state, nsteps / checkpoint_every checkpoints, one segment of
+   adjoint state, one checkpoint per segment but the last, one segment of
    strain rates -- become part of the workspace; the trace capacity is
    raised to nsteps).  The region must lie clear of the absorbing layer and
    the grid's edges: 1 <= i0 < i1 <= nr - max(npml_r, 2), max(npml_z + 1, 1)

@@ -126,7 +126,7 @@ struct cw_sim {
   float *adj_pz[NPSI_Z] = {};
   float *adj_T[9] = {};
   float *adj_C[6] = {};         // dt-scaled effective moduli and buoyancies (the medium's layout)
-  float *adj_ckpt = nullptr;    // checkpoints [ncp][9 n + 12 slab_r + 6 slab_z]
+  float *adj_ckpt = nullptr;    // checkpoints [ncp - 1][9 n + 12 slab_r + 6 slab_z] (none of the last segment)
   float *adj_Z = nullptr;       // strain rates of one segment [every][6][region nodes]
   double *adj_glam = nullptr, *adj_gmu = nullptr;   // per region cell
   float *adj_w = nullptr;       // receiver adjoint weights [steps][receivers]
@@ -219,7 +219,7 @@ size_t adj_bytes(const cw_sim *s)
              + 9 * s->n                        // term adjoints
              + 6 * s->nm                       // effective coefficients
              + 2 * 64                          // alignment of the two blocks above
-             + ncp * adj_state_floats(s)       // checkpoints
+             + (ncp - 1) * adj_state_floats(s) // checkpoints (the last segment needs none)
              + (size_t)s->adj_every * 6 * adj_region_nodes(s)
              + (size_t)s->adj_steps * s->receivers.size();
   return f * sizeof(float) + 2 * adj_region_cells(s) * sizeof(double) + 1024;
@@ -662,7 +662,7 @@ cw_status cw_bind(cw_sim *s, void *workspace, uint64_t bytes, void *stream)
     p = align64(p);
     for (int q = 0; q < 6; q++) { s->adj_C[q] = p; p += s->nm; }
     const size_t ncp = (size_t)((s->adj_steps + s->adj_every - 1) / s->adj_every);
-    s->adj_ckpt = p; p += ncp * adj_state_floats(s);
+    s->adj_ckpt = p; p += (ncp - 1) * adj_state_floats(s);
     s->adj_Z = p; p += (size_t)s->adj_every * 6 * adj_region_nodes(s);
     s->adj_w = p; p += (size_t)s->adj_steps * s->receivers.size();
     char *c = (char *)p;
@@ -1260,7 +1260,7 @@ cw_status cw_set_adjoint(cw_sim *s, int64_t nsteps, int32_t checkpoint_every, in
   if ((st = check_adjoint_region(&t)) != CW_OK) return st;
   s->adj = true;
   s->adj_steps = nsteps;
-  s->adj_every = checkpoint_every;
+  s->adj_every = (int)std::min<int64_t>(checkpoint_every, std::max<int64_t>(nsteps, 1));   // a segment holds at most the run
   s->adj_i0 = i0; s->adj_i1 = i1; s->adj_k0 = k0; s->adj_nb = nbins; s->adj_br = bin_rows;
   if (s->trace_cap < nsteps) s->trace_cap = nsteps;
   s->adj_mu0.clear();
@@ -1358,12 +1358,38 @@ cw_status cw_gradient(cw_sim *s, int64_t n0, int64_t n1, double *loss, double *g
     }
     return CW_OK;
   };
-  // forward from rest, a checkpoint at the start of every segment
+  // the adjoint step's arguments and coefficients (the capture of the strain
+  // rates needs the grid's metric from them)
+  const StepArgs sa = step_args(s, 0, 1);
+  AdjArgs a{};
+  a.nr = s->nr; a.nt = s->nt; a.nz = s->nz; a.npr = s->npr; a.npz = s->npz; a.nzs = nzs_of(s);
+  a.dt = sa.dt; a.inv_dr = sa.inv_dr; a.inv_dz = sa.inv_dz; a.inv_dth = sa.inv_dth;
+  a.inv_rc = sa.inv_rc; a.inv_rf = sa.inv_rf;
+  a.rho = sa.rho; a.lam = sa.lam; a.mu = sa.mu; a.m_ring = sa.m_ring; a.m_row = sa.m_row;
+  for (int q = 0; q < NF; q++) a.fb[q] = s->adj_fb[q];
+  for (int q = 0; q < NPSI_R; q++) a.pr[q] = s->adj_pr[q];
+  for (int q = 0; q < NPSI_Z; q++) a.pz[q] = s->adj_pz[q];
+  for (int q = 0; q < 9; q++) a.T[q] = s->adj_T[q];
+  for (int q = 0; q < 6; q++) a.C[q] = s->adj_C[q];
+  a.tab_r = sa.tab_r; a.tab_z = sa.tab_z;
+  HIPCHK(launch_adjoint_coefs(a, s->stream));
+  // forward from rest, a checkpoint at the start of every segment but the
+  // last, whose strain rates are stored as it is run, so that the backward
+  // sweep starts without recomputing it (with one segment nothing is
+  // recomputed)
   if ((st = zero_state(s)) != CW_OK) return st;
   for (int64_t t = 0; t < N; t += C) {
-    ck_cur[t / C] = s->cur;
-    if ((st = state_copy(s->adj_ckpt + (size_t)(t / C) * nst, s->cur, true)) != CW_OK) return st;
-    if ((st = cw_step(s, std::min<int64_t>(C, N - t))) != CW_OK) return st;
+    if (t / C < ncp - 1) {
+      ck_cur[t / C] = s->cur;
+      if ((st = state_copy(s->adj_ckpt + (size_t)(t / C) * nst, s->cur, true)) != CW_OK) return st;
+      if ((st = cw_step(s, C)) != CW_OK) return st;
+      continue;
+    }
+    for (int64_t u = t; u < N; u++) {
+      if ((st = cw_step(s, 1)) != CW_OK) return st;
+      HIPCHK(launch_adjoint_capture(a, g, s->fields[s->cur][VR], s->fields[s->cur][VT],
+                                    s->fields[s->cur][VZ], s->adj_Z + (size_t)(u - t) * 6 * nreg, s->stream));
+    }
   }
   // loss and the receivers' adjoint weights
   std::vector<double> tr((size_t)nrec * s->trace_cap);
@@ -1386,27 +1412,17 @@ cw_status cw_gradient(cw_sim *s, int64_t n0, int64_t n1, double *loss, double *g
   // adjoint state and accumulators from zero
   HIPCHK(hipMemsetAsync(s->adj_fb[0], 0, nst * sizeof(float), s->stream));
   HIPCHK(hipMemsetAsync(s->adj_glam, 0, 2 * ncell * sizeof(double), s->stream));
-  const StepArgs sa = step_args(s, 0, 1);
-  AdjArgs a{};
-  a.nr = s->nr; a.nt = s->nt; a.nz = s->nz; a.npr = s->npr; a.npz = s->npz; a.nzs = nzs_of(s);
-  a.dt = sa.dt; a.inv_dr = sa.inv_dr; a.inv_dz = sa.inv_dz; a.inv_dth = sa.inv_dth;
-  a.inv_rc = sa.inv_rc; a.inv_rf = sa.inv_rf;
-  a.rho = sa.rho; a.lam = sa.lam; a.mu = sa.mu; a.m_ring = sa.m_ring; a.m_row = sa.m_row;
-  for (int q = 0; q < NF; q++) a.fb[q] = s->adj_fb[q];
-  for (int q = 0; q < NPSI_R; q++) a.pr[q] = s->adj_pr[q];
-  for (int q = 0; q < NPSI_Z; q++) a.pz[q] = s->adj_pz[q];
-  for (int q = 0; q < 9; q++) a.T[q] = s->adj_T[q];
-  for (int q = 0; q < 6; q++) a.C[q] = s->adj_C[q];
-  a.tab_r = sa.tab_r; a.tab_z = sa.tab_z;
-  HIPCHK(launch_adjoint_coefs(a, s->stream));
-  // segments backwards: recompute the segment's strain rates, then its adjoint steps
+  // segments backwards: recompute the segment's strain rates (but for the
+  // last segment's, stored by the forward run), then its adjoint steps
   for (int64_t seg = ncp - 1; seg >= 0; seg--) {
     const int64_t t0 = seg * C, t1 = std::min(t0 + C, N);
-    if ((st = state_copy(s->adj_ckpt + (size_t)seg * nst, ck_cur[seg], false)) != CW_OK) return st;
-    s->cur = ck_cur[seg];
-    s->nstep = t0;
-    HIPCHK(launch_set_step(s->d_step, t0, s->stream));
-    for (int64_t t = t0; t < t1; t++) {
+    if (seg < ncp - 1) {
+      if ((st = state_copy(s->adj_ckpt + (size_t)seg * nst, ck_cur[seg], false)) != CW_OK) return st;
+      s->cur = ck_cur[seg];
+      s->nstep = t0;
+      HIPCHK(launch_set_step(s->d_step, t0, s->stream));
+    }
+    for (int64_t t = t0; t < t1 && seg < ncp - 1; t++) {
       if ((st = cw_step(s, 1)) != CW_OK) return st;
       HIPCHK(launch_adjoint_capture(a, g, s->fields[s->cur][VR], s->fields[s->cur][VT], s->fields[s->cur][VZ],
                                     s->adj_Z + (size_t)(t - t0) * 6 * nreg, s->stream));
