@@ -804,7 +804,7 @@ cw_status cw_step(cw_sim *s, int64_t nsteps)
                         : launch_velocity_basic(a, s->storage, s->stream, tail);
   };
   // With the one-cell float32 velocity update, a step's receivers and step
-  // counter are taken by the first workgroups of the next step's velocity
+  // counter are taken by extra workgroups at the front of the next step's velocity
   // launch (it reads only the buffer they sample and does not read the
   // counter), so that only the last step of a run of steps -- a call, or a
   // captured graph -- has a launch of its own for them.  The 16-bit storages

@@ -168,7 +168,7 @@ size_t fused_lds_bytes(int nr);                 // dynamic LDS of the fused step
 constexpr int kMaxFusedRings = 2048;            // nr limit of the fused step (LDS tables)
 hipError_t launch_fused(const FusedArgs &f, hipStream_t stream);
 // The previous step's receivers and step counter, folded into the next
-// velocity launch (float32 storage): blocks = ceil(max(nrec, 1) / 4)
+// velocity launch (float32 storage): blocks = ceil(max(nrec, 1) / 4) extra
 // workgroups take them; done is a zeroed finish counter, left at zero.
 struct TailArgs {
   const Receiver *rec;

@@ -180,9 +180,9 @@ __device__ void record_one(const Receiver &r, int m, int64_t step, int64_t cap, 
 }
 
 
-// The receivers and the step counter of the previous step, done by the
-// first T.blocks workgroups of the velocity launch that follows it instead
-// of by a launch of their own: workgroup b samples receivers 4b .. 4b+3 (one
+// The receivers and the step counter of the previous step, done by T.blocks
+// extra workgroups of the velocity launch that follows it instead of by a
+// launch of their own: workgroup b samples receivers 4b .. 4b+3 (one
 // wavefront each) from the buffer this step reads (the previous step's
 // result, which no launch of this step writes); the last of these
 // workgroups to finish, once every one of them has read the counter,
@@ -207,13 +207,17 @@ __device__ void previous_step_tail(const TailArgs &T, const StepArgs &a)
   }
 }
 
-// kTail: the first T.blocks workgroups first finish the previous step
-// (previous_step_tail)
+// kTail: T.blocks extra workgroups at the front of the grid finish the
+// previous step (previous_step_tail) and update no cells; the others take
+// the column segments in the same order as without them
 template <class S, bool kTail>
 __global__ void __launch_bounds__(256) k_velocity_basic(StepArgs a, int nbx, TailArgs T)
 {
-  if (kTail && (int)blockIdx.x < T.blocks) previous_step_tail<S>(T, a);
-  const int t = xcd_tile(blockIdx.x, gridDim.x);
+  if (kTail && (int)blockIdx.x < T.blocks) {
+    previous_step_tail<S>(T, a);
+    return;
+  }
+  const int t = kTail ? (int)blockIdx.x - T.blocks : xcd_tile(blockIdx.x, gridDim.x);
   const int bx = t % nbx;
   const int k = bx * 256 + threadIdx.x;
   int i, j;
@@ -617,8 +621,9 @@ hipError_t launch_velocity_basic(const StepArgs &a, int storage, hipStream_t str
   const long g = (long)nbx * a.nt * a.nr;
   if (g > 0x7fffffff) return hipErrorInvalidConfiguration;
   if (tail) {
-    if (storage != ST_F32 || tail->blocks < 1 || tail->blocks > g) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_velocity_basic<StF32, true>), dim3((unsigned)g), dim3(256), 0, stream, a, nbx, *tail);
+    if (storage != ST_F32 || tail->blocks < 1 || g + tail->blocks > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_velocity_basic<StF32, true>), dim3((unsigned)(g + tail->blocks)), dim3(256), 0, stream, a,
+                       nbx, *tail);
     return hipGetLastError();
   }
   return dispatch(storage, [&](auto s) {
