@@ -752,9 +752,17 @@ def main():
                      "traffic": traffic,
                      "traffic_kind": "L2-miss bytes per step (FETCH_SIZE + WRITE_SIZE, copy-calibrated; "
                                      "Infinity Cache hits count in them)",
+                     # the counter-measured rate against the peak (an upper bound on the
+                     # HBM rate: cache hits beyond L2 count in it)
+                     "traffic_GBps": round(traffic / kern_s / 1e9, 1) if traffic else None,
+                     "traffic_frac": round(traffic / kern_s / 1e9 / HBM_PEAK_GBS, 4) if traffic else None,
                      "bytes_per_cell_update": round(bpc, 2), "alg_bytes_per_step": step_alg,
                      "kernel_ms_per_step": round(kern_s * 1e3, 4),
-                     "frac_of_wall_step": round(value * bpc / HBM_PEAK_GBS, 4)},
+                     "frac_of_wall_step": round(value * bpc / HBM_PEAK_GBS, 4),
+                     # for comparison only: the same rate counted with the bytes a 3-D
+                     # medium would add (this workload's medium does not vary along theta)
+                     "frac_at_3d_medium_bytes": round(
+                         algorithmic_bytes("fused", w, n_r, n_z, fb, False) / kern_s / 1e9 / HBM_PEAK_GBS, 4)},
         "kernel_own_bytes_roofline": {"kernel": dom, "achieved": round(dom_achieved, 1), "peak": HBM_PEAK_GBS,
                                       "unit": "GB/s", "frac": round(dom_achieved / HBM_PEAK_GBS, 4),
                                       "own_bytes_per_launch": dom_alg, "avg_launch_ms": round(avg_s * 1e3, 4),
