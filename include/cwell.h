@@ -199,6 +199,19 @@ cw_status cw_steps_done(const cw_sim *s, int64_t *n);
 enum { CW_STORE_F32 = 0, CW_STORE_F16, CW_STORE_BF16 };
 cw_status cw_set_storage(cw_sim *s, int32_t storage);
 
+/* Rounding of the bfloat16 field stores of the step kernels:
+   CW_ROUND_NEAREST (default, nearest even) or CW_ROUND_STOCHASTIC (the
+   MI355X's stochastic-rounding conversion: a value is rounded up with the
+   probability of the fraction of a unit that rounding down would drop, so
+   the rounding error has mean zero and per-step increments smaller than
+   half a unit of the stored value are kept on average).  The random bits
+   are an integer hash of the cell, the field and the step number, so runs
+   are bitwise reproducible, graph replay included.  Source injections
+   still round to nearest.  Other storages ignore the mode.  Callable at any
+   time; CW_ERR_ARG for an unknown mode. */
+enum { CW_ROUND_NEAREST = 0, CW_ROUND_STOCHASTIC };
+cw_status cw_set_rounding(cw_sim *s, int32_t mode);
+
 /* Kernel path of cw_step.  All paths compute the same scheme; results
    agree to float32 rounding.
    CW_PATH_TWO_PASS: a velocity launch and a stress launch per step, small

@@ -101,6 +101,7 @@ struct cw_sim {
   int psi_cur = 0;
   int path = CW_PATH_AUTO;
   int storage = ST_F32;
+  int rounding = CW_ROUND_NEAREST;   // rounding of the 16-bit field stores (cw_set_rounding)
   float *d_scl = nullptr;       // [3][NF]: scale of buffer 0, buffer 1, next write
   float scl_init[3 * NF] = {};  // host copy of the scales zero_state starts from
   unsigned *d_maxabs = nullptr; // [NF][kMaxSlots]
@@ -358,6 +359,8 @@ StepArgs step_args(const cw_sim *s, int in, int out)
   a.scl_in = s->d_scl + in * NF;
   a.scl_out = s->d_scl + 2 * NF;
   a.maxabs = s->d_maxabs;
+  a.step = s->d_step;
+  a.sr = s->rounding == CW_ROUND_STOCHASTIC && s->storage == ST_BF16;
   return a;
 }
 
@@ -1128,6 +1131,15 @@ cw_status cw_set_storage(cw_sim *s, int32_t storage)
   if (!configurable(s, &st)) return st;
   if (storage < CW_STORE_F32 || storage > CW_STORE_BF16) return fail(CW_ERR_ARG, "bad storage %d", storage);
   s->storage = storage;
+  return CW_OK;
+}
+
+cw_status cw_set_rounding(cw_sim *s, int32_t mode)
+{
+  if (!s) return fail(CW_ERR_ARG, "null simulation");
+  if (mode != CW_ROUND_NEAREST && mode != CW_ROUND_STOCHASTIC) return fail(CW_ERR_ARG, "bad rounding mode %d", mode);
+  s->drop_graph();
+  s->rounding = mode;
   return CW_OK;
 }
 

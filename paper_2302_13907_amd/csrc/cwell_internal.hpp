@@ -76,6 +76,10 @@ struct StepArgs {
   const Inject *inj;
   int ninj, inj_i0, inj_i1;   // inj_i0..inj_i1: the rings the sources touch
   const int64_t *step;
+  // bfloat16 storage: the step kernels round their field stores
+  // stochastically (random bits from the cell, the field and *step) instead
+  // of to nearest even
+  int sr;
 };
 
 

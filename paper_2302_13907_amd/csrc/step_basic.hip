@@ -287,9 +287,11 @@ __global__ void __launch_bounds__(256) k_velocity_basic(StepArgs a, int nbx, Tai
   const float vz = S::ldn(a.in[VZ], p, c[VZ]) + a.dt * b_z * (z_dr + z_b + z_dz);
   if (live) {
     const float *o = a.scl_out;
-    S::stn(a.out[VR], p, vr, 1.0f / o[VR]);
-    S::stn(a.out[VT], p, vt, 1.0f / o[VT]);
-    S::stn(a.out[VZ], p, vz, 1.0f / o[VZ]);
+    const bool sr = sr_on<S>(a);
+    const unsigned sb = sr_base<S>(a, p);
+    S::stn(a.out[VR], p, vr, 1.0f / o[VR], sr_key(sb, VR), sr);
+    S::stn(a.out[VT], p, vt, 1.0f / o[VT], sr_key(sb, VT), sr);
+    S::stn(a.out[VZ], p, vz, 1.0f / o[VZ], sr_key(sb, VZ), sr);
   }
   if (S::scaled) {
     track_max(a.maxabs + VR * kMaxSlots, live ? vr : 0.0f);
@@ -387,12 +389,14 @@ __device__ __forceinline__ void stress_cell(const StepArgs &a, int i, int j, int
     }
   }
   if (live) {
-    S::stn(a.out[SRR], p, s_rr, 1.0f / o[SRR]);
-    S::stn(a.out[STT], p, s_tt, 1.0f / o[STT]);
-    S::stn(a.out[SZZ], p, s_zz, 1.0f / o[SZZ]);
-    S::stn(a.out[SRT], p, s_rt, 1.0f / o[SRT]);
-    S::stn(a.out[SRZ], p, s_rz, 1.0f / o[SRZ]);
-    S::stn(a.out[STZ], p, s_tz, 1.0f / o[STZ]);
+    const bool sr = sr_on<S>(a);
+    const unsigned sb = sr_base<S>(a, p);
+    S::stn(a.out[SRR], p, s_rr, 1.0f / o[SRR], sr_key(sb, SRR), sr);
+    S::stn(a.out[STT], p, s_tt, 1.0f / o[STT], sr_key(sb, STT), sr);
+    S::stn(a.out[SZZ], p, s_zz, 1.0f / o[SZZ], sr_key(sb, SZZ), sr);
+    S::stn(a.out[SRT], p, s_rt, 1.0f / o[SRT], sr_key(sb, SRT), sr);
+    S::stn(a.out[SRZ], p, s_rz, 1.0f / o[SRZ], sr_key(sb, SRZ), sr);
+    S::stn(a.out[STZ], p, s_tz, 1.0f / o[STZ], sr_key(sb, STZ), sr);
   }
   if (S::scaled && live) {
     mx[0] = fmaxf(mx[0], fabsf(s_rr)); mx[1] = fmaxf(mx[1], fabsf(s_tt)); mx[2] = fmaxf(mx[2], fabsf(s_zz));

@@ -33,16 +33,26 @@ constexpr int kRows = CW_VEC_ROWS;
 //             2.369 / 2.759 at 8 / 8;
 //   float16:  5 / 7 -> 2.097 / 2.375, against 2.129 / 2.617 at 6 / none;
 //             8 spills.
+// The stochastically rounding bfloat16 kernels need a few more registers
+// (the random bits): their stress update asks for 6 waves per SIMD (at 7 it
+// spills 36 bytes per lane).
+#ifndef CW_SR_STRESS_WAVES
+#define CW_SR_STRESS_WAVES 6
+#endif
 #ifndef CW_VEC_WAVES
-template <class S> struct Occupancy { static constexpr int vel = 1, str = 8; };
-template <> struct Occupancy<StF16> { static constexpr int vel = 5, str = 7; };
-template <> struct Occupancy<StBF16> { static constexpr int vel = 7, str = 7; };
+template <class S> struct Occupancy { static constexpr int vel = 1, str = 8, vel_sr = 1, str_sr = 8; };
+template <> struct Occupancy<StF16> { static constexpr int vel = 5, str = 7, vel_sr = 5, str_sr = 7; };
+template <> struct Occupancy<StBF16> { static constexpr int vel = 7, str = 7, vel_sr = 7, str_sr = CW_SR_STRESS_WAVES; };
 #else
-template <class S> struct Occupancy { static constexpr int vel = CW_VEC_WAVES, str = CW_VEC_WAVES; };
+template <class S> struct Occupancy {
+  static constexpr int vel = CW_VEC_WAVES, str = CW_VEC_WAVES, vel_sr = CW_VEC_WAVES, str_sr = CW_VEC_WAVES;
+};
 #endif
 
-// velocity update of the lane's VW cells of column (i, j); mr, mt, mz collect |v| maxima
-template <class S>
+// velocity update of the lane's VW cells of column (i, j); mr, mt, mz collect |v| maxima.
+// kSR: the field stores round stochastically (a separate instantiation: the
+// extra registers of the random bits would make the default form spill)
+template <class S, bool kSR = false>
 __device__ __forceinline__ void velocity_column(const StepArgs &a, int i, int j, int kb, bool live, float &mr,
                                                 float &mt, float &mz)
 {
@@ -139,17 +149,19 @@ __device__ __forceinline__ void velocity_column(const StepArgs &a, int i, int j,
   }
   if (live) {
     const float *o = a.scl_out;
-    S::stb(L.fieldw(a.out[VR], i), L.v0, L.sj, vr, S::scaled ? inv_pow2(o[VR]) : 1.0f);
-    S::stb(L.fieldw(a.out[VT], i), L.v0, L.sj, vt, S::scaled ? inv_pow2(o[VT]) : 1.0f);
-    S::stb(L.fieldw(a.out[VZ], i), L.v0, L.sj, vz, S::scaled ? inv_pow2(o[VZ]) : 1.0f);
+    constexpr bool sr = kSR && S::stochastic;
+    const unsigned sb = sr ? sr_base<S>(a, at(a, i, j, kb)) : 0u;
+    S::stb(L.fieldw(a.out[VR], i), L.v0, L.sj, vr, S::scaled ? inv_pow2(o[VR]) : 1.0f, sr_key(sb, VR), sr);
+    S::stb(L.fieldw(a.out[VT], i), L.v0, L.sj, vt, S::scaled ? inv_pow2(o[VT]) : 1.0f, sr_key(sb, VT), sr);
+    S::stb(L.fieldw(a.out[VZ], i), L.v0, L.sj, vz, S::scaled ? inv_pow2(o[VZ]) : 1.0f, sr_key(sb, VZ), sr);
   }
 }
 
 // One workgroup per (ring, CW_VEC_ROWS theta rows, depth segment of 1024
 // cells): the rows are done one after the other, so each wavefront lives
 // several column segments long and its set-up is paid once.
-template <class S>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Occupancy<S>::vel)))
+template <class S, bool kSR>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kSR ? Occupancy<S>::vel_sr : Occupancy<S>::vel)))
 k_velocity_vec(StepArgs a, int nbx)
 {
   const int bx = blockIdx.x % nbx;
@@ -160,7 +172,7 @@ k_velocity_vec(StepArgs a, int nbx)
   const bool live = k0 < a.nz;
   const int kb = live ? k0 : a.nz - VW;            // dead lanes compute on a valid group, store nothing
   float mr = 0.0f, mt = 0.0f, mz = 0.0f;
-  for (int j = j0; j < j1; j++) velocity_column<S>(a, i, j, kb, live, mr, mt, mz);
+  for (int j = j0; j < j1; j++) velocity_column<S, kSR>(a, i, j, kb, live, mr, mt, mz);
   if (S::scaled) {
     track_max(a.maxabs + VR * kMaxSlots, live ? mr : 0.0f);
     track_max(a.maxabs + VT * kMaxSlots, live ? mt : 0.0f);
@@ -169,7 +181,7 @@ k_velocity_vec(StepArgs a, int nbx)
 }
 
 // stress update of the lane's VW cells of column (i, j); mx collects |sigma| maxima
-template <class S>
+template <class S, bool kSR = false>
 __device__ __forceinline__ void stress_column(const StepArgs &a, int i, int j, int kb, bool live, float (&mx)[6])
 {
   const int jm = j == 0 ? a.nt - 1 : j - 1;
@@ -281,17 +293,19 @@ __device__ __forceinline__ void stress_column(const StepArgs &a, int i, int j, i
     mx[4] = fmaxf(mx[4], fabsf(srz[e])); mx[5] = fmaxf(mx[5], fabsf(stz[e]));
   }
   if (live) {
-    S::stb(L.fieldw(a.out[SRR], i), L.v0, L.sj, srr, S::scaled ? inv_pow2(o[SRR]) : 1.0f);
-    S::stb(L.fieldw(a.out[STT], i), L.v0, L.sj, stt, S::scaled ? inv_pow2(o[STT]) : 1.0f);
-    S::stb(L.fieldw(a.out[SZZ], i), L.v0, L.sj, szz, S::scaled ? inv_pow2(o[SZZ]) : 1.0f);
-    S::stb(L.fieldw(a.out[SRT], i), L.v0, L.sj, srt, S::scaled ? inv_pow2(o[SRT]) : 1.0f);
-    S::stb(L.fieldw(a.out[SRZ], i), L.v0, L.sj, srz, S::scaled ? inv_pow2(o[SRZ]) : 1.0f);
-    S::stb(L.fieldw(a.out[STZ], i), L.v0, L.sj, stz, S::scaled ? inv_pow2(o[STZ]) : 1.0f);
+    constexpr bool sr = kSR && S::stochastic;
+    const unsigned sb = sr ? sr_base<S>(a, at(a, i, j, kb)) : 0u;
+    S::stb(L.fieldw(a.out[SRR], i), L.v0, L.sj, srr, S::scaled ? inv_pow2(o[SRR]) : 1.0f, sr_key(sb, SRR), sr);
+    S::stb(L.fieldw(a.out[STT], i), L.v0, L.sj, stt, S::scaled ? inv_pow2(o[STT]) : 1.0f, sr_key(sb, STT), sr);
+    S::stb(L.fieldw(a.out[SZZ], i), L.v0, L.sj, szz, S::scaled ? inv_pow2(o[SZZ]) : 1.0f, sr_key(sb, SZZ), sr);
+    S::stb(L.fieldw(a.out[SRT], i), L.v0, L.sj, srt, S::scaled ? inv_pow2(o[SRT]) : 1.0f, sr_key(sb, SRT), sr);
+    S::stb(L.fieldw(a.out[SRZ], i), L.v0, L.sj, srz, S::scaled ? inv_pow2(o[SRZ]) : 1.0f, sr_key(sb, SRZ), sr);
+    S::stb(L.fieldw(a.out[STZ], i), L.v0, L.sj, stz, S::scaled ? inv_pow2(o[STZ]) : 1.0f, sr_key(sb, STZ), sr);
   }
 }
 
-template <class S>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Occupancy<S>::str)))
+template <class S, bool kSR>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kSR ? Occupancy<S>::str_sr : Occupancy<S>::str)))
 k_stress_vec(StepArgs a, int nbx)
 {
   const int bx = blockIdx.x % nbx;
@@ -302,7 +316,7 @@ k_stress_vec(StepArgs a, int nbx)
   const bool live = k0 < a.nz;
   const int kb = live ? k0 : a.nz - VW;
   float mx[6] = {0, 0, 0, 0, 0, 0};
-  for (int j = j0; j < j1; j++) stress_column<S>(a, i, j, kb, live, mx);
+  for (int j = j0; j < j1; j++) stress_column<S, kSR>(a, i, j, kb, live, mx);
   if (S::scaled) {
 #pragma unroll
     for (int q = 0; q < 6; q++) track_max(a.maxabs + (SRR + q) * kMaxSlots, live ? mx[q] : 0.0f);
@@ -390,8 +404,12 @@ hipError_t launch_velocity_vec(const StepArgs &a, int storage, hipStream_t strea
   const int nbx = (a.nz / VW + 255) / 256;
   const long g = (long)nbx * ((a.nt + kRows - 1) / kRows) * a.nr;
   if (g > 0x7fffffff || !vec_applies(a.nt, a.nz)) return hipErrorInvalidConfiguration;
+  if (a.sr && storage == ST_BF16) {
+    hipLaunchKernelGGL((k_velocity_vec<StBF16, true>), dim3((unsigned)g), dim3(256), 0, stream, a, nbx);
+    return hipGetLastError();
+  }
   return dispatch(storage, [&](auto s) {
-    hipLaunchKernelGGL(k_velocity_vec<decltype(s)>, dim3((unsigned)g), dim3(256), 0, stream, a, nbx);
+    hipLaunchKernelGGL((k_velocity_vec<decltype(s), false>), dim3((unsigned)g), dim3(256), 0, stream, a, nbx);
     return hipGetLastError();
   });
 }
@@ -401,8 +419,12 @@ hipError_t launch_stress_vec(const StepArgs &a, int storage, hipStream_t stream)
   const int nbx = (a.nz / VW + 255) / 256;
   const long g = (long)nbx * ((a.nt + kRows - 1) / kRows) * a.nr;
   if (g > 0x7fffffff || !vec_applies(a.nt, a.nz)) return hipErrorInvalidConfiguration;
+  if (a.sr && storage == ST_BF16) {
+    hipLaunchKernelGGL((k_stress_vec<StBF16, true>), dim3((unsigned)g), dim3(256), 0, stream, a, nbx);
+    return hipGetLastError();
+  }
   return dispatch(storage, [&](auto s) {
-    hipLaunchKernelGGL(k_stress_vec<decltype(s)>, dim3((unsigned)g), dim3(256), 0, stream, a, nbx);
+    hipLaunchKernelGGL((k_stress_vec<decltype(s), false>), dim3((unsigned)g), dim3(256), 0, stream, a, nbx);
     return hipGetLastError();
   });
 }

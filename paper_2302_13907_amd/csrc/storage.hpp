@@ -7,6 +7,8 @@
 #include <hip/hip_runtime.h>
 #include <cstddef>
 
+#include "cwell_internal.hpp"
+
 namespace cw {
 
 // Buffer accesses: a wavefront-uniform resource (base address and size in
@@ -65,6 +67,19 @@ __device__ __forceinline__ float ldb1(rsrc_t r, unsigned voff, unsigned soff)
   return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
 }
 
+// A 32-bit integer hash (two multiply and three xor-shift rounds; the
+// "lowbias32" constants of C. Wellons' hash-prospector): the counter-based
+// random bits of stochastic rounding, from a cell, a field and a step.
+__device__ __forceinline__ unsigned hash32(unsigned x)
+{
+  x ^= x >> 16;
+  x *= 0x7feb352du;
+  x ^= x >> 15;
+  x *= 0x846ca68bu;
+  x ^= x >> 16;
+  return x;
+}
+
 struct StF32 {
   static constexpr bool scaled = false;
   static constexpr unsigned bytes = 4;   // bytes per stored value
@@ -81,7 +96,9 @@ struct StF32 {
     ldb4<kOwnLoadAux>(o, r, voff, soff);
   }
   __device__ static float ldb1(rsrc_t r, unsigned voff, unsigned soff, float) { return cw::ldb1(r, voff, soff); }
-  __device__ static void stb(rsrc_t r, unsigned voff, unsigned soff, const float (&v)[4], float)
+  static constexpr bool stochastic = false;   // float32 stores are exact: no rounding mode
+  __device__ static void stb(rsrc_t r, unsigned voff, unsigned soff, const float (&v)[4], float, unsigned = 0u,
+                             bool = false)
   {
     stb4<kFieldStoreAux>(r, voff, soff, v);
   }
@@ -91,7 +108,7 @@ struct StF32 {
   {
     return CW_NT_OWN ? __builtin_nontemporal_load(f + p) : f[p];
   }
-  __device__ static void stn(float *f, size_t p, float v, float)
+  __device__ static void stn(float *f, size_t p, float v, float, unsigned = 0u, bool = false)
   {
     if (CW_NT_STORE) __builtin_nontemporal_store(v, f + p);
     else f[p] = v;
@@ -142,7 +159,9 @@ struct StF16 {
   {
     return (float)__builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0)) * s;
   }
-  __device__ static void stb(rsrc_t r, unsigned voff, unsigned soff, const float (&v)[4], float is)
+  static constexpr bool stochastic = false;   // float16 stores round to nearest even
+  __device__ static void stb(rsrc_t r, unsigned voff, unsigned soff, const float (&v)[4], float is, unsigned = 0u,
+                             bool = false)
   {
     h4 h;
     h[0] = (_Float16)(v[0] * is); h[1] = (_Float16)(v[1] * is);
@@ -158,7 +177,7 @@ struct StF16 {
     const _Float16 *h = reinterpret_cast<const _Float16 *>(f) + p;
     return (float)(CW_NT_OWN ? __builtin_nontemporal_load(h) : *h) * s;
   }
-  __device__ static void stn(float *f, size_t p, float v, float is)
+  __device__ static void stn(float *f, size_t p, float v, float is, unsigned = 0u, bool = false)
   {
     _Float16 *h = reinterpret_cast<_Float16 *>(f) + p;
     const _Float16 x = (_Float16)(v * is);
@@ -225,11 +244,37 @@ struct StBF16 {
   {
     return unpack(__builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0));
   }
-  __device__ static void stb(rsrc_t r, unsigned voff, unsigned soff, const float (&v)[4], float)
+  // Stochastic rounding (gfx950 v_cvt_sr_bf16_f32): the value is rounded up
+  // with probability equal to the fraction of a unit in the last place that
+  // rounding down would drop, so the rounding error has mean zero and the
+  // small per-step increments of a slowly varying field are kept on
+  // average instead of being lost below half a unit.  The instruction takes
+  // its 16 random bits from bits 31..16 of its random operand, so one
+  // 32-bit random word serves two values (the word, and the word shifted
+  // left by 16).
+  static constexpr bool stochastic = true;
+  __device__ static unsigned pack2_sr(float a, unsigned ra, float b, unsigned rb)
+  {
+    bf2 h = {};
+    h = __builtin_amdgcn_cvt_sr_bf16_f32(h, a, ra, false);
+    h = __builtin_amdgcn_cvt_sr_bf16_f32(h, b, rb, true);
+    return __builtin_bit_cast(unsigned, h);
+  }
+  // sr: stochastic rounding with the random bits hash32(key) (a second word
+  // for the last two values is derived by an odd multiplier); else nearest
+  // even
+  __device__ static void stb(rsrc_t r, unsigned voff, unsigned soff, const float (&v)[4], float, unsigned key = 0u,
+                             bool sr = false)
   {
     u32x2 u;
-    u.x = pack2(v[0], v[1]);
-    u.y = pack2(v[2], v[3]);
+    if (sr) {
+      const unsigned rnd = hash32(key), rnd2 = rnd * 0x9e3779b1u;
+      u.x = pack2_sr(v[0], rnd, v[1], rnd << 16);
+      u.y = pack2_sr(v[2], rnd2, v[3], rnd2 << 16);
+    } else {
+      u.x = pack2(v[0], v[1]);
+      u.y = pack2(v[2], v[3]);
+    }
     __builtin_amdgcn_raw_buffer_store_b64(u, r, voff, soff, kFieldStoreAux);
   }
   __device__ static void st(float *f, size_t p, float v, float)
@@ -241,10 +286,10 @@ struct StBF16 {
     const unsigned short *h = reinterpret_cast<const unsigned short *>(f) + p;
     return unpack(CW_NT_OWN ? __builtin_nontemporal_load(h) : *h);
   }
-  __device__ static void stn(float *f, size_t p, float v, float)
+  __device__ static void stn(float *f, size_t p, float v, float, unsigned key = 0u, bool sr = false)
   {
     unsigned short *h = reinterpret_cast<unsigned short *>(f) + p;
-    const unsigned short x = pack(v);
+    const unsigned short x = sr ? (unsigned short)pack2_sr(v, hash32(key), 0.0f, 0u) : pack(v);
     if (CW_NT_STORE) __builtin_nontemporal_store(x, h);
     else *h = x;
   }
@@ -266,5 +311,20 @@ struct StBF16 {
     *reinterpret_cast<uint2 *>(reinterpret_cast<unsigned short *>(f) + p) = u;
   }
 };
+
+// Stochastic rounding of a step's stores (storages that have it, when
+// asked for).  The random bits of field q's value(s) at linear cell index c
+// (the first cell of a group) are hash32 of the key c ^ (q << 28) ^ h(step),
+// formed by the store only when it rounds stochastically: cells below 2^28
+// and fields below 16 never share a key within a step.
+template <class S>
+__device__ __forceinline__ bool sr_on(const StepArgs &a) { return S::stochastic && a.sr != 0; }
+// c ^ h(step) for the lane's cell (0 when the stores round to nearest)
+template <class S>
+__device__ __forceinline__ unsigned sr_base(const StepArgs &a, size_t c)
+{
+  return sr_on<S>(a) ? (unsigned)c ^ hash32((unsigned)*a.step * 0x9e3779b9u + 0x632be5abu) : 0u;
+}
+__device__ __forceinline__ unsigned sr_key(unsigned base, int q) { return base ^ ((unsigned)q << 28); }
 
 }  // namespace cw

@@ -31,7 +31,7 @@ EXPORTS = ("cw_create", "cw_set_material", "cw_set_material_rz", "cw_set_pml", "
            "cw_workspace_bytes", "cw_bind", "cw_step", "cw_sync", "cw_get_traces",
            "cw_get_field", "cw_set_field", "cw_energy", "cw_reset", "cw_steps_done",
            "cw_ricker", "cw_destroy", "cw_last_error", "cw_profile", "cw_profile_read",
-           "cw_set_path", "cw_set_storage", "cw_stream_probe", "cw_set_graph", "cw_set_adjoint",
+           "cw_set_path", "cw_set_storage", "cw_set_rounding", "cw_stream_probe", "cw_set_graph", "cw_set_adjoint",
            "cw_set_region_moduli", "cw_gradient", "cw_batch_create", "cw_batch_set_tile",
            "cw_batch_workspace_bytes", "cw_batch_bind", "cw_batch_set_occupancy", "cw_batch_set_graph", "cw_batch_step", "cw_batch_destroy",
            "cw_refined_create", "cw_refined_cells", "cw_refined_set_material_rz", "cw_refined_set_pml",
@@ -43,6 +43,7 @@ EXPORTS = ("cw_create", "cw_set_material", "cw_set_material_rz", "cw_set_pml", "
 STORAGE = {"f32": 0, "f16": 1, "bf16": 2}
 
 PATHS = {"auto": 0, "two-pass": 1, "fused": 2}
+ROUNDING = {"nearest": 0, "stochastic": 1}
 
 KERNELS = {"velocity": 0, "stress": 1, "fused": 2, "inject": 3, "record": 4}
 
@@ -97,6 +98,7 @@ def load():
         "cw_ricker": [D, DP, I64, DP],
         "cw_profile": [P, I32],
         "cw_set_path": [P, I32],
+        "cw_set_rounding": [P, I32],
         "cw_set_storage": [P, I32],
         "cw_profile_read": [P, I32, DP, ctypes.POINTER(I64)],
         "cw_stream_probe": [P, ctypes.c_uint64, I32, I32, I32, I32, P, DP],
@@ -318,6 +320,10 @@ class Sim:
     def set_storage(self, storage: str):
         """Field storage: "f32", "f16" (per-field power-of-two scales) or "bf16"."""
         _check(self.lib.cw_set_storage(self.h, STORAGE[storage]))
+
+    def set_rounding(self, mode: str):
+        """Rounding of the bfloat16 field stores: "nearest" (default) or "stochastic"."""
+        _check(self.lib.cw_set_rounding(self.h, ROUNDING[mode]))
 
     def set_path(self, path: str):
         """Kernel path of step(): "auto", "two-pass" or "fused"."""
