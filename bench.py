@@ -345,7 +345,8 @@ def oracle_timing():
     return out
 
 
-def run_steps(w, storage: str, path: str, warmup: int, steps: int, graph: int = 0, profile: bool = True):
+def run_steps(w, storage: str, path: str, warmup: int, steps: int, graph: int = 0, profile: bool = True,
+              rounding: str = "nearest"):
     """Set up workload w, bind it, run warmup + timed steps; returns
     (seconds for the timed steps, {kernel: (ms, launches)}, traces).  With
     graph > 0 the steps are replayed from a captured graph of that many
@@ -368,6 +369,7 @@ def run_steps(w, storage: str, path: str, warmup: int, steps: int, graph: int = 
     s.set_trace_capacity(total)
     s.set_path(path)
     s.set_storage(storage)
+    s.set_rounding(rounding)
     s.set_graph(graph)
     log("binding %.2f GB workspace (%s storage)" % (s.workspace_bytes() / 1e9, storage))
     s.bind("cuda:0")
@@ -610,7 +612,8 @@ def refined_form(uniform_ms: float, warmup: int = 10, steps: int = 100):
 
 def storage_forms(path: str, warmup: int = 10, steps: int = 100):
     """Gcell-updates/s of the mixed-precision workload with float32, float16
-    and bfloat16 field storage (float32 arithmetic in every case)."""
+    and bfloat16 field storage (float32 arithmetic in every case), and with
+    bfloat16 stores rounded stochastically."""
     from paper_2302_13907_amd import inputs
     w = inputs.mixed_precision_case()
     log("storage forms on %s" % w.name)
@@ -619,7 +622,10 @@ def storage_forms(path: str, warmup: int = 10, steps: int = 100):
         el, times, _ = run_steps(w, st, path, warmup, steps)
         res[st] = {"value": round(w.cells * steps / el / 1e9, 3),
                    "ms_per_step": round(el / steps * 1e3, 4)}
-    for st in ("f16", "bf16"):
+    # bfloat16 with stochastically rounded stores
+    el, _, _ = run_steps(w, "bf16", path, warmup, steps, rounding="stochastic")
+    res["bf16_stochastic"] = {"value": round(w.cells * steps / el / 1e9, 3), "ms_per_step": round(el / steps * 1e3, 4)}
+    for st in ("f16", "bf16", "bf16_stochastic"):
         res[st]["speedup_vs_f32"] = round(res[st]["value"] / res["f32"]["value"], 3)
     return res
 
