@@ -128,6 +128,22 @@ def test_stream_probe_validation():
     assert b"7 reads" in lib.cw_last_error()
 
 
+def test_rounding_mode_validation():
+    """cw_set_rounding takes the two declared modes, before and after the
+    storage is chosen, and rejects anything else without touching the device."""
+    lib = cwell.load()
+    s = cwell.Sim(6, 4, 10, 5e-3, 5e-3)
+    assert lib.cw_set_rounding(None, 0) == -1
+    for bad in (-1, 2, 7):
+        assert lib.cw_set_rounding(s.h, bad) == -1
+        assert b"rounding mode" in lib.cw_last_error()
+    s.set_rounding("stochastic")
+    s.set_storage("bf16")
+    s.set_rounding("nearest")
+    with pytest.raises(KeyError):
+        s.set_rounding("up")
+
+
 def test_graph_steps_validation():
     s = cwell.Sim(6, 4, 10, 5e-3, 5e-3)
     for bad in (-2, 3, 4098):
