@@ -132,11 +132,19 @@ __device__ __forceinline__ int zrow(const StepArgs &a, int k)
   return -1;
 }
 
-// psi <- b psi + a X; returns X + psi
-__device__ __forceinline__ float cpml(float *psi, size_t p, float ca, float cb, float X)
+// Layer memory of one cell (read and written only by that cell:
+// non-temporal).  A layer block reads every coefficient and memory value it
+// needs (ldpsi) before it writes any (cpml): a store could alias a later
+// read, so one array after the other would cost the cell a memory round
+// trip per array, six in a radial layer.
+__device__ __forceinline__ float ldpsi(const float *psi, size_t p)
 {
-  // the layer memory is read and written only by its own cell: non-temporal
-  const float v = cb * (CW_NT_OWN ? __builtin_nontemporal_load(psi + p) : psi[p]) + ca * X;
+  return CW_NT_OWN ? __builtin_nontemporal_load(psi + p) : psi[p];
+}
+// psi <- b psi + a X from the value old read at p; returns X + psi
+__device__ __forceinline__ float cpml(float *psi, size_t p, float old, float ca, float cb, float X)
+{
+  const float v = cb * old + ca * X;
   if (CW_NT_STORE) __builtin_nontemporal_store(v, psi + p);
   else psi[p] = v;
   return X + v;
@@ -272,20 +280,28 @@ __global__ void __launch_bounds__(256) k_velocity_basic(StepArgs a, int nbx, Tai
   if (ir >= 0 && live) {
     const size_t q = ((size_t)ir * a.nt + j) * a.nz + k;
     const float *T = a.tab_r;
-    r_dr = cpml(a.psi_r[R_VR_DR], q, T[AR_F * a.nr + i], T[BR_F * a.nr + i], r_dr);
-    r_b = cpml(a.psi_r[R_VR_B], q, T[AT_F * a.nr + i], T[BT_F * a.nr + i], r_b);
-    t_dr = cpml(a.psi_r[R_VT_DR], q, T[AR_C * a.nr + i], T[BR_C * a.nr + i], t_dr);
-    t_b = cpml(a.psi_r[R_VT_B], q, T[AT_C * a.nr + i], T[BT_C * a.nr + i], t_b);
-    z_dr = cpml(a.psi_r[R_VZ_DR], q, T[AR_C * a.nr + i], T[BR_C * a.nr + i], z_dr);
-    z_b = cpml(a.psi_r[R_VZ_B], q, T[AT_C * a.nr + i], T[BT_C * a.nr + i], z_b);
+    float *const *P = a.psi_r;
+    const float arf = T[AR_F * a.nr + i], brf = T[BR_F * a.nr + i], atf = T[AT_F * a.nr + i], btf = T[BT_F * a.nr + i];
+    const float arc = T[AR_C * a.nr + i], brc = T[BR_C * a.nr + i], atc = T[AT_C * a.nr + i], btc = T[BT_C * a.nr + i];
+    const float m0 = ldpsi(P[R_VR_DR], q), m1 = ldpsi(P[R_VR_B], q), m2 = ldpsi(P[R_VT_DR], q);
+    const float m3 = ldpsi(P[R_VT_B], q), m4 = ldpsi(P[R_VZ_DR], q), m5 = ldpsi(P[R_VZ_B], q);
+    r_dr = cpml(P[R_VR_DR], q, m0, arf, brf, r_dr);
+    r_b = cpml(P[R_VR_B], q, m1, atf, btf, r_b);
+    t_dr = cpml(P[R_VT_DR], q, m2, arc, brc, t_dr);
+    t_b = cpml(P[R_VT_B], q, m3, atc, btc, t_b);
+    z_dr = cpml(P[R_VZ_DR], q, m4, arc, brc, z_dr);
+    z_b = cpml(P[R_VZ_B], q, m5, atc, btc, z_b);
   }
   const int kz = live ? zrow(a, k) : -1;
   if (kz >= 0) {
     const size_t q = ((size_t)i * a.nt + j) * a.nzs + kz;
     const float *T = a.tab_z;
-    r_dz = cpml(a.psi_z[Z_VR_DZ], q, T[AZ_C * a.nz + k], T[BZ_C * a.nz + k], r_dz);
-    t_dz = cpml(a.psi_z[Z_VT_DZ], q, T[AZ_C * a.nz + k], T[BZ_C * a.nz + k], t_dz);
-    z_dz = cpml(a.psi_z[Z_VZ_DZ], q, T[AZ_H * a.nz + k], T[BZ_H * a.nz + k], z_dz);
+    float *const *P = a.psi_z;
+    const float azc = T[AZ_C * a.nz + k], bzc = T[BZ_C * a.nz + k], azh = T[AZ_H * a.nz + k], bzh = T[BZ_H * a.nz + k];
+    const float m0 = ldpsi(P[Z_VR_DZ], q), m1 = ldpsi(P[Z_VT_DZ], q), m2 = ldpsi(P[Z_VZ_DZ], q);
+    r_dz = cpml(P[Z_VR_DZ], q, m0, azc, bzc, r_dz);
+    t_dz = cpml(P[Z_VT_DZ], q, m1, azc, bzc, t_dz);
+    z_dz = cpml(P[Z_VZ_DZ], q, m2, azh, bzh, z_dz);
   }
 
   const float vr = vr_old + a.dt * b_r * (r_dr + r_b + r_dz);
@@ -335,32 +351,46 @@ __device__ __forceinline__ void stress_cell(const StepArgs &a, int i, int j, int
   float tz_b = irc * (vz_jp - vz0) * a.inv_dth;
   float tz_dz = (vt_kp - vt0) * a.inv_dz;
 
+  // the old stresses are read before the layer block, whose stores could
+  // alias them (read after it, they would take a second memory round trip);
+  // the moduli after it.  Measured at 256 x 128 x 8192, ms per launch: 3.160
+  // this way, 3.176 with both after the block, 3.208 with both before it
+  // (more registers held across it), 3.182 with only the moduli before it.
+  const int k1 = kk + 1 < a.nz ? kk + 1 : a.nz - 1;
+  const size_t p = col.c + kk;
+  const size_t pm = col.m + kk;
+  const float *c = a.scl_in;
+  const float so_rr = S::ldn(a.in[SRR], p, c[SRR]), so_tt = S::ldn(a.in[STT], p, c[STT]);
+  const float so_zz = S::ldn(a.in[SZZ], p, c[SZZ]), so_rt = S::ldn(a.in[SRT], p, c[SRT]);
+  const float so_rz = S::ldn(a.in[SRZ], p, c[SRZ]), so_tz = S::ldn(a.in[STZ], p, c[STZ]);
   const int ir = i - (a.nr - a.npr);
   if (ir >= 0 && live) {
     const size_t q = ((size_t)ir * a.nt + j) * a.nz + k;
     const float *T = a.tab_r;
-    err = cpml(a.psi_r[R_N_DR], q, T[AR_C * a.nr + i], T[BR_C * a.nr + i], err);
-    ett = cpml(a.psi_r[R_N_B], q, T[AT_C * a.nr + i], T[BT_C * a.nr + i], ett);
-    rt_dr = cpml(a.psi_r[R_RT_DR], q, T[AR_F * a.nr + i], T[BR_F * a.nr + i], rt_dr);
-    rt_b = cpml(a.psi_r[R_RT_B], q, T[AT_F * a.nr + i], T[BT_F * a.nr + i], rt_b);
-    rz_dr = cpml(a.psi_r[R_RZ_DR], q, T[AR_F * a.nr + i], T[BR_F * a.nr + i], rz_dr);
-    tz_b = cpml(a.psi_r[R_TZ_B], q, T[AT_C * a.nr + i], T[BT_C * a.nr + i], tz_b);
+    float *const *P = a.psi_r;
+    const float arf = T[AR_F * a.nr + i], brf = T[BR_F * a.nr + i], atf = T[AT_F * a.nr + i], btf = T[BT_F * a.nr + i];
+    const float arc = T[AR_C * a.nr + i], brc = T[BR_C * a.nr + i], atc = T[AT_C * a.nr + i], btc = T[BT_C * a.nr + i];
+    const float m0 = ldpsi(P[R_N_DR], q), m1 = ldpsi(P[R_N_B], q), m2 = ldpsi(P[R_RT_DR], q);
+    const float m3 = ldpsi(P[R_RT_B], q), m4 = ldpsi(P[R_RZ_DR], q), m5 = ldpsi(P[R_TZ_B], q);
+    err = cpml(P[R_N_DR], q, m0, arc, brc, err);
+    ett = cpml(P[R_N_B], q, m1, atc, btc, ett);
+    rt_dr = cpml(P[R_RT_DR], q, m2, arf, brf, rt_dr);
+    rt_b = cpml(P[R_RT_B], q, m3, atf, btf, rt_b);
+    rz_dr = cpml(P[R_RZ_DR], q, m4, arf, brf, rz_dr);
+    tz_b = cpml(P[R_TZ_B], q, m5, atc, btc, tz_b);
   }
   const int kz = live ? zrow(a, k) : -1;
   if (kz >= 0) {
     const size_t q = ((size_t)i * a.nt + j) * a.nzs + kz;
     const float *T = a.tab_z;
-    ezz = cpml(a.psi_z[Z_N_DZ], q, T[AZ_C * a.nz + k], T[BZ_C * a.nz + k], ezz);
-    rz_dz = cpml(a.psi_z[Z_RZ_DZ], q, T[AZ_H * a.nz + k], T[BZ_H * a.nz + k], rz_dz);
-    tz_dz = cpml(a.psi_z[Z_TZ_DZ], q, T[AZ_H * a.nz + k], T[BZ_H * a.nz + k], tz_dz);
+    float *const *P = a.psi_z;
+    const float azc = T[AZ_C * a.nz + k], bzc = T[BZ_C * a.nz + k], azh = T[AZ_H * a.nz + k], bzh = T[BZ_H * a.nz + k];
+    const float m0 = ldpsi(P[Z_N_DZ], q), m1 = ldpsi(P[Z_RZ_DZ], q), m2 = ldpsi(P[Z_TZ_DZ], q);
+    ezz = cpml(P[Z_N_DZ], q, m0, azc, bzc, ezz);
+    rz_dz = cpml(P[Z_RZ_DZ], q, m1, azh, bzh, rz_dz);
+    tz_dz = cpml(P[Z_TZ_DZ], q, m2, azh, bzh, tz_dz);
   }
 
-  // moduli and old stresses after the layer block: read before it (as in
-  // the velocity update) they hold 27 more registers across it, and the
-  // launch at 256 x 128 x 8192 took 3.231 against 3.194 ms
-  const int k1 = kk + 1 < a.nz ? kk + 1 : a.nz - 1;
-  const size_t p = col.c + kk;
-  const size_t pm = col.m + kk;
   const float lam = a.lam[pm], mu = a.mu[pm];
   const float mu_i1 = a.mu[col.m_i1 + kk], mu_jp = a.mu[col.m_jp + kk];
   const float mu_k1 = a.mu[col.m + k1];
@@ -368,15 +398,14 @@ __device__ __forceinline__ void stress_cell(const StepArgs &a, int i, int j, int
   const float mu_rz = hm4(mu, mu_i1, mu_k1, a.mu[col.m_i1 + k1]);
   const float mu_tz = hm4(mu, mu_jp, mu_k1, a.mu[col.m_jp + k1]);
 
-  const float *c = a.scl_in;
   const float tr = err + ett + ezz;
   const float lt = lam * tr, m2 = 2.0f * mu;
-  float s_rr = S::ldn(a.in[SRR], p, c[SRR]) + a.dt * (lt + m2 * err);
-  float s_tt = S::ldn(a.in[STT], p, c[STT]) + a.dt * (lt + m2 * ett);
-  float s_zz = S::ldn(a.in[SZZ], p, c[SZZ]) + a.dt * (lt + m2 * ezz);
-  float s_rt = S::ldn(a.in[SRT], p, c[SRT]) + a.dt * mu_rt * (rt_dr + rt_b);
-  float s_rz = S::ldn(a.in[SRZ], p, c[SRZ]) + a.dt * mu_rz * (rz_dr + rz_dz);
-  float s_tz = S::ldn(a.in[STZ], p, c[STZ]) + a.dt * mu_tz * (tz_b + tz_dz);
+  float s_rr = so_rr + a.dt * (lt + m2 * err);
+  float s_tt = so_tt + a.dt * (lt + m2 * ett);
+  float s_zz = so_zz + a.dt * (lt + m2 * ezz);
+  float s_rt = so_rt + a.dt * mu_rt * (rt_dr + rt_b);
+  float s_rz = so_rz + a.dt * mu_rz * (rz_dr + rz_dz);
+  float s_tz = so_tz + a.dt * mu_tz * (tz_b + tz_dz);
   // this step's stress sources at the cell, in the order they were added
   // (only workgroups of the rings the sources touch look at the list: the
   // scalar unit is this kernel's busiest)

@@ -79,9 +79,9 @@ __device__ __forceinline__ void velocity_column(const StepArgs &a, int i, int j,
   S::ldb(stz_jm, R_stz, L.v0, L.sjm, c[STZ]);
   S::ldb(szz0, R_szz, L.v0, L.sj, c[SZZ]);
   // depth neighbours of the group (zero outside the grid)
-  const float srz_b = L.has_b ? S::ldb1(R_srz, L.vb, L.sj, c[SRZ]) : 0.0f;
-  const float stz_b = L.has_b ? S::ldb1(R_stz, L.vb, L.sj, c[STZ]) : 0.0f;
-  const float szz_a = L.has_a ? S::ldb1(R_szz, L.va, L.sj, c[SZZ]) : 0.0f;
+  const float srz_b = ldz<S>(L.has_b, R_srz, L.vb, L.sj, c[SRZ]);
+  const float stz_b = ldz<S>(L.has_b, R_stz, L.vb, L.sj, c[STZ]);
+  const float szz_a = ldz<S>(L.has_a, R_szz, L.va, L.sj, c[SZZ]);
   float rho0[VW], rho_i1[VW], rho_jp[VW];
   const rsrc_t R_rho = L.med(a.rho, i);
   ldb4(rho0, R_rho, L.m0, L.mj);
@@ -200,9 +200,9 @@ __device__ __forceinline__ void stress_column(const StepArgs &a, int i, int j, i
   S::ldb(vz0, R_vz, L.v0, L.sj, o[VZ]);
   ldf<S>(vz_ip, L, a, vZ, o[VZ], i + 1, L.sj);
   S::ldb(vz_jp, R_vz, L.v0, L.sjp, o[VZ]);
-  const float vr_a = L.has_a ? S::ldb1(R_vr, L.va, L.sj, o[VR]) : 0.0f;
-  const float vt_a = L.has_a ? S::ldb1(R_vt, L.va, L.sj, o[VT]) : 0.0f;
-  const float vz_b = L.has_b ? S::ldb1(R_vz, L.vb, L.sj, o[VZ]) : 0.0f;
+  const float vr_a = ldz<S>(L.has_a, R_vr, L.va, L.sj, o[VR]);
+  const float vt_a = ldz<S>(L.has_a, R_vt, L.va, L.sj, o[VT]);
+  const float vz_b = ldz<S>(L.has_b, R_vz, L.vb, L.sj, o[VZ]);
 
   const float irc = a.inv_rc[i], irf = a.inv_rf[i];
   float err[VW], ett[VW], ezz[VW], rt_dr[VW], rt_b[VW], rz_dr[VW], rz_dz[VW], tz_b[VW], tz_dz[VW];

@@ -53,29 +53,6 @@ __device__ __forceinline__ float ld1(const float *f, float s, const StepArgs &a,
   return (k >= 0 && k < a.nz) ? v : 0.0f;
 }
 
-__device__ __forceinline__ void ldv4(float (&o)[VW], const float *f, size_t p)
-{
-  const float4 v = *reinterpret_cast<const float4 *>(f + p);
-  o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
-}
-__device__ __forceinline__ void stv4(float *f, size_t p, const float (&v)[VW])
-{
-  *reinterpret_cast<float4 *>(f + p) = make_float4(v[0], v[1], v[2], v[3]);
-}
-
-// layer memory update of VW consecutive values in the radial slab: psi <- b psi + a X, X += psi
-__device__ __forceinline__ void cpml_v(float *psi, size_t q, float ca, float cb, float (&X)[VW])
-{
-  float p[VW];
-  ldv4(p, psi, q);
-#pragma unroll
-  for (int e = 0; e < VW; e++) {
-    p[e] = cb * p[e] + ca * X[e];
-    X[e] += p[e];
-  }
-  stv4(psi, q, p);
-}
-
 __device__ __forceinline__ float cpml1(float *psi, size_t q, float ca, float cb, float X)
 {
   const float v = cb * psi[q] + ca * X;
@@ -136,12 +113,26 @@ struct Lanes {
 };
 
 // VW values of a field at ring i, row offset soff: zero for a ring outside
-// [0, nr) unless a ghost ring stands there
+// [0, nr) unless a ghost ring stands there.
+// In 16-bit storage such a ring is read through an empty resource (size 0:
+// every read is out of range and returns zero) rather than skipped by a
+// branch: those forms convert a value where it is loaded, so a load inside
+// a branch waits there for every load in flight, and the six guarded
+// neighbour reads of a column cost six memory round trips one after the
+// other (measured at 256 x 128 x 8192: bfloat16 4.01 -> 3.87 ms per step,
+// float16 4.55 -> 4.30).  Float32 keeps the branch, which waits for nothing:
+// read unconditionally, the batched launches were 2 % slower.
 template <class S>
 __device__ __forceinline__ void ldf(float (&o)[VW], const Lanes<S> &L, const StepArgs &a, const float *f, float s,
                                     int i, unsigned soff)
 {
-  if ((i < 0 && !a.ghost_in) || (i >= a.nr && !a.ghost_out)) {
+  const bool out = (i < 0 && !a.ghost_in) || (i >= a.nr && !a.ghost_out);
+  if (S::bytes == 2) {
+    const rsrc_t r = make_rsrc(S::adv(f, (ptrdiff_t)(out ? 0 : i) * (ptrdiff_t)L.ring), out ? 0u : L.ringb);
+    S::ldb(o, r, L.v0, soff, s);
+    return;
+  }
+  if (out) {
 #pragma unroll
     for (int e = 0; e < VW; e++) o[e] = 0.0f;
     return;
@@ -149,7 +140,25 @@ __device__ __forceinline__ void ldf(float (&o)[VW], const Lanes<S> &L, const Ste
   S::ldb(o, L.field(f, i), L.v0, soff, s);
 }
 
-// layer memory update of the lane's VW values of one radial-slab array: psi <- b psi + a X, X += psi
+// one depth neighbour of the lane's group (offset voff, clamped to a valid
+// cell when there is none), zero when there is none; in 16-bit storage read
+// unconditionally and selected, for the reason given at ldf
+template <class S>
+__device__ __forceinline__ float ldz(bool has, rsrc_t r, unsigned voff, unsigned soff, float s)
+{
+  if (S::bytes == 2) {
+    const float x = S::ldb1(r, voff, soff, s);
+    return has ? x : 0.0f;
+  }
+  return has ? S::ldb1(r, voff, soff, s) : 0.0f;
+}
+
+// layer memory update of the lane's VW values of one radial-slab array: psi <- b psi + a X, X += psi.
+// The arrays of a layer block are updated one after the other, each read
+// waiting for the previous store.  Reading them two at a time before writing
+// (as the one-cell kernels read all six) held more registers and made the
+// four-cell forms slower at 256 x 128 x 8192: bfloat16 4.22 against 3.87 ms
+// per step, float16 4.66 against 4.31.
 __device__ __forceinline__ void cpml_b(rsrc_t r, unsigned voff, unsigned soff, float ca, float cb, float (&X)[VW])
 {
   float p[VW];
