@@ -44,11 +44,14 @@ __device__ __forceinline__ float hm4(float p, float q, float r, float s)
   return 4.0f * rcp(rcp(p) + rcp(q) + rcp(r) + rcp(s));
 }
 // transposed layer recursion: forward psi' = b psi + a X, out = X + psi';
-// from out's adjoint and psi''s adjoint (in *pb) returns X's adjoint and
-// leaves psi's adjoint in *pb
-__device__ __forceinline__ float sadj(float *pb, float ca, float cb, float outb)
+// from out's adjoint and psi''s adjoint (old, read from *pb) returns X's
+// adjoint and leaves psi's adjoint in *pb.  A cell's layer block reads
+// every old value and coefficient before it writes any: a store could
+// alias a later read, so one array after the other would cost the cell a
+// memory round trip per array.
+__device__ __forceinline__ float sadj(float *pb, float old, float ca, float cb, float outb)
 {
-  const float t = *pb + outb;
+  const float t = old + outb;
   *pb = cb * t;
   return outb + ca * t;
 }
@@ -122,20 +125,28 @@ __device__ __forceinline__ void stress_terms_cell(const AdjArgs &a, int i, int j
   if (ir >= 0) {
     const size_t q = ((size_t)ir * a.nt + j) * a.nz + k;
     const float *T = a.tab_r;
-    err = sadj(&a.pr[R_N_DR][q], T[AR_C * a.nr + i], T[BR_C * a.nr + i], err);
-    ett = sadj(&a.pr[R_N_B][q], T[AT_C * a.nr + i], T[BT_C * a.nr + i], ett);
-    rt_dr = sadj(&a.pr[R_RT_DR][q], T[AR_F * a.nr + i], T[BR_F * a.nr + i], zrt);
-    rt_b = sadj(&a.pr[R_RT_B][q], T[AT_F * a.nr + i], T[BT_F * a.nr + i], zrt);
-    rz_dr = sadj(&a.pr[R_RZ_DR][q], T[AR_F * a.nr + i], T[BR_F * a.nr + i], zrz);
-    tz_b = sadj(&a.pr[R_TZ_B][q], T[AT_C * a.nr + i], T[BT_C * a.nr + i], ztz);
+    float *const *P = a.pr;
+    const float ar_c = T[AR_C * a.nr + i], br_c = T[BR_C * a.nr + i], at_c = T[AT_C * a.nr + i], bt_c = T[BT_C * a.nr + i];
+    const float ar_f = T[AR_F * a.nr + i], br_f = T[BR_F * a.nr + i], at_f = T[AT_F * a.nr + i], bt_f = T[BT_F * a.nr + i];
+    const float m0 = P[R_N_DR][q], m1 = P[R_N_B][q], m2 = P[R_RT_DR][q];
+    const float m3 = P[R_RT_B][q], m4 = P[R_RZ_DR][q], m5 = P[R_TZ_B][q];
+    err = sadj(&P[R_N_DR][q], m0, ar_c, br_c, err);
+    ett = sadj(&P[R_N_B][q], m1, at_c, bt_c, ett);
+    rt_dr = sadj(&P[R_RT_DR][q], m2, ar_f, br_f, zrt);
+    rt_b = sadj(&P[R_RT_B][q], m3, at_f, bt_f, zrt);
+    rz_dr = sadj(&P[R_RZ_DR][q], m4, ar_f, br_f, zrz);
+    tz_b = sadj(&P[R_TZ_B][q], m5, at_c, bt_c, ztz);
   }
   const int kz = zrow(a, k);
   if (kz >= 0) {
     const size_t q = ((size_t)i * a.nt + j) * a.nzs + kz;
     const float *T = a.tab_z;
-    ezz = sadj(&a.pz[Z_N_DZ][q], T[AZ_C * a.nz + k], T[BZ_C * a.nz + k], ezz);
-    rz_dz = sadj(&a.pz[Z_RZ_DZ][q], T[AZ_H * a.nz + k], T[BZ_H * a.nz + k], zrz);
-    tz_dz = sadj(&a.pz[Z_TZ_DZ][q], T[AZ_H * a.nz + k], T[BZ_H * a.nz + k], ztz);
+    float *const *P = a.pz;
+    const float az_c = T[AZ_C * a.nz + k], bz_c = T[BZ_C * a.nz + k], az_h = T[AZ_H * a.nz + k], bz_h = T[BZ_H * a.nz + k];
+    const float m0 = P[Z_N_DZ][q], m1 = P[Z_RZ_DZ][q], m2 = P[Z_TZ_DZ][q];
+    ezz = sadj(&P[Z_N_DZ][q], m0, az_c, bz_c, ezz);
+    rz_dz = sadj(&P[Z_RZ_DZ][q], m1, az_h, bz_h, zrz);
+    tz_dz = sadj(&P[Z_TZ_DZ][q], m2, az_h, bz_h, ztz);
   }
   a.T[0][p] = err; a.T[1][p] = ett; a.T[2][p] = ezz;
   a.T[3][p] = rt_dr; a.T[4][p] = rt_b; a.T[5][p] = rz_dr;
@@ -208,20 +219,28 @@ __device__ __forceinline__ void velocity_terms_cell(const AdjArgs &a, int i, int
   if (ir >= 0) {
     const size_t q = ((size_t)ir * a.nt + j) * a.nz + k;
     const float *T = a.tab_r;
-    r_dr = sadj(&a.pr[R_VR_DR][q], T[AR_F * a.nr + i], T[BR_F * a.nr + i], wr);
-    r_b = sadj(&a.pr[R_VR_B][q], T[AT_F * a.nr + i], T[BT_F * a.nr + i], wr);
-    t_dr = sadj(&a.pr[R_VT_DR][q], T[AR_C * a.nr + i], T[BR_C * a.nr + i], wt);
-    t_b = sadj(&a.pr[R_VT_B][q], T[AT_C * a.nr + i], T[BT_C * a.nr + i], wt);
-    z_dr = sadj(&a.pr[R_VZ_DR][q], T[AR_C * a.nr + i], T[BR_C * a.nr + i], wz);
-    z_b = sadj(&a.pr[R_VZ_B][q], T[AT_C * a.nr + i], T[BT_C * a.nr + i], wz);
+    float *const *P = a.pr;
+    const float ar_f = T[AR_F * a.nr + i], br_f = T[BR_F * a.nr + i], at_f = T[AT_F * a.nr + i], bt_f = T[BT_F * a.nr + i];
+    const float ar_c = T[AR_C * a.nr + i], br_c = T[BR_C * a.nr + i], at_c = T[AT_C * a.nr + i], bt_c = T[BT_C * a.nr + i];
+    const float m0 = P[R_VR_DR][q], m1 = P[R_VR_B][q], m2 = P[R_VT_DR][q];
+    const float m3 = P[R_VT_B][q], m4 = P[R_VZ_DR][q], m5 = P[R_VZ_B][q];
+    r_dr = sadj(&P[R_VR_DR][q], m0, ar_f, br_f, wr);
+    r_b = sadj(&P[R_VR_B][q], m1, at_f, bt_f, wr);
+    t_dr = sadj(&P[R_VT_DR][q], m2, ar_c, br_c, wt);
+    t_b = sadj(&P[R_VT_B][q], m3, at_c, bt_c, wt);
+    z_dr = sadj(&P[R_VZ_DR][q], m4, ar_c, br_c, wz);
+    z_b = sadj(&P[R_VZ_B][q], m5, at_c, bt_c, wz);
   }
   const int kz = zrow(a, k);
   if (kz >= 0) {
     const size_t q = ((size_t)i * a.nt + j) * a.nzs + kz;
     const float *T = a.tab_z;
-    r_dz = sadj(&a.pz[Z_VR_DZ][q], T[AZ_C * a.nz + k], T[BZ_C * a.nz + k], wr);
-    t_dz = sadj(&a.pz[Z_VT_DZ][q], T[AZ_C * a.nz + k], T[BZ_C * a.nz + k], wt);
-    z_dz = sadj(&a.pz[Z_VZ_DZ][q], T[AZ_H * a.nz + k], T[BZ_H * a.nz + k], wz);
+    float *const *P = a.pz;
+    const float az_c = T[AZ_C * a.nz + k], bz_c = T[BZ_C * a.nz + k], az_h = T[AZ_H * a.nz + k], bz_h = T[BZ_H * a.nz + k];
+    const float m0 = P[Z_VR_DZ][q], m1 = P[Z_VT_DZ][q], m2 = P[Z_VZ_DZ][q];
+    r_dz = sadj(&P[Z_VR_DZ][q], m0, az_c, bz_c, wr);
+    t_dz = sadj(&P[Z_VT_DZ][q], m1, az_c, bz_c, wt);
+    z_dz = sadj(&P[Z_VZ_DZ][q], m2, az_h, bz_h, wz);
   }
   a.T[0][p] = r_dr; a.T[1][p] = r_b; a.T[2][p] = r_dz;
   a.T[3][p] = t_dr; a.T[4][p] = t_b; a.T[5][p] = t_dz;
@@ -323,16 +342,28 @@ __device__ __forceinline__ void st4(float *f, size_t q, const float (&v)[AW])
 #define CW_ADJ_NT 1
 #endif
 typedef float f4v __attribute__((ext_vector_type(4)));
-// f[q..q+3] += v: the gathers' own updates, which no other lane of the
-// launch reads, load and store non-temporally (the caches stay with the
-// arrays that neighbouring columns re-read)
-__device__ __forceinline__ void add4(float *f, size_t q, const float (&v)[AW])
+// f[m][q..q+3] += v[m] for the N arrays f[0..N-1]: the gathers' own
+// updates, which no other lane of the launch reads, load and store
+// non-temporally (the caches stay with the arrays that neighbouring columns
+// re-read).  Every old value is read before any sum is stored: a store could
+// alias a later read, so one array after the other would cost the lane a
+// memory round trip per array.
+template <int N>
+__device__ __forceinline__ void add4n(float *const *f, size_t q, const float (&v)[N][AW])
 {
-  f4v *p = reinterpret_cast<f4v *>(f + q);
-  f4v o = CW_ADJ_NT ? __builtin_nontemporal_load(p) : *p;
-  o.x += v[0]; o.y += v[1]; o.z += v[2]; o.w += v[3];
-  if (CW_ADJ_NT) __builtin_nontemporal_store(o, p);
-  else *p = o;
+  f4v o[N];
+#pragma unroll
+  for (int m = 0; m < N; m++) {
+    f4v *p = reinterpret_cast<f4v *>(f[m] + q);
+    o[m] = CW_ADJ_NT ? __builtin_nontemporal_load(p) : *p;
+  }
+#pragma unroll
+  for (int m = 0; m < N; m++) {
+    f4v *p = reinterpret_cast<f4v *>(f[m] + q);
+    o[m].x += v[m][0]; o[m].y += v[m][1]; o[m].z += v[m][2]; o[m].w += v[m][3];
+    if (CW_ADJ_NT) __builtin_nontemporal_store(o[m], p);
+    else *p = o[m];
+  }
 }
 // ---- fused gathers (nz a multiple of 4).  Outside the layer slabs a
 // term is a pointwise function of the field adjoints and the medium, so
@@ -501,7 +532,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CW_ADJ
     slab_terms1(a, i, j, kbm, Tb);
     slab_terms1(a, i, j, kba, Ta);
   }
-  float gr[AW], gt[AW], gz[AW];
+  float g[3][AW];
   for (int e = 0; e < AW; e++) {
     const int k = kb + e;
     float r = T[0][e] * a.inv_dr + 0.5f * ci * T[1][e];
@@ -519,11 +550,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CW_ADJ
     z -= T[5][e] * a.inv_dr;
     if (has_im) z += Tim[5][e] * a.inv_dr;
     z += ci * (Tjm[7][e] - T[7][e]) * a.inv_dth;
-    gr[e] = r; gt[e] = t; gz[e] = z;
+    g[0][e] = r; g[1][e] = t; g[2][e] = z;
   }
-  add4(a.fb[VR], c.p, gr);
-  add4(a.fb[VT], c.p, gt);
-  add4(a.fb[VZ], c.p, gz);
+  add4n<3>(a.fb + VR, c.p, g);
 }
 
 template <bool AXI>
@@ -572,7 +601,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CW_ADJ
     if (k + 1 < a.nz) tz -= (e + 1 < AW ? T[5][e + 1] : Ta[5]) * a.inv_dz;
     g[0][e] = rr; g[1][e] = tt; g[2][e] = zz; g[3][e] = rt; g[4][e] = rz; g[5][e] = tz;
   }
-  for (int q = 0; q < 6; q++) add4(a.fb[SRR + q], c.p, g[q]);
+  add4n<6>(a.fb + SRR, c.p, g);
 }
 
 // receivers: the loss's derivative with respect to sigma^{n+1}; weights
