@@ -146,16 +146,18 @@ cw_status cw_bind(cw_sim *s, void *workspace, uint64_t bytes, void *stream);
 /* Enqueue nsteps time steps.  Asynchronous. */
 cw_status cw_step(cw_sim *s, int64_t nsteps);
 
-/* Wait for all work enqueued by this simulation. */
+/* Wait for all work enqueued by this simulation.  With float16 storage,
+   CW_ERR_NONFINITE once a field has overflowed (see cw_set_storage). */
 cw_status cw_sync(cw_sim *s);
 
 /* Copy the traces recorded so far into out (float64, [nreceivers][cap]
    row-major, cap >= steps done).  *nsteps_done receives the step count.
-   Synchronous. */
+   Synchronous.  CW_ERR_NONFINITE (traces copied) as cw_sync. */
 cw_status cw_get_traces(cw_sim *s, double *out, int64_t cap, int64_t *nsteps_done);
 
 /* Copy one field of the current state to host float32 [nr][ntheta][nz]
-   (16-bit storage is converted, scale applied).  Synchronous. */
+   (16-bit storage is converted, scale applied).  Synchronous.
+   CW_ERR_NONFINITE (field copied) as cw_sync. */
 cw_status cw_get_field(cw_sim *s, int32_t field, float *host_out);
 
 /* Overwrite one field of the current state (initial conditions, restart);
@@ -194,6 +196,13 @@ cw_status cw_steps_done(const cw_sim *s, int64_t *n);
    float16 values carry a power-of-two scale per field: after every step
    the device sets the next scale from the largest magnitude just written,
    so that the stored maxima sit in [2^10, 2^11) (no host round trip).
+   A field may therefore grow by up to 2^5 from one step to the next; a
+   larger jump (a state far from equilibrium, such as unrelated random
+   stresses and velocities set with cw_set_field) stores infinities, and
+   cw_sync, cw_get_field and cw_get_traces then return CW_ERR_NONFINITE
+   until cw_reset.  A source does not cause it by itself: the first write
+   of a field a source injects into takes the scale of its largest
+   injected value.
    bfloat16 has float32's exponent range and needs no scale.  Rounding is
    to nearest even.  Call before cw_bind. */
 enum { CW_STORE_F32 = 0, CW_STORE_F16, CW_STORE_BF16 };

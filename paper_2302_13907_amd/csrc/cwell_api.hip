@@ -104,7 +104,7 @@ struct cw_sim {
   int rounding = CW_ROUND_NEAREST;   // rounding of the 16-bit field stores (cw_set_rounding)
   float *d_scl = nullptr;       // [3][NF]: scale of buffer 0, buffer 1, next write
   float scl_init[3 * NF] = {};  // host copy of the scales zero_state starts from
-  unsigned *d_maxabs = nullptr; // [NF][kMaxSlots]
+  unsigned *d_maxabs = nullptr; // [NF][kMaxSlots], then the float16 overflow word (kOverflowWord)
   Inject *d_inject = nullptr;
   int ninject = 0;
   std::vector<Inject> inject_host;
@@ -243,7 +243,7 @@ Layout layout(const cw_sim *s)
   L.rec = take(s->receivers.size() * sizeof(Receiver));
   L.traces = take(s->receivers.size() * (size_t)s->trace_cap * sizeof(double));
   L.energy = take((kEnergyBlocks + 1) * sizeof(double));
-  L.scales = take(3 * NF * sizeof(float) + NF * kMaxSlots * sizeof(unsigned));
+  L.scales = take(3 * NF * sizeof(float) + (kOverflowWord + 1) * sizeof(unsigned));
   L.step = take(2 * sizeof(int64_t));   // the step counter, then the finish counter of the step's last launch
   L.adj = take(adj_bytes(s));
   L.total = off;
@@ -414,7 +414,7 @@ cw_status zero_state(cw_sim *s)
       s->scl_init[2 * NF + q] = std::ldexp(1.0f, ex - kF16TargetExp);
     }
   HIPCHK(hipMemcpyAsync(s->d_scl, s->scl_init, sizeof s->scl_init, hipMemcpyHostToDevice, s->stream));
-  HIPCHK(hipMemsetAsync(s->d_maxabs, 0, NF * kMaxSlots * sizeof(unsigned), s->stream));
+  HIPCHK(hipMemsetAsync(s->d_maxabs, 0, (kOverflowWord + 1) * sizeof(unsigned), s->stream));
   const size_t psir = 2 * (size_t)NPSI_R * s->npr * s->nt * s->nz * sizeof(float);
   const size_t psiz = 2 * (size_t)NPSI_Z * s->nr * s->nt * nzs_of(s) * sizeof(float);
   if (psir) HIPCHK(hipMemsetAsync(s->ws + L.psir, 0, psir, s->stream));
@@ -942,12 +942,32 @@ cw_status cw_step(cw_sim *s, int64_t nsteps)
   return CW_OK;
 }
 
+// After the stream has drained: CW_ERR_NONFINITE once a float16 field has
+// overflowed (the device sets the field's bit; it stays set until the state
+// is reset), else CW_OK.
+static cw_status check_overflow(cw_sim *s)
+{
+  if (s->storage != ST_F16) return CW_OK;
+  unsigned mask = 0u;
+  HIPCHK(hipMemcpyAsync(&mask, s->d_maxabs + kOverflowWord, sizeof mask, hipMemcpyDeviceToHost, s->stream));
+  HIPCHK(hipStreamSynchronize(s->stream));
+  if (!mask) return CW_OK;
+  static const char *const name[NF] = {"vr", "vt", "vz", "srr", "stt", "szz", "srt", "srz", "stz"};
+  int q = 0;
+  while (!(mask >> q & 1u)) q++;
+  return fail(CW_ERR_NONFINITE,
+              "float16 field %s overflowed (fields mask 0x%x): it grew more than its scale's headroom of 2^%d "
+              "in one step; the state is not valid until cw_reset or cw_bind",
+              name[q], mask, 16 - kF16TargetExp);
+}
+
 cw_status cw_sync(cw_sim *s)
 {
   if (!s) return fail(CW_ERR_ARG, "null simulation");
   if (!s->bound) return fail(CW_ERR_STATE, "cw_bind first");
+  HIPCHK(hipSetDevice(s->device));
   HIPCHK(hipStreamSynchronize(s->stream));
-  return CW_OK;
+  return check_overflow(s);
 }
 
 cw_status cw_get_traces(cw_sim *s, double *out, int64_t cap, int64_t *nsteps_done)
@@ -961,7 +981,7 @@ cw_status cw_get_traces(cw_sim *s, double *out, int64_t cap, int64_t *nsteps_don
   HIPCHK(hipMemcpy2DAsync(out, cap * sizeof(double), s->d_traces, s->trace_cap * sizeof(double),
                           s->nstep * sizeof(double), s->receivers.size(), hipMemcpyDeviceToHost, s->stream));
   HIPCHK(hipStreamSynchronize(s->stream));
-  return CW_OK;
+  return check_overflow(s);
 }
 
 // float16 scale for values up to maxabs: 2^(e - target), max = f 2^e
@@ -1012,7 +1032,7 @@ cw_status cw_get_field(cw_sim *s, int32_t field, float *host_out)
   } else {
     for (size_t p = 0; p < s->n; p++) host_out[p] = bf16_to_float(raw[p]);
   }
-  return CW_OK;
+  return check_overflow(s);
 }
 
 cw_status cw_set_field(cw_sim *s, int32_t field, const float *host_in)

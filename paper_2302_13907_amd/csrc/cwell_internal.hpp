@@ -12,6 +12,9 @@ enum Field { VR = 0, VT, VZ, SRR, STT, SZZ, SRT, SRZ, STZ, NF };
 // Storage of the 9 fields (arithmetic is float32 in every case).
 enum Storage { ST_F32 = 0, ST_F16, ST_BF16 };
 constexpr int kMaxSlots = 64;       // max-abs slots per field (float16 scale tracking)
+// after the NF * kMaxSlots maxima slots: one word whose bit q says that
+// float16 field q overflowed (grew past its scale's headroom in one step)
+constexpr int kOverflowWord = NF * kMaxSlots;
 
 // Layer memory variables living in the radial slab i >= nr - npml_r.
 enum PsiR {
@@ -65,8 +68,8 @@ struct StepArgs {
   // 16-bit storage: a stored value times its field's scale is the physical
   // value.  scl_in scales the level-n buffer, scl_out the level-n+1 buffer;
   // maxabs collects the largest |value| written (float bits, kMaxSlots
-  // slots per field, for the next step's scale).  Unused (scales 1) for
-  // float32 storage.
+  // slots per field, for the next step's scale), then the overflow word
+  // (kOverflowWord).  Unused (scales 1) for float32 storage.
   const float *scl_in, *scl_out;
   unsigned *maxabs;
   // Source injections of a solo two-pass step: the list, its length, the

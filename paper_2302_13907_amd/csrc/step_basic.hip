@@ -508,17 +508,26 @@ __global__ void __launch_bounds__(256) k_inject_batch(const BatchInst *B, int ph
 
 // New float16 scale of field q: 2^(e - target) with max|v| = f 2^e,
 // f in [0.5, 1); unchanged while the field is still identically zero.  The
-// maxima slots are cleared for the next step.
+// maxima slots are cleared for the next step.  The maxima are of the
+// float32 values before their conversion, so a maximum of 65520 or more
+// times the scale they were stored with means that a value outran the
+// scale's headroom (2^16 / 2^target) in one step and was stored as
+// infinity (65520 is the least value that float16 rounds to infinity), and
+// a NaN maximum that a NaN was written: the field's bit is set in the
+// overflow word, which stays set until the state is reset.
 __device__ void rescale_field(int q, float *scl_written, float *scl_next, unsigned *maxabs)
 {
-  scl_written[q] = scl_next[q];
+  const float used = scl_next[q];
+  scl_written[q] = used;
   unsigned mb = 0u;
   for (int c = 0; c < kMaxSlots; c++) {
     mb = max(mb, maxabs[q * kMaxSlots + c]);
     maxabs[q * kMaxSlots + c] = 0u;
   }
   const float m = __builtin_bit_cast(float, mb);
-  if (m > 0.0f) {
+  if (m != m || m >= 65520.0f * used) {
+    atomicOr(&maxabs[kOverflowWord], 1u << q);
+  } else if (m > 0.0f) {
     int e;
     frexpf(m, &e);
     scl_next[q] = ldexpf(1.0f, e - kF16TargetExp);
