@@ -61,6 +61,17 @@ __device__ __forceinline__ void velocity_column(const StepArgs &a, int i, int j,
   const Lanes<S> L(a, kb, j, jm, jp);
   const float *c = a.scl_in;
   const int i1 = i + 1 <= a.m_last ? i + 1 : a.m_last;   // medium ring index, clamped at the edge
+  // densities first: issued after the stresses, the compiler held them
+  // back until most stress reads had returned, a second round trip.
+  // Measured: bfloat16 velocity update at 256 x 128 x 8192 1.699 -> 1.682
+  // ms per launch (three runs on one box); refined grid 37.5-37.7 against
+  // 37.5-38.9 Gcell/s (run-to-run spread).
+  float rho0[VW], rho_i1[VW], rho_jp[VW];
+  const rsrc_t R_rho = L.med(a.rho, i);
+  ldb4(rho0, R_rho, L.m0, L.mj);
+  ldb4(rho_i1, L.med(a.rho, i1), L.m0, L.mj);              // medium index clamped at the edge
+  ldb4(rho_jp, R_rho, L.m0, L.mjp);
+  const float rho_a = ldb1(R_rho, L.ma, L.mj);
   float srr0[VW], srr1[VW], stt0[VW], stt1[VW], stt_jp[VW], srt0[VW], srt_jm[VW], srt_im[VW];
   float srz0[VW], srz_im[VW], stz0[VW], stz_jm[VW], szz0[VW];
   const rsrc_t R_srr = L.field(a.in[SRR], i), R_stt = L.field(a.in[STT], i), R_srt = L.field(a.in[SRT], i);
@@ -82,12 +93,6 @@ __device__ __forceinline__ void velocity_column(const StepArgs &a, int i, int j,
   const float srz_b = ldz<S>(L.has_b, R_srz, L.vb, L.sj, c[SRZ]);
   const float stz_b = ldz<S>(L.has_b, R_stz, L.vb, L.sj, c[STZ]);
   const float szz_a = ldz<S>(L.has_a, R_szz, L.va, L.sj, c[SZZ]);
-  float rho0[VW], rho_i1[VW], rho_jp[VW];
-  const rsrc_t R_rho = L.med(a.rho, i);
-  ldb4(rho0, R_rho, L.m0, L.mj);
-  ldb4(rho_i1, L.med(a.rho, i1), L.m0, L.mj);              // medium index clamped at the edge
-  ldb4(rho_jp, R_rho, L.m0, L.mjp);
-  const float rho_a = ldb1(R_rho, L.ma, L.mj);
 
   const float irc = a.inv_rc[i], irf = a.inv_rf[i];
   float r_dr[VW], r_b[VW], r_dz[VW], t_dr[VW], t_b[VW], t_dz[VW], z_dr[VW], z_b[VW], z_dz[VW];
@@ -204,6 +209,19 @@ __device__ __forceinline__ void stress_column(const StepArgs &a, int i, int j, i
   const float vt_a = ldz<S>(L.has_a, R_vt, L.va, L.sj, o[VT]);
   const float vz_b = ldz<S>(L.has_b, R_vz, L.vb, L.sj, o[VZ]);
 
+  // The old stresses: float16 reads them here, with the velocities and
+  // before the layer block, whose stores could alias them (read after it
+  // they take a second memory round trip); the other storages read them
+  // after it (below), where they hold fewer registers across the block.
+  // Measured at 256 x 128 x 8192, ms per stress launch, read here against
+  // after the block: float16 2.20 against 2.30-2.38; bfloat16 2.14 against
+  // 2.04-2.12; float32 (8 waves per SIMD) spilled and slowed the solo
+  // four-cell step by 28 %.
+  float old[6][VW];
+  if constexpr (S::scaled) {
+#pragma unroll
+    for (int q = 0; q < 6; q++) S::ldbu(old[q], L.field(a.in[SRR + q], i), L.v0, L.sj, a.scl_in[SRR + q]);
+  }
   const float irc = a.inv_rc[i], irf = a.inv_rf[i];
   float err[VW], ett[VW], ezz[VW], rt_dr[VW], rt_b[VW], rz_dr[VW], rz_dz[VW], tz_b[VW], tz_dz[VW];
 #pragma unroll
@@ -262,12 +280,20 @@ __device__ __forceinline__ void stress_column(const StepArgs &a, int i, int j, i
   const rsrc_t R_srr = L.field(a.in[SRR], i), R_stt = L.field(a.in[STT], i), R_szz = L.field(a.in[SZZ], i);
   const rsrc_t R_srt = L.field(a.in[SRT], i), R_srz = L.field(a.in[SRZ], i), R_stz = L.field(a.in[STZ], i);
   float srr[VW], stt[VW], szz[VW], srt[VW], srz[VW], stz[VW];
-  S::ldbu(srr, R_srr, L.v0, L.sj, c[SRR]);
-  S::ldbu(stt, R_stt, L.v0, L.sj, c[STT]);
-  S::ldbu(szz, R_szz, L.v0, L.sj, c[SZZ]);
-  S::ldbu(srt, R_srt, L.v0, L.sj, c[SRT]);
-  S::ldbu(srz, R_srz, L.v0, L.sj, c[SRZ]);
-  S::ldbu(stz, R_stz, L.v0, L.sj, c[STZ]);
+  if constexpr (S::scaled) {
+#pragma unroll
+    for (int e = 0; e < VW; e++) {
+      srr[e] = old[0][e]; stt[e] = old[1][e]; szz[e] = old[2][e];
+      srt[e] = old[3][e]; srz[e] = old[4][e]; stz[e] = old[5][e];
+    }
+  } else {
+    S::ldbu(srr, R_srr, L.v0, L.sj, c[SRR]);
+    S::ldbu(stt, R_stt, L.v0, L.sj, c[STT]);
+    S::ldbu(szz, R_szz, L.v0, L.sj, c[SZZ]);
+    S::ldbu(srt, R_srt, L.v0, L.sj, c[SRT]);
+    S::ldbu(srz, R_srz, L.v0, L.sj, c[SRZ]);
+    S::ldbu(stz, R_stz, L.v0, L.sj, c[STZ]);
+  }
 #pragma unroll
   for (int e = 0; e < VW; e++) {
     const float ik = e == VW - 1 ? ia : im[e + 1];            // 1/mu at k+1
