@@ -48,6 +48,19 @@ ROUNDING = {"nearest": 0, "stochastic": 1}
 KERNELS = {"velocity": 0, "stress": 1, "fused": 2, "inject": 3, "record": 4}
 
 
+def _pick(table, key, what: str) -> int:
+    """The C enum value of a named choice; ValueError naming the choices."""
+    if isinstance(table, dict):
+        if key in table:
+            return table[key]
+        names = list(table)
+    else:
+        if key in table:
+            return table.index(key)
+        names = list(table)
+    raise ValueError("unknown %s %r (one of %s)" % (what, key, ", ".join(map(str, names))))
+
+
 class CwellError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__("%s: %s" % (STATUS.get(status, status), msg))
@@ -242,12 +255,12 @@ class Sim:
 
     def add_source(self, kind: str, i: int, j: int, k: int, w: Sequence[float]):
         w = np.ascontiguousarray(w, dtype=np.float64)
-        _check(self.lib.cw_add_source(self.h, SRC_KINDS[kind], i, j, k, _dp(w), len(w)))
+        _check(self.lib.cw_add_source(self.h, _pick(SRC_KINDS, kind, "source kind"), i, j, k, _dp(w), len(w)))
 
     def add_receiver(self, kind: str, i: int, j: int, k: int, field: Optional[str] = None) -> int:
         rid = ctypes.c_int32()
-        fid = FIELDS.index(field) if field else 0
-        _check(self.lib.cw_add_receiver(self.h, REC_KINDS[kind], fid, i, j, k, ctypes.byref(rid)))
+        fid = _pick(FIELDS, field, "field") if field else 0
+        _check(self.lib.cw_add_receiver(self.h, _pick(REC_KINDS, kind, "receiver kind"), fid, i, j, k, ctypes.byref(rid)))
         self.nrec += 1
         return rid.value
 
@@ -295,12 +308,12 @@ class Sim:
 
     def field(self, name: str) -> np.ndarray:
         out = np.empty(self.shape, dtype=np.float32)
-        _check(self.lib.cw_get_field(self.h, FIELDS.index(name), _fp(out)))
+        _check(self.lib.cw_get_field(self.h, _pick(FIELDS, name, "field"), _fp(out)))
         return out
 
     def set_field(self, name: str, a):
         a = np.ascontiguousarray(np.broadcast_to(a, self.shape), dtype=np.float32)
-        _check(self.lib.cw_set_field(self.h, FIELDS.index(name), _fp(a)))
+        _check(self.lib.cw_set_field(self.h, _pick(FIELDS, name, "field"), _fp(a)))
 
     def energy(self) -> float:
         e = ctypes.c_double()
@@ -319,15 +332,15 @@ class Sim:
 
     def set_storage(self, storage: str):
         """Field storage: "f32", "f16" (per-field power-of-two scales) or "bf16"."""
-        _check(self.lib.cw_set_storage(self.h, STORAGE[storage]))
+        _check(self.lib.cw_set_storage(self.h, _pick(STORAGE, storage, "storage")))
 
     def set_rounding(self, mode: str):
         """Rounding of the bfloat16 field stores: "nearest" (default) or "stochastic"."""
-        _check(self.lib.cw_set_rounding(self.h, ROUNDING[mode]))
+        _check(self.lib.cw_set_rounding(self.h, _pick(ROUNDING, mode, "rounding mode")))
 
     def set_path(self, path: str):
         """Kernel path of step(): "auto", "two-pass" or "fused"."""
-        _check(self.lib.cw_set_path(self.h, PATHS[path]))
+        _check(self.lib.cw_set_path(self.h, _pick(PATHS, path, "path")))
 
     def set_adjoint(self, nsteps: int, checkpoint_every: int, region):
         """Configure the adjoint gradient (before bind): region = (i0, i1, k0,
@@ -367,7 +380,7 @@ class Sim:
         """(summed device milliseconds, launches) recorded for one step kernel."""
         ms = ctypes.c_double()
         n = ctypes.c_int64()
-        _check(self.lib.cw_profile_read(self.h, KERNELS[kernel], ctypes.byref(ms), ctypes.byref(n)))
+        _check(self.lib.cw_profile_read(self.h, _pick(KERNELS, kernel, "kernel"), ctypes.byref(ms), ctypes.byref(n)))
         return ms.value, n.value
 
 
@@ -475,12 +488,12 @@ class Refined:
 
     def add_source(self, kind: str, i: int, j: int, k: int, w: Sequence[float]):
         w = np.ascontiguousarray(w, dtype=np.float64)
-        _check(self.lib.cw_refined_add_source(self.h, SRC_KINDS[kind], i, j, k, _dp(w), len(w)))
+        _check(self.lib.cw_refined_add_source(self.h, _pick(SRC_KINDS, kind, "source kind"), i, j, k, _dp(w), len(w)))
 
     def add_receiver(self, kind: str, i: int, j: int, k: int, field: Optional[str] = None) -> int:
         rid = ctypes.c_int32()
-        fid = FIELDS.index(field) if field else 0
-        _check(self.lib.cw_refined_add_receiver(self.h, REC_KINDS[kind], fid, i, j, k, ctypes.byref(rid)))
+        fid = _pick(FIELDS, field, "field") if field else 0
+        _check(self.lib.cw_refined_add_receiver(self.h, _pick(REC_KINDS, kind, "receiver kind"), fid, i, j, k, ctypes.byref(rid)))
         self.nrec += 1
         return rid.value
 
@@ -517,12 +530,12 @@ class Refined:
 
     def field(self, name: str) -> np.ndarray:
         out = np.empty(self.cells, dtype=np.float32)
-        _check(self.lib.cw_refined_get_field(self.h, FIELDS.index(name), _fp(out)))
+        _check(self.lib.cw_refined_get_field(self.h, _pick(FIELDS, name, "field"), _fp(out)))
         return out
 
     def set_field(self, name: str, a):
         a = np.ascontiguousarray(np.reshape(a, self.cells), dtype=np.float32)
-        _check(self.lib.cw_refined_set_field(self.h, FIELDS.index(name), _fp(a)))
+        _check(self.lib.cw_refined_set_field(self.h, _pick(FIELDS, name, "field"), _fp(a)))
 
     def energy(self) -> float:
         e = ctypes.c_double()

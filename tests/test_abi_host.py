@@ -140,8 +140,10 @@ def test_rounding_mode_validation():
     s.set_rounding("stochastic")
     s.set_storage("bf16")
     s.set_rounding("nearest")
-    with pytest.raises(KeyError):
+    with pytest.raises(ValueError, match="rounding mode 'up'"):
         s.set_rounding("up")
+    with pytest.raises(ValueError, match="storage"):
+        s.set_storage("f8")
 
 
 def test_graph_steps_validation():
