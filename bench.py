@@ -410,11 +410,13 @@ def stream_ceiling(kernel: str, axisym: bool, roofline: dict, lane_bytes: int = 
     log("stream ceiling: %d reads + %d writes" % (r, w))
     mix = cwell.stream_probe(r, w) / 1e9
     mix4 = cwell.stream_probe(r, w, lane_bytes=4) / 1e9
+    nt = cwell.stream_probe(r, w, lane_bytes=lane_bytes, nontemporal=True) / 1e9
     copy = cwell.stream_probe(1, 1) / 1e9
     ref = mix4 if lane_bytes == 4 else mix
     return {"kernel": kernel, "reads": r, "writes": w, "GBps": round(mix, 1), "GBps_4B_lanes": round(mix4, 1),
-            "copy_GBps": round(copy, 1), "kernel_lane_bytes": lane_bytes,
-            "frac_of_ceiling": round(roofline["achieved"] / ref, 4)}
+            "GBps_nontemporal": round(nt, 1), "copy_GBps": round(copy, 1), "kernel_lane_bytes": lane_bytes,
+            "frac_of_ceiling": round(roofline["achieved"] / ref, 4),
+            "frac_of_nontemporal_ceiling": round(roofline["achieved"] / nt, 4)}
 
 
 def graph_replay(path: str, graph: int = 20, steps: int = 300):

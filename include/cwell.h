@@ -408,11 +408,15 @@ void cw_refined_destroy(cw_refined *r);
    every group of the write arrays receives the sum of the same group of
    the read arrays, one group per thread, a group being lane_bytes = 16
    (four floats) or 4 (one float) bytes; CW_ERR_ARG for other widths.
+   lane_bytes | CW_PROBE_NONTEMPORAL makes every load and store
+   non-temporal (the lines are not kept): the rate of a stream none of
+   whose data is read again.
    Runs 2 untimed passes and `reps` timed ones
    on `stream` (a hipStream_t, NULL for the default stream), waits, and
    returns the average milliseconds per pass.  Supported (nread, nwrite):
    (1, 1), (9, 3), (10, 3), (9, 6), (11, 6), (9, 9), (12, 9) -- the stream
    mixes of the step kernels; others give CW_ERR_RANGE. */
+#define CW_PROBE_NONTEMPORAL 0x100
 cw_status cw_stream_probe(void *dev, uint64_t bytes_per_array, int32_t nread, int32_t nwrite, int32_t lane_bytes,
                           int32_t reps, void *stream, double *ms_per_pass);
 

@@ -1235,7 +1235,10 @@ cw_status cw_stream_probe(void *dev, uint64_t bytes_per_array, int32_t nread, in
                           int32_t reps, void *stream, double *ms_per_pass)
 {
   if (!dev || !ms_per_pass || reps < 1) return fail(CW_ERR_ARG, "null buffer or result, or reps < 1");
-  if (lane_bytes != 4 && lane_bytes != 16) return fail(CW_ERR_ARG, "lane_bytes must be 4 or 16");
+  const bool nt = (lane_bytes & CW_PROBE_NONTEMPORAL) != 0;
+  lane_bytes &= ~CW_PROBE_NONTEMPORAL;
+  if (lane_bytes != 4 && lane_bytes != 16)
+    return fail(CW_ERR_ARG, "lane_bytes must be 4 or 16 (with CW_PROBE_NONTEMPORAL or not)");
   if (((uintptr_t)dev & 15) || bytes_per_array < 16 || (bytes_per_array & 15))
     return fail(CW_ERR_ARG, "the buffer must be 16-byte aligned and each array a positive multiple of 16 bytes");
   if (!stream_mix_supported(nread, nwrite))
@@ -1251,7 +1254,7 @@ cw_status cw_stream_probe(void *dev, uint64_t bytes_per_array, int32_t nread, in
   float ms = 0.0f;
   auto run = [&](int n) {
     for (int q = 0; q < n; q++)
-      if (launch_stream(dev, bytes_per_array, lane_bytes, nread, nwrite, st) != hipSuccess) return false;
+      if (launch_stream(dev, bytes_per_array, lane_bytes, nt, nread, nwrite, st) != hipSuccess) return false;
     return true;
   };
   if (!run(2) || hipEventRecord(e0, st) != hipSuccess || !run(reps) || hipEventRecord(e1, st) != hipSuccess ||

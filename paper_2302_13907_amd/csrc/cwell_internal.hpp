@@ -281,7 +281,8 @@ hipError_t launch_adjoint_capture(const AdjArgs &a, const AdjRegion &g, const fl
                                   const float *vz, float *Z, hipStream_t stream);
 hipError_t launch_set_step(int64_t *step, int64_t value, hipStream_t stream);
 bool stream_mix_supported(int r, int w);
-hipError_t launch_stream(const void *base, size_t bytes_per_array, int lane_bytes, int r, int w, hipStream_t stream);
+hipError_t launch_stream(const void *base, size_t bytes_per_array, int lane_bytes, bool nt, int r, int w,
+                         hipStream_t stream);
 hipError_t launch_velocity_vec(const StepArgs &a, int storage, hipStream_t stream);
 hipError_t launch_stress_vec(const StepArgs &a, int storage, hipStream_t stream);
 

@@ -181,12 +181,16 @@ def ricker(f0: float, t) -> np.ndarray:
     return out
 
 
+PROBE_NONTEMPORAL = 0x100       # CW_PROBE_NONTEMPORAL
+
+
 def stream_probe(nread: int, nwrite: int, bytes_per_array: int = 1 << 30, reps: int = 10,
-                 device: str = "cuda", lane_bytes: int = 16) -> float:
+                 device: str = "cuda", lane_bytes: int = 16, nontemporal: bool = False) -> float:
     """Achieved bytes per second of a kernel that only streams nread arrays
     in and nwrite arrays out (the access pattern of a step kernel without
     its stencil), lane_bytes (16 or 4) per thread and array, on a
-    torch-allocated buffer on the current stream."""
+    torch-allocated buffer on the current stream; nontemporal: every load
+    and store non-temporal."""
     import torch
     lib = load()
     n = nread + nwrite
@@ -197,7 +201,8 @@ def stream_probe(nread: int, nwrite: int, bytes_per_array: int = 1 << 30, reps: 
     stream = torch.cuda.current_stream(buf.device).cuda_stream
     ms = ctypes.c_double()
     _check(lib.cw_stream_probe(ctypes.c_void_p(ptr), int(bytes_per_array), int(nread), int(nwrite),
-                               int(lane_bytes), int(reps), ctypes.c_void_p(stream), ctypes.byref(ms)))
+                               int(lane_bytes) | (PROBE_NONTEMPORAL if nontemporal else 0), int(reps),
+                               ctypes.c_void_p(stream), ctypes.byref(ms)))
     del buf
     return n * bytes_per_array / (ms.value * 1e-3)
 

@@ -123,6 +123,9 @@ def test_stream_probe_validation():
     assert lib.cw_stream_probe(ctypes.c_void_p(4096), 1000, 9, 3, 16, 1, None, ctypes.byref(ms)) == -1
     assert lib.cw_stream_probe(ctypes.c_void_p(4096), 1 << 20, 9, 3, 16, 0, None, ctypes.byref(ms)) == -1
     assert lib.cw_stream_probe(ctypes.c_void_p(4096), 1 << 20, 9, 3, 8, 1, None, ctypes.byref(ms)) == -1
+    nt = cwell.PROBE_NONTEMPORAL
+    assert lib.cw_stream_probe(ctypes.c_void_p(4096), 1 << 20, 9, 3, 8 | nt, 1, None, ctypes.byref(ms)) == -1
+    assert lib.cw_stream_probe(ctypes.c_void_p(4096), 1 << 20, 9, 3, 16 | nt | 1, 1, None, ctypes.byref(ms)) == -1
     assert b"lane_bytes" in lib.cw_last_error()
     assert lib.cw_stream_probe(ctypes.c_void_p(4096), 1 << 20, 7, 2, 4, 1, None, ctypes.byref(ms)) == -2
     assert b"7 reads" in lib.cw_last_error()
