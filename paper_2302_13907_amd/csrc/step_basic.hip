@@ -102,8 +102,6 @@ __device__ __forceinline__ float ldr(const float *f, float s, bool in, size_t co
   return in ? v : 0.0f;
 }
 
-// depth neighbour k (the lane's depth +- 1) of column col; zero beyond the
-// top and bottom faces, where the load itself is clamped into the column
 // The same reads, non-temporal: for the last read of a value in the
 // launch's dispatch order (ring by ring, then azimuth, then depth), after
 // which no other column needs the line; the first and middle reads stay
@@ -122,6 +120,8 @@ __device__ __forceinline__ float ldrn(const float *f, float s, bool in, size_t c
   return in ? v : 0.0f;
 }
 
+// depth neighbour k (the lane's depth +- 1) of column col; zero beyond the
+// top and bottom faces, where the load itself is clamped into the column
 template <class S>
 __device__ __forceinline__ float ldz(const float *f, float s, const StepArgs &a, size_t col, int k)
 {
