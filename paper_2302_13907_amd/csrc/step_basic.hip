@@ -294,32 +294,47 @@ __global__ void __launch_bounds__(256) k_velocity_basic(StepArgs a, int nbx, Tai
   const float vr_old = S::ldn(a.in[VR], p, c[VR]), vt_old = S::ldn(a.in[VT], p, c[VT]);
   const float vz_old = S::ldn(a.in[VZ], p, c[VZ]);
 
+  // The radial and the depth layer blocks read their memory and coefficients
+  // before either block writes: a store could alias a later read, so the
+  // depth block's reads would otherwise wait for the radial block's stores,
+  // a second memory round trip for the cells in both layers (which set the
+  // launch's length on small grids: 48 x 32 x 192, 16.5 -> 15.8 us per step
+  // with the stress update read the same way; 256 x 128 x 8192 unchanged).
   const int ir = i - (a.nr - a.npr);
-  if (ir >= 0 && live) {
-    const size_t q = ((size_t)ir * a.nt + j) * a.nz + k;
-    const float *T = a.tab_r;
-    float *const *P = a.psi_r;
-    const float arf = T[AR_F * a.nr + i], brf = T[BR_F * a.nr + i], atf = T[AT_F * a.nr + i], btf = T[BT_F * a.nr + i];
-    const float arc = T[AR_C * a.nr + i], brc = T[BR_C * a.nr + i], atc = T[AT_C * a.nr + i], btc = T[BT_C * a.nr + i];
-    const float m0 = ldpsi(P[R_VR_DR], q), m1 = ldpsi(P[R_VR_B], q), m2 = ldpsi(P[R_VT_DR], q);
-    const float m3 = ldpsi(P[R_VT_B], q), m4 = ldpsi(P[R_VZ_DR], q), m5 = ldpsi(P[R_VZ_B], q);
-    r_dr = cpml(P[R_VR_DR], q, m0, arf, brf, r_dr);
-    r_b = cpml(P[R_VR_B], q, m1, atf, btf, r_b);
-    t_dr = cpml(P[R_VT_DR], q, m2, arc, brc, t_dr);
-    t_b = cpml(P[R_VT_B], q, m3, atc, btc, t_b);
-    z_dr = cpml(P[R_VZ_DR], q, m4, arc, brc, z_dr);
-    z_b = cpml(P[R_VZ_B], q, m5, atc, btc, z_b);
-  }
+  const bool lr = ir >= 0 && live;
   const int kz = live ? zrow(a, k) : -1;
-  if (kz >= 0) {
-    const size_t q = ((size_t)i * a.nt + j) * a.nzs + kz;
+  const bool lz = kz >= 0;
+  const size_t qr = lr ? ((size_t)ir * a.nt + j) * a.nz + k : 0;
+  const size_t qz = lz ? ((size_t)i * a.nt + j) * a.nzs + kz : 0;
+  float *const *P = a.psi_r;
+  float *const *Z = a.psi_z;
+  float arf = 0, brf = 0, atf = 0, btf = 0, arc = 0, brc = 0, atc = 0, btc = 0;
+  float m0 = 0, m1 = 0, m2 = 0, m3 = 0, m4 = 0, m5 = 0;
+  float azc = 0, bzc = 0, azh = 0, bzh = 0, n0 = 0, n1 = 0, n2 = 0;
+  if (lr) {
+    const float *T = a.tab_r;
+    arf = T[AR_F * a.nr + i]; brf = T[BR_F * a.nr + i]; atf = T[AT_F * a.nr + i]; btf = T[BT_F * a.nr + i];
+    arc = T[AR_C * a.nr + i]; brc = T[BR_C * a.nr + i]; atc = T[AT_C * a.nr + i]; btc = T[BT_C * a.nr + i];
+    m0 = ldpsi(P[R_VR_DR], qr); m1 = ldpsi(P[R_VR_B], qr); m2 = ldpsi(P[R_VT_DR], qr);
+    m3 = ldpsi(P[R_VT_B], qr); m4 = ldpsi(P[R_VZ_DR], qr); m5 = ldpsi(P[R_VZ_B], qr);
+  }
+  if (lz) {
     const float *T = a.tab_z;
-    float *const *P = a.psi_z;
-    const float azc = T[AZ_C * a.nz + k], bzc = T[BZ_C * a.nz + k], azh = T[AZ_H * a.nz + k], bzh = T[BZ_H * a.nz + k];
-    const float m0 = ldpsi(P[Z_VR_DZ], q), m1 = ldpsi(P[Z_VT_DZ], q), m2 = ldpsi(P[Z_VZ_DZ], q);
-    r_dz = cpml(P[Z_VR_DZ], q, m0, azc, bzc, r_dz);
-    t_dz = cpml(P[Z_VT_DZ], q, m1, azc, bzc, t_dz);
-    z_dz = cpml(P[Z_VZ_DZ], q, m2, azh, bzh, z_dz);
+    azc = T[AZ_C * a.nz + k]; bzc = T[BZ_C * a.nz + k]; azh = T[AZ_H * a.nz + k]; bzh = T[BZ_H * a.nz + k];
+    n0 = ldpsi(Z[Z_VR_DZ], qz); n1 = ldpsi(Z[Z_VT_DZ], qz); n2 = ldpsi(Z[Z_VZ_DZ], qz);
+  }
+  if (lr) {
+    r_dr = cpml(P[R_VR_DR], qr, m0, arf, brf, r_dr);
+    r_b = cpml(P[R_VR_B], qr, m1, atf, btf, r_b);
+    t_dr = cpml(P[R_VT_DR], qr, m2, arc, brc, t_dr);
+    t_b = cpml(P[R_VT_B], qr, m3, atc, btc, t_b);
+    z_dr = cpml(P[R_VZ_DR], qr, m4, arc, brc, z_dr);
+    z_b = cpml(P[R_VZ_B], qr, m5, atc, btc, z_b);
+  }
+  if (lz) {
+    r_dz = cpml(Z[Z_VR_DZ], qz, n0, azc, bzc, r_dz);
+    t_dz = cpml(Z[Z_VT_DZ], qz, n1, azc, bzc, t_dz);
+    z_dz = cpml(Z[Z_VZ_DZ], qz, n2, azh, bzh, z_dz);
   }
 
   const float vr = vr_old + a.dt * b_r * (r_dr + r_b + r_dz);
@@ -369,11 +384,15 @@ __device__ __forceinline__ void stress_cell(const StepArgs &a, int i, int j, int
   float tz_b = irc * (vz_jp - vz0) * a.inv_dth;
   float tz_dz = (vt_kp - vt0) * a.inv_dz;
 
-  // the old stresses are read before the layer block, whose stores could
-  // alias them (read after it, they would take a second memory round trip);
-  // the moduli after it.  Measured at 256 x 128 x 8192, ms per launch: 3.160
-  // this way, 3.176 with both after the block, 3.208 with both before it
-  // (more registers held across it), 3.182 with only the moduli before it.
+  // Everything the cell reads from memory is read before the first layer
+  // store, which could alias a later read and make it wait: the old
+  // stresses, both layer blocks' memory and coefficients, then the moduli.
+  // At 256 x 128 x 8192 the launch takes 3.16 ms in this order as in the
+  // earlier one (layer blocks one after the other, moduli after them); at
+  // 48 x 32 x 192, where the cells of both layers set the launch's length,
+  // the step drops from 16.5 to 15.8 us with the velocity update read the
+  // same way.  (With the blocks apart, reading the moduli before them cost
+  // 3.182 ms against 3.160.)
   const int k1 = kk + 1 < a.nz ? kk + 1 : a.nz - 1;
   const size_t p = col.c + kk;
   const size_t pm = col.m + kk;
@@ -382,39 +401,48 @@ __device__ __forceinline__ void stress_cell(const StepArgs &a, int i, int j, int
   const float so_zz = S::ldn(a.in[SZZ], p, c[SZZ]), so_rt = S::ldn(a.in[SRT], p, c[SRT]);
   const float so_rz = S::ldn(a.in[SRZ], p, c[SRZ]), so_tz = S::ldn(a.in[STZ], p, c[STZ]);
   const int ir = i - (a.nr - a.npr);
-  if (ir >= 0 && live) {
-    const size_t q = ((size_t)ir * a.nt + j) * a.nz + k;
-    const float *T = a.tab_r;
-    float *const *P = a.psi_r;
-    const float arf = T[AR_F * a.nr + i], brf = T[BR_F * a.nr + i], atf = T[AT_F * a.nr + i], btf = T[BT_F * a.nr + i];
-    const float arc = T[AR_C * a.nr + i], brc = T[BR_C * a.nr + i], atc = T[AT_C * a.nr + i], btc = T[BT_C * a.nr + i];
-    const float m0 = ldpsi(P[R_N_DR], q), m1 = ldpsi(P[R_N_B], q), m2 = ldpsi(P[R_RT_DR], q);
-    const float m3 = ldpsi(P[R_RT_B], q), m4 = ldpsi(P[R_RZ_DR], q), m5 = ldpsi(P[R_TZ_B], q);
-    err = cpml(P[R_N_DR], q, m0, arc, brc, err);
-    ett = cpml(P[R_N_B], q, m1, atc, btc, ett);
-    rt_dr = cpml(P[R_RT_DR], q, m2, arf, brf, rt_dr);
-    rt_b = cpml(P[R_RT_B], q, m3, atf, btf, rt_b);
-    rz_dr = cpml(P[R_RZ_DR], q, m4, arf, brf, rz_dr);
-    tz_b = cpml(P[R_TZ_B], q, m5, atc, btc, tz_b);
-  }
+  const bool lr = ir >= 0 && live;
   const int kz = live ? zrow(a, k) : -1;
-  if (kz >= 0) {
-    const size_t q = ((size_t)i * a.nt + j) * a.nzs + kz;
-    const float *T = a.tab_z;
-    float *const *P = a.psi_z;
-    const float azc = T[AZ_C * a.nz + k], bzc = T[BZ_C * a.nz + k], azh = T[AZ_H * a.nz + k], bzh = T[BZ_H * a.nz + k];
-    const float m0 = ldpsi(P[Z_N_DZ], q), m1 = ldpsi(P[Z_RZ_DZ], q), m2 = ldpsi(P[Z_TZ_DZ], q);
-    ezz = cpml(P[Z_N_DZ], q, m0, azc, bzc, ezz);
-    rz_dz = cpml(P[Z_RZ_DZ], q, m1, azh, bzh, rz_dz);
-    tz_dz = cpml(P[Z_TZ_DZ], q, m2, azh, bzh, tz_dz);
+  const bool lz = kz >= 0;
+  const size_t qr = lr ? ((size_t)ir * a.nt + j) * a.nz + k : 0;
+  const size_t qz = lz ? ((size_t)i * a.nt + j) * a.nzs + kz : 0;
+  float *const *P = a.psi_r;
+  float *const *Z = a.psi_z;
+  float arf = 0, brf = 0, atf = 0, btf = 0, arc = 0, brc = 0, atc = 0, btc = 0;
+  float g0 = 0, g1 = 0, g2 = 0, g3 = 0, g4 = 0, g5 = 0;
+  float azc = 0, bzc = 0, azh = 0, bzh = 0, n0 = 0, n1 = 0, n2 = 0;
+  if (lr) {
+    const float *T = a.tab_r;
+    arf = T[AR_F * a.nr + i]; brf = T[BR_F * a.nr + i]; atf = T[AT_F * a.nr + i]; btf = T[BT_F * a.nr + i];
+    arc = T[AR_C * a.nr + i]; brc = T[BR_C * a.nr + i]; atc = T[AT_C * a.nr + i]; btc = T[BT_C * a.nr + i];
+    g0 = ldpsi(P[R_N_DR], qr); g1 = ldpsi(P[R_N_B], qr); g2 = ldpsi(P[R_RT_DR], qr);
+    g3 = ldpsi(P[R_RT_B], qr); g4 = ldpsi(P[R_RZ_DR], qr); g5 = ldpsi(P[R_TZ_B], qr);
   }
-
+  if (lz) {
+    const float *T = a.tab_z;
+    azc = T[AZ_C * a.nz + k]; bzc = T[BZ_C * a.nz + k]; azh = T[AZ_H * a.nz + k]; bzh = T[BZ_H * a.nz + k];
+    n0 = ldpsi(Z[Z_N_DZ], qz); n1 = ldpsi(Z[Z_RZ_DZ], qz); n2 = ldpsi(Z[Z_TZ_DZ], qz);
+  }
   const float lam = a.lam[pm], mu = a.mu[pm];
   const float mu_i1 = a.mu[col.m_i1 + kk], mu_jp = a.mu[col.m_jp + kk];
   const float mu_k1 = a.mu[col.m + k1];
-  const float mu_rt = hm4(mu, mu_i1, mu_jp, a.mu[col.m_i1jp + kk]);
-  const float mu_rz = hm4(mu, mu_i1, mu_k1, a.mu[col.m_i1 + k1]);
-  const float mu_tz = hm4(mu, mu_jp, mu_k1, a.mu[col.m_jp + k1]);
+  const float mu_i1jp = a.mu[col.m_i1jp + kk], mu_i1k1 = a.mu[col.m_i1 + k1], mu_jpk1 = a.mu[col.m_jp + k1];
+  if (lr) {
+    err = cpml(P[R_N_DR], qr, g0, arc, brc, err);
+    ett = cpml(P[R_N_B], qr, g1, atc, btc, ett);
+    rt_dr = cpml(P[R_RT_DR], qr, g2, arf, brf, rt_dr);
+    rt_b = cpml(P[R_RT_B], qr, g3, atf, btf, rt_b);
+    rz_dr = cpml(P[R_RZ_DR], qr, g4, arf, brf, rz_dr);
+    tz_b = cpml(P[R_TZ_B], qr, g5, atc, btc, tz_b);
+  }
+  if (lz) {
+    ezz = cpml(Z[Z_N_DZ], qz, n0, azc, bzc, ezz);
+    rz_dz = cpml(Z[Z_RZ_DZ], qz, n1, azh, bzh, rz_dz);
+    tz_dz = cpml(Z[Z_TZ_DZ], qz, n2, azh, bzh, tz_dz);
+  }
+  const float mu_rt = hm4(mu, mu_i1, mu_jp, mu_i1jp);
+  const float mu_rz = hm4(mu, mu_i1, mu_k1, mu_i1k1);
+  const float mu_tz = hm4(mu, mu_jp, mu_k1, mu_jpk1);
 
   const float tr = err + ett + ezz;
   const float lt = lam * tr, m2 = 2.0f * mu;
