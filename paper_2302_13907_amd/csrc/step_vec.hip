@@ -122,15 +122,20 @@ __device__ __forceinline__ void velocity_column(const StepArgs &a, int i, int j,
     cpml_b(L.f32(a.psi_r[R_VZ_B], ir), L.m0, L.tj, T[AT_C * a.nr + i], T[BT_C * a.nr + i], z_b);
   }
   if (live && a.npz > 0 && (kb < a.npz || kb + VW - 1 >= a.nz - 1 - a.npz)) {
-    const float *T = a.tab_z;
+    if (S::bytes == 2) {
+      cpml_z3(a, i, j, kb, a.psi_z[Z_VR_DZ], a.psi_z[Z_VT_DZ], a.psi_z[Z_VZ_DZ], a.tab_z, false, false, true, r_dz,
+              t_dz, z_dz);
+    } else {
+      const float *T = a.tab_z;
 #pragma unroll
-    for (int e = 0; e < VW; e++) {
-      const int k = kb + e, kz = zrow(a, k);
-      if (kz < 0) continue;
-      const size_t q = ((size_t)i * a.nt + j) * a.nzs + kz;
-      r_dz[e] = cpml1(a.psi_z[Z_VR_DZ], q, T[AZ_C * a.nz + k], T[BZ_C * a.nz + k], r_dz[e]);
-      t_dz[e] = cpml1(a.psi_z[Z_VT_DZ], q, T[AZ_C * a.nz + k], T[BZ_C * a.nz + k], t_dz[e]);
-      z_dz[e] = cpml1(a.psi_z[Z_VZ_DZ], q, T[AZ_H * a.nz + k], T[BZ_H * a.nz + k], z_dz[e]);
+      for (int e = 0; e < VW; e++) {
+        const int k = kb + e, kz = zrow(a, k);
+        if (kz < 0) continue;
+        const size_t q = ((size_t)i * a.nt + j) * a.nzs + kz;
+        r_dz[e] = cpml1(a.psi_z[Z_VR_DZ], q, T[AZ_C * a.nz + k], T[BZ_C * a.nz + k], r_dz[e]);
+        t_dz[e] = cpml1(a.psi_z[Z_VT_DZ], q, T[AZ_C * a.nz + k], T[BZ_C * a.nz + k], t_dz[e]);
+        z_dz[e] = cpml1(a.psi_z[Z_VZ_DZ], q, T[AZ_H * a.nz + k], T[BZ_H * a.nz + k], z_dz[e]);
+      }
     }
   }
   const rsrc_t R_vr = L.field(a.in[VR], i), R_vt = L.field(a.in[VT], i), R_vz = L.field(a.in[VZ], i);
@@ -250,15 +255,20 @@ __device__ __forceinline__ void stress_column(const StepArgs &a, int i, int j, i
     cpml_b(L.f32(a.psi_r[R_TZ_B], ir), L.m0, L.tj, T[AT_C * a.nr + i], T[BT_C * a.nr + i], tz_b);
   }
   if (live && a.npz > 0 && (kb < a.npz || kb + VW - 1 >= a.nz - 1 - a.npz)) {
-    const float *T = a.tab_z;
+    if (S::bytes == 2) {
+      cpml_z3(a, i, j, kb, a.psi_z[Z_N_DZ], a.psi_z[Z_RZ_DZ], a.psi_z[Z_TZ_DZ], a.tab_z, false, true, true, ezz,
+              rz_dz, tz_dz);
+    } else {
+      const float *T = a.tab_z;
 #pragma unroll
-    for (int e = 0; e < VW; e++) {
-      const int k = kb + e, kz = zrow(a, k);
-      if (kz < 0) continue;
-      const size_t q = ((size_t)i * a.nt + j) * a.nzs + kz;
-      ezz[e] = cpml1(a.psi_z[Z_N_DZ], q, T[AZ_C * a.nz + k], T[BZ_C * a.nz + k], ezz[e]);
-      rz_dz[e] = cpml1(a.psi_z[Z_RZ_DZ], q, T[AZ_H * a.nz + k], T[BZ_H * a.nz + k], rz_dz[e]);
-      tz_dz[e] = cpml1(a.psi_z[Z_TZ_DZ], q, T[AZ_H * a.nz + k], T[BZ_H * a.nz + k], tz_dz[e]);
+      for (int e = 0; e < VW; e++) {
+        const int k = kb + e, kz = zrow(a, k);
+        if (kz < 0) continue;
+        const size_t q = ((size_t)i * a.nt + j) * a.nzs + kz;
+        ezz[e] = cpml1(a.psi_z[Z_N_DZ], q, T[AZ_C * a.nz + k], T[BZ_C * a.nz + k], ezz[e]);
+        rz_dz[e] = cpml1(a.psi_z[Z_RZ_DZ], q, T[AZ_H * a.nz + k], T[BZ_H * a.nz + k], rz_dz[e]);
+        tz_dz[e] = cpml1(a.psi_z[Z_TZ_DZ], q, T[AZ_H * a.nz + k], T[BZ_H * a.nz + k], tz_dz[e]);
+      }
     }
   }
   // moduli: reciprocals of mu at the cell and its neighbours (r, theta, depth)

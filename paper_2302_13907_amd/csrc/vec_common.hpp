@@ -60,6 +60,41 @@ __device__ __forceinline__ float cpml1(float *psi, size_t q, float ca, float cb,
   return X + v;
 }
 
+// Depth-layer memory of the lane's VW cells for three slab arrays p0..p2
+// (hN: array N takes the half-node coefficients): psi <- b psi + a X,
+// X += psi for the cells inside the layer.  The arrays and the table are
+// declared not to overlap, so a cell's three slab reads and its coefficients
+// go out together instead of each waiting for the previous array's store:
+// four memory round trips per lane in the layer instead of twelve.  The
+// 16-bit forms use it (256 x 128 x 8192: float16 step 4.06 -> 3.90 ms,
+// bfloat16 3.88 -> 3.84; float16 on 192 x 96 x 4096 61.8 -> 64.3
+// Gcell/s).  In float32 the four-cell stress update then spilled registers
+// and was 8 % slower, so float32 keeps the arrays one after the other; the
+// same treatment of the radial block cost bfloat16 8 % (spills) for 0.3 %
+// in float16.
+__device__ __forceinline__ void cpml_z3(const StepArgs &a, int i, int j, int kb, float *__restrict__ p0,
+                                        float *__restrict__ p1, float *__restrict__ p2, const float *__restrict__ T,
+                                        bool h0, bool h1, bool h2, float (&X0)[VW], float (&X1)[VW],
+                                        float (&X2)[VW])
+{
+#pragma unroll
+  for (int e = 0; e < VW; e++) {
+    const int k = kb + e, kz = zrow(a, k);
+    if (kz < 0) continue;
+    const size_t q = ((size_t)i * a.nt + j) * a.nzs + kz;
+    const float ac = T[AZ_C * a.nz + k], bc = T[BZ_C * a.nz + k], ah = T[AZ_H * a.nz + k], bh = T[BZ_H * a.nz + k];
+    const float v0 = (h0 ? bh : bc) * p0[q] + (h0 ? ah : ac) * X0[e];
+    p0[q] = v0;
+    X0[e] = X0[e] + v0;
+    const float v1 = (h1 ? bh : bc) * p1[q] + (h1 ? ah : ac) * X1[e];
+    p1[q] = v1;
+    X1[e] = X1[e] + v1;
+    const float v2 = (h2 ? bh : bc) * p2[q] + (h2 ? ah : ac) * X2[e];
+    p2[q] = v2;
+    X2[e] = X2[e] + v2;
+  }
+}
+
 // largest |x| of the wavefront into one of 64 slots of a field (spreads
 // the atomics of a launch over 64 addresses)
 __device__ __forceinline__ void track_max(unsigned *slots, float m)
