@@ -57,9 +57,10 @@ def algorithmic_bytes(kernel: str, w, n_r: int, n_z: int, fb: int = 4, axisym: b
     raise ValueError(kernel)
 
 
-# the sources the profiled step kernels (two-pass, fused, sources, receivers) are built from
+# the sources the profiled step kernels (two-pass, fused, sources, receivers) are built from, and the
+# host code that lays out their arrays (the padded field rings)
 PROFILED_SOURCES = ("cwell_internal.hpp", "storage.hpp", "vec_common.hpp", "step_basic.hip", "step_vec.hip",
-                    "step_fused.hip")
+                    "step_fused.hip", "cwell_api.hip")
 
 
 def kernel_source_hash() -> str:

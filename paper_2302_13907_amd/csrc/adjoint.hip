@@ -24,7 +24,7 @@ namespace {
 
 __device__ __forceinline__ size_t at(const AdjArgs &a, int i, int j, int k)
 {
-  return ((size_t)i * a.nt + j) * a.nz + k;
+  return (size_t)i * a.rs + (size_t)j * a.nz + k;
 }
 __device__ __forceinline__ size_t mat(const AdjArgs &a, int i, int j, int k)
 {
@@ -322,7 +322,7 @@ __device__ __forceinline__ bool col(const AdjArgs &a, Col &c)
   c.kb = c.live ? k0 : a.nz - AW;                  // dead lanes compute on a valid group, store nothing
   c.jm = c.j == 0 ? a.nt - 1 : c.j - 1;
   c.jp = c.j == a.nt - 1 ? 0 : c.j + 1;
-  c.ring = (size_t)a.nt * a.nz;
+  c.ring = a.rs;
   c.p = at(a, c.i, c.j, c.kb);
   c.pjm = at(a, c.i, c.jm, c.kb);
   c.pjp = at(a, c.i, c.jp, c.kb);

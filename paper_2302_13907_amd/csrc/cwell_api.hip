@@ -57,6 +57,9 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 }  // namespace
 
+// padding after each ring of a field array (see cw_sim::rs)
+constexpr size_t kRingPadBytes = 4096;
+
 struct cw_sim {
   // grid
   int nr = 0, nt = 0, nz = 0;
@@ -70,7 +73,22 @@ struct cw_sim {
   bool ghost_in = false, ghost_out = false;
   int med_extra = 0;
   double vp_ref = 0;
-  size_t n_alloc() const { return (size_t)(nr + ghost_in + ghost_out) * nt * nz; }
+  // rs: values from one ring of a field array to the next.  A ring may be
+  // followed by kRingPadBytes of padding, which moves the radial neighbours
+  // a cell reads off a power-of-two distance; where it is applied is what
+  // measured faster (same box, alternated): float32 at 256 x 128 x 8192
+  // (4 MB rings) 5.777 -> 5.499 ms per step (8 KB of padding: 5.814), but
+  // at 128 x 64 x 2048 (512 KB rings) the adjoint gradient 2.062 -> 2.129 s;
+  // bfloat16 3.842 -> 3.765 ms at 256 x 128 x 8192 and 1.149 -> 1.112 at
+  // 192 x 96 x 4096; float16 3.899 -> 3.944 and 1.176 -> 1.188.  So:
+  // float32 rings of 4 MB or more, and bfloat16.
+  size_t rs() const
+  {
+    const size_t ring = (size_t)nt * nz, eb = storage == ST_F32 ? 4 : 2;
+    const bool pad = storage == ST_BF16 || (storage == ST_F32 && ring * eb >= ((size_t)4 << 20));
+    return ring + (pad ? kRingPadBytes / eb : 0);
+  }
+  size_t n_alloc() const { return (size_t)(nr + ghost_in + ghost_out) * rs(); }
   // medium (float32 copies, uploaded at bind) and what the setup derives from it
   std::vector<float> rho, lam, mu;
   bool have_material = false;
@@ -210,14 +228,14 @@ size_t adj_region_cells(const cw_sim *s)
 }
 size_t adj_state_floats(const cw_sim *s)
 {
-  return NF * s->n + (size_t)NPSI_R * s->npr * s->nt * s->nz + (size_t)NPSI_Z * s->nr * s->nt * nzs_of(s);
+  return NF * s->n_alloc() + (size_t)NPSI_R * s->npr * s->nt * s->nz + (size_t)NPSI_Z * s->nr * s->nt * nzs_of(s);
 }
 size_t adj_bytes(const cw_sim *s)
 {
   if (!s->adj) return 0;
   const size_t ncp = (size_t)((s->adj_steps + s->adj_every - 1) / s->adj_every);
   size_t f = adj_state_floats(s)               // adjoint fields and layer memory
-             + 9 * s->n                        // term adjoints
+             + 9 * s->n_alloc()                // term adjoints
              + 6 * s->nm                       // effective coefficients
              + 2 * 64                          // alignment of the two blocks above
              + (ncp - 1) * adj_state_floats(s) // checkpoints (the last segment needs none)
@@ -361,6 +379,7 @@ StepArgs step_args(const cw_sim *s, int in, int out)
   a.maxabs = s->d_maxabs;
   a.step = s->d_step;
   a.sr = s->rounding == CW_ROUND_STOCHASTIC && s->storage == ST_BF16;
+  a.rs = s->rs();
   return a;
 }
 
@@ -631,7 +650,7 @@ cw_status cw_bind(cw_sim *s, void *workspace, uint64_t bytes, void *stream)
   for (int b = 0; b < 2; b++)
     for (int q = 0; q < NF; q++)
       s->fields[b][q] = (float *)(w + L.fields + (((size_t)b * NF + q) * s->n_alloc() +
-                                                  (s->ghost_in ? (size_t)s->nt * s->nz : 0)) * field_bytes(s));
+                                                  (s->ghost_in ? s->rs() : 0)) * field_bytes(s));
   s->d_scl = (float *)(w + L.scales);
   s->d_maxabs = (unsigned *)(s->d_scl + 3 * NF);
   s->d_rho = (float *)(w + L.material);
@@ -656,12 +675,12 @@ cw_status cw_bind(cw_sim *s, void *workspace, uint64_t bytes, void *stream)
   s->d_done = (unsigned *)(s->d_step + 1);
   if (s->adj) {
     float *p = (float *)(w + L.adj);
-    for (int q = 0; q < NF; q++) { s->adj_fb[q] = p; p += s->n; }
+    for (int q = 0; q < NF; q++) { s->adj_fb[q] = p; p += s->n_alloc(); }
     for (int q = 0; q < NPSI_R; q++) { s->adj_pr[q] = slab_r ? p : nullptr; p += slab_r; }
     for (int q = 0; q < NPSI_Z; q++) { s->adj_pz[q] = slab_z ? p : nullptr; p += slab_z; }
     auto align64 = [](float *q) { return (float *)(((uintptr_t)q + 255) & ~(uintptr_t)255); };
     p = align64(p);                               // the term and coefficient arrays take 16-byte accesses
-    for (int q = 0; q < 9; q++) { s->adj_T[q] = p; p += s->n; }
+    for (int q = 0; q < 9; q++) { s->adj_T[q] = p; p += s->n_alloc(); }
     p = align64(p);
     for (int q = 0; q < 6; q++) { s->adj_C[q] = p; p += s->nm; }
     const size_t ncp = (size_t)((s->adj_steps + s->adj_every - 1) / s->adj_every);
@@ -863,7 +882,8 @@ cw_status cw_step(cw_sim *s, int64_t nsteps)
     const StepArgs a = step_args(s, s->cur, 1 - s->cur);
     f.nr = s->nr; f.nt = s->nt; f.nz = s->nz; f.npr = s->npr; f.npz = s->npz; f.nzs = nzs_of(s);
     f.dt = a.dt; f.inv_dr = a.inv_dr; f.inv_dz = a.inv_dz; f.inv_dth = a.inv_dth;
-    f.n = s->n;
+    f.n = s->n_alloc();
+    f.rs = s->rs();
     f.slab_r = (size_t)s->npr * s->nt * s->nz;
     f.slab_z = (size_t)s->nr * s->nt * nzs_of(s);
     f.in = s->fields[s->cur][0];
@@ -1009,6 +1029,15 @@ static uint16_t float_to_bf16(float f)
   return (uint16_t)(u >> 16);
 }
 
+// Copy between a packed host array [nr][nt][nz] of eb-byte values and a
+// field array, whose rings lie rs() values apart.
+static hipError_t field_copy(cw_sim *s, void *dst, const void *src, size_t eb, bool to_host)
+{
+  const size_t ring = (size_t)s->nt * s->nz * eb, pitch = s->rs() * eb;
+  return to_host ? hipMemcpy2DAsync(dst, ring, src, pitch, ring, s->nr, hipMemcpyDeviceToHost, s->stream)
+                 : hipMemcpy2DAsync(dst, pitch, src, ring, ring, s->nr, hipMemcpyHostToDevice, s->stream);
+}
+
 cw_status cw_get_field(cw_sim *s, int32_t field, float *host_out)
 {
   if (!s || !host_out) return fail(CW_ERR_ARG, "null argument");
@@ -1016,14 +1045,14 @@ cw_status cw_get_field(cw_sim *s, int32_t field, float *host_out)
   if (!s->bound) return fail(CW_ERR_STATE, "cw_bind first");
   HIPCHK(hipSetDevice(s->device));
   if (s->storage == ST_F32) {
-    HIPCHK(hipMemcpyAsync(host_out, s->fields[s->cur][field], s->n * sizeof(float), hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(field_copy(s, host_out, s->fields[s->cur][field], sizeof(float), true));
     HIPCHK(hipStreamSynchronize(s->stream));
     return CW_OK;
   }
   std::vector<uint16_t> raw;
   try { raw.resize(s->n); } catch (...) { return fail(CW_ERR_NOMEM, "out of host memory"); }
   float scl = 1.0f;
-  HIPCHK(hipMemcpyAsync(raw.data(), s->fields[s->cur][field], s->n * 2, hipMemcpyDeviceToHost, s->stream));
+  HIPCHK(field_copy(s, raw.data(), s->fields[s->cur][field], 2, true));
   HIPCHK(hipMemcpyAsync(&scl, s->d_scl + s->cur * NF + field, sizeof(float), hipMemcpyDeviceToHost, s->stream));
   HIPCHK(hipStreamSynchronize(s->stream));
   if (s->storage == ST_F16) {
@@ -1044,7 +1073,7 @@ cw_status cw_set_field(cw_sim *s, int32_t field, const float *host_in)
   for (size_t p = 0; p < s->n; p++)
     if (!std::isfinite(host_in[p])) return fail(CW_ERR_NONFINITE, "value %zu is not finite", p);
   if (s->storage == ST_F32) {
-    HIPCHK(hipMemcpyAsync(s->fields[s->cur][field], host_in, s->n * sizeof(float), hipMemcpyHostToDevice, s->stream));
+    HIPCHK(field_copy(s, s->fields[s->cur][field], host_in, sizeof(float), false));
     HIPCHK(hipStreamSynchronize(s->stream));
     return CW_OK;
   }
@@ -1060,7 +1089,7 @@ cw_status cw_set_field(cw_sim *s, int32_t field, const float *host_in)
   } else {
     for (size_t p = 0; p < s->n; p++) raw[p] = float_to_bf16(host_in[p]);
   }
-  HIPCHK(hipMemcpyAsync(s->fields[s->cur][field], raw.data(), s->n * 2, hipMemcpyHostToDevice, s->stream));
+  HIPCHK(field_copy(s, s->fields[s->cur][field], raw.data(), 2, false));
   // the buffer's scale, and the scale of the next write of this field
   HIPCHK(hipMemcpyAsync(s->d_scl + s->cur * NF + field, &scl, sizeof(float), hipMemcpyHostToDevice, s->stream));
   HIPCHK(hipMemcpyAsync(s->d_scl + 2 * NF + field, &scl, sizeof(float), hipMemcpyHostToDevice, s->stream));
@@ -1374,7 +1403,7 @@ cw_status cw_gradient(cw_sim *s, int64_t n0, int64_t n1, double *loss, double *g
   if ((st = check_adjoint_region(s)) != CW_OK) return st;
   HIPCHK(hipSetDevice(s->device));
   const int64_t N = s->adj_steps, C = s->adj_every, ncp = (N + C - 1) / C;
-  const size_t nst = adj_state_floats(s), n = s->n;
+  const size_t nst = adj_state_floats(s), n = s->n_alloc();
   const size_t slab_r = (size_t)s->npr * s->nt * s->nz, slab_z = (size_t)s->nr * s->nt * nzs_of(s);
   const int nrec = (int)s->receivers.size();
   const AdjRegion g = adj_region(s);
@@ -1398,6 +1427,7 @@ cw_status cw_gradient(cw_sim *s, int64_t n0, int64_t n1, double *loss, double *g
   const StepArgs sa = step_args(s, 0, 1);
   AdjArgs a{};
   a.nr = s->nr; a.nt = s->nt; a.nz = s->nz; a.npr = s->npr; a.npz = s->npz; a.nzs = nzs_of(s);
+  a.rs = sa.rs;
   a.dt = sa.dt; a.inv_dr = sa.inv_dr; a.inv_dz = sa.inv_dz; a.inv_dth = sa.inv_dth;
   a.inv_rc = sa.inv_rc; a.inv_rf = sa.inv_rf;
   a.rho = sa.rho; a.lam = sa.lam; a.mu = sa.mu; a.m_ring = sa.m_ring; a.m_row = sa.m_row;
@@ -1997,7 +2027,7 @@ cw_status cw_refined_bind(cw_refined *r, void *workspace, uint64_t bytes, void *
     for (int q = 1; q < nzn; q++) {
       const cw_sim *C = r->zones[q - 1], *F = r->zones[q];
       const int nc = r->nth[q - 1], nf = r->nth[q];
-      const size_t cring = (size_t)nc * r->nz, fring = (size_t)nf * r->nz;
+      const size_t cring = C->rs(), fring = F->rs();   // ring strides of the two zones' field arrays
       const float *Pint = r->d_mat + mo[q], *Phalf = Pint + (size_t)nf * nc;
       const float *Rint = Pint + 2 * (size_t)nf * nc, *Rhalf = Pint + 3 * (size_t)nf * nc;
       auto c_last = [&](int b, int f) { return C->fields[b][f] + (size_t)(C->nr - 1) * cring; };

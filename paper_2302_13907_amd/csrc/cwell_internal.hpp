@@ -83,6 +83,10 @@ struct StepArgs {
   // stochastically (random bits from the cell, the field and *step) instead
   // of to nearest even
   int sr;
+  // values from one ring of a field array to the next (a ring holds nt x nz;
+  // the rest is padding): cell (i, j, k) of a field is at i rs + j nz + k.
+  // The layer-memory slabs and the medium keep their own unpadded layouts.
+  size_t rs;
 };
 
 
@@ -153,7 +157,8 @@ constexpr int kMaxFusedInject = 12;
 struct FusedArgs {
   int nr, nt, nz, npr, npz, nzs;
   float dt, inv_dr, inv_dz, inv_dth;
-  size_t n, slab_r, slab_z;
+  size_t n, slab_r, slab_z;  // n: values from one field array to the next
+  size_t rs;                  // ring stride of the field arrays (StepArgs::rs)
   const float *in;
   float *out;
   const float *med;
@@ -252,6 +257,7 @@ hipError_t launch_step_done_batch(const BatchInst *dev, int count, hipStream_t s
 // scratch arrays of n values for the adjoints of the update terms.
 struct AdjArgs {
   int nr, nt, nz, npr, npz, nzs;
+  size_t rs;                // ring stride of the fields, their adjoints and the term arrays (StepArgs::rs)
   float dt, inv_dr, inv_dz, inv_dth;
   const float *inv_rc, *inv_rf;
   const float *rho, *lam, *mu;

@@ -31,7 +31,7 @@ namespace {
 
 __device__ __forceinline__ size_t at(const StepArgs &a, int i, int j, int k)
 {
-  return ((size_t)i * a.nt + j) * a.nz + k;
+  return (size_t)i * a.rs + (size_t)j * a.nz + k;
 }
 
 // index of cell (i, j, k) in the medium arrays
@@ -62,11 +62,11 @@ __device__ __forceinline__ Cols cols(const StepArgs &a, int i, int j)
   const int jm = j == 0 ? a.nt - 1 : j - 1;
   const int jp = j == a.nt - 1 ? 0 : j + 1;
   const int i1 = i + 1 <= a.m_last ? i + 1 : a.m_last;
-  const size_t nz = (size_t)a.nz, row = (size_t)i * a.nt, ring = (size_t)a.nt * nz;
+  const size_t nz = (size_t)a.nz, base = (size_t)i * a.rs, ring = a.rs;
   Cols q;
-  q.c = (row + j) * nz;
-  q.jp = (row + jp) * nz;
-  q.jm = (row + jm) * nz;
+  q.c = base + (size_t)j * nz;
+  q.jp = base + (size_t)jp * nz;
+  q.jm = base + (size_t)jm * nz;
   q.ip_in = i + 1 < a.nr;
   q.im_in = i > 0;
   q.ip = q.ip_in ? q.c + ring : q.c;

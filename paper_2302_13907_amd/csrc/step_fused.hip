@@ -113,13 +113,13 @@ __global__ void __launch_bounds__(TJ * 64) k_step_fused(FusedArgs F)
   const int kc = k < 0 ? 0 : (k >= nz ? nz - 1 : k);   // clamped (medium, safe addresses)
   const int wm = w > 0 ? w - 1 : 0, wp = w < TJ - 1 ? w + 1 : TJ - 1;
 
-  const size_t plane = (size_t)nt * nz;
+  const size_t plane = (size_t)nt * nz, fplane = F.rs;   // ring strides: layer memory, fields
   const uint32_t off0 = (uint32_t)(j * nz + kc) * 4u;  // byte offset of this lane's cell in a ring
   const float *fin = F.in, *med = F.med;
   float *fout = F.out;
   const size_t n = F.n;
   auto fld = [&](int q, int i, uint32_t o) -> float {   // input field q at ring i (0 outside)
-    const float v = ldo(fin + q * n + (size_t)(i < nr ? i : nr - 1) * plane, o);
+    const float v = ldo(fin + q * n + (size_t)(i < nr ? i : nr - 1) * fplane, o);
     return (kin && i < nr) ? v : 0.0f;
   };
   // byte offset of this lane's cell in a ring of the medium (no theta term when the
@@ -247,7 +247,7 @@ __global__ void __launch_bounds__(TJ * 64) k_step_fused(FusedArgs F)
       }
       if (!kin) vn = Three{0, 0, 0};
       if (own) {
-        float *o = fout + (size_t)m * plane;
+        float *o = fout + (size_t)m * fplane;
         sto(o + VR * n, off, vn.r); sto(o + VT * n, off, vn.t); sto(o + VZ * n, off, vn.z);
       }
     }
@@ -353,7 +353,7 @@ __global__ void __launch_bounds__(TJ * 64) k_step_fused(FusedArgs F)
         }
       }
       if (own) {
-        float *o = fout + (size_t)q * plane;
+        float *o = fout + (size_t)q * fplane;
         sto(o + SRR * n, off, sn.rr); sto(o + STT * n, off, sn.tt); sto(o + SZZ * n, off, sn.zz);
         sto(o + SRT * n, off, sn.rt); sto(o + SRZ * n, off, sn.rz); sto(o + STZ * n, off, sn.tz);
       }

@@ -12,7 +12,7 @@ constexpr int VW = 4;
 
 __device__ __forceinline__ size_t at(const StepArgs &a, int i, int j, int k)
 {
-  return ((size_t)i * a.nt + j) * a.nz + k;
+  return (size_t)i * a.rs + (size_t)j * a.nz + k;
 }
 
 // index of cell (i, j, k) in the medium arrays
@@ -116,16 +116,17 @@ struct Lanes {
   unsigned sj, sjm, sjp;    // field bytes of rows j, j - 1, j + 1 within a ring
   unsigned tj, tjm, tjp;    // float32 bytes of the same rows (layer memory)
   unsigned mj, mjp;         // medium bytes of rows j, j + 1 (0 when the medium does not vary along theta)
-  size_t ring;              // values per ring
-  unsigned ringb, ringm;    // bytes per ring: fields, float32 arrays
+  size_t ring, pring;       // ring strides (values): fields (padded), layer memory (nt x nz)
+  unsigned ringb, ringm;    // bytes of one ring's cells: fields, float32 arrays
   size_t mring;             // medium values per ring
   unsigned mringb;
 
   __device__ Lanes(const StepArgs &a, int kb, int j, int jm, int jp)
   {
-    ring = (size_t)a.nt * a.nz;
-    ringb = (unsigned)(ring * S::bytes);
-    ringm = (unsigned)(ring * 4);
+    ring = a.rs;
+    pring = (size_t)a.nt * a.nz;
+    ringb = (unsigned)(pring * S::bytes);
+    ringm = (unsigned)(pring * 4);
     has_b = kb > 0;
     has_a = kb + VW < a.nz;
     v0 = (unsigned)kb * S::bytes;
@@ -143,7 +144,7 @@ struct Lanes {
   // (i may be -1: a ghost ring before ring 0)
   __device__ rsrc_t field(const float *f, int i) const { return make_rsrc(S::adv(f, (ptrdiff_t)i * (ptrdiff_t)ring), ringb); }
   __device__ rsrc_t fieldw(float *f, int i) const { return make_rsrc(S::adv(f, (ptrdiff_t)i * (ptrdiff_t)ring), ringb); }
-  __device__ rsrc_t f32(const float *f, int i) const { return make_rsrc(f + (size_t)i * ring, ringm); }
+  __device__ rsrc_t f32(const float *f, int i) const { return make_rsrc(f + (size_t)i * pring, ringm); }
   __device__ rsrc_t med(const float *f, int i) const { return make_rsrc(f + (size_t)i * mring, mringb); }
 };
 
