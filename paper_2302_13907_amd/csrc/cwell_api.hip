@@ -58,7 +58,7 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 }  // namespace
 
 // padding after each ring of a field array (see cw_sim::rs)
-constexpr size_t kRingPadBytes = 4096;
+constexpr size_t kRingPadBytes = 4096, kRingPadSmallBytes = 1024;
 
 struct cw_sim {
   // grid
@@ -74,19 +74,24 @@ struct cw_sim {
   int med_extra = 0;
   double vp_ref = 0;
   // rs: values from one ring of a field array to the next.  A ring may be
-  // followed by kRingPadBytes of padding, which moves the radial neighbours
-  // a cell reads off a power-of-two distance; where it is applied is what
-  // measured faster (same box, alternated): float32 at 256 x 128 x 8192
-  // (4 MB rings) 5.777 -> 5.499 ms per step (8 KB of padding: 5.814), but
-  // at 128 x 64 x 2048 (512 KB rings) the adjoint gradient 2.062 -> 2.129 s;
-  // bfloat16 3.842 -> 3.765 ms at 256 x 128 x 8192 and 1.149 -> 1.112 at
-  // 192 x 96 x 4096; float16 3.899 -> 3.944 and 1.176 -> 1.188.  So:
-  // float32 rings of 4 MB or more, and bfloat16.
+  // followed by padding, which moves the radial neighbours a cell reads off
+  // a power-of-two distance; how much is what measured fastest (same box,
+  // alternated, ms per step unless stated; padding 0 / 1 / 2 / 4 / 6 KB):
+  //   float32, 256 x 128 x 8192 (4 MB rings): 5.783 / 5.676 / 5.576 / 5.509 / 5.627
+  //   float32, adjoint gradient at 128 x 64 x 2048 (512 KB rings), s:
+  //     2.072 / 2.028 / 2.028 / 2.134 / 2.037
+  //   bfloat16, 256 x 128 x 8192: 3.868 / 3.804 / 3.778 / 3.772 / 3.771
+  //   float16, 256 x 128 x 8192: 3.940 / 4.071 / 3.969 / 3.974 / 3.960
+  // With 1 KB on float32 rings from 128 KB to 4 MB the 48-instance batch
+  // of 128 x 64 x Nz was 0.5 % slower and the 48 x 32 x 192 step unchanged.
+  // So: 4 KB for float32 rings of 4 MB or more and for bfloat16, 1 KB for
+  // float32 rings from 128 KB, none for float16 or smaller rings.
   size_t rs() const
   {
-    const size_t ring = (size_t)nt * nz, eb = storage == ST_F32 ? 4 : 2;
-    const bool pad = storage == ST_BF16 || (storage == ST_F32 && ring * eb >= ((size_t)4 << 20));
-    return ring + (pad ? kRingPadBytes / eb : 0);
+    const size_t ring = (size_t)nt * nz, eb = storage == ST_F32 ? 4 : 2, bytes = ring * eb;
+    if (storage == ST_F16) return ring;
+    if (storage == ST_BF16 || bytes >= ((size_t)4 << 20)) return ring + kRingPadBytes / eb;
+    return ring + (bytes >= ((size_t)128 << 10) ? kRingPadSmallBytes / eb : 0);
   }
   size_t n_alloc() const { return (size_t)(nr + ghost_in + ghost_out) * rs(); }
   // medium (float32 copies, uploaded at bind) and what the setup derives from it
